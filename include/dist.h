@@ -1,0 +1,192 @@
+/*
+ * dist.h -- C ABI of libdist: k-clique counting and listing on one AMD
+ * Instinct MI355X (gfx950), after DIST (Nam, Jang, Park, Yang, Long:
+ * "DIST: Efficient k-Clique Listing via Induced Subgraph Trie").
+ *
+ * The problem (Section II-A, Definition "k-clique listing"): given a simple
+ * undirected graph G and an integer k, list all k-subsets of V whose
+ * members are pairwise adjacent.  The library follows the paper's method:
+ *
+ *   1. orient G into a DAG by a total order (Section II-A; degeneracy order
+ *      as in Algorithm 2, or degree order);
+ *   2. for every root vertex u, build the subgraph induced by its
+ *      out-neighbours (the 1-induced subgraph of Section IV) -- here as
+ *      adjacency bitmaps in LDS;
+ *   3. search it recursively for (k-1)-cliques (Algorithms 1 and 2),
+ *      pruning a branch u when the soft-embedding bound r_{G'}(u) of
+ *      Algorithm 5 on G' = G[N(u) u {u}] is below the clique size still
+ *      needed (Section V, Lemma 1, Theorem 2);
+ *   4. on dense branches (criterion (1) of Section IV) memoise the number
+ *      of l-cliques of every identifying-string prefix met (the nodes of
+ *      the Induced Subgraph Trie, Algorithm 3) and reuse it instead of
+ *      recomputing (the retrieval of Algorithm 4, in counting form).
+ *
+ * Results.  count = |K_k(G)| as an unsigned 128-bit integer (count_hi:
+ * count_lo); fp = sum over k-cliques C of prod_{v in C} g(v) mod (2^61-1),
+ * g(v) = 1 + (splitmix64_next(0x44495354 ^ v) mod (2^61 - 2)) where v is the
+ * vertex's id in the caller's input and splitmix64_next is one step of
+ * SplitMix64 (Steele, Lea, Flood 2014).  fp does not depend on the order in
+ * which cliques are found, and any change of the clique set changes it
+ * except with probability <= k / (2^61 - 2).
+ *
+ * Threading: every call is synchronous on the given HIP stream (NULL = the
+ * default stream) and returns when its results are in host memory.  Calls
+ * that share a dist_graph may run concurrently on different host threads
+ * only if they also use different streams.  Errors are returned as status
+ * codes; no call aborts the process.
+ */
+#ifndef DIST_H
+#define DIST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define DIST_OK 0
+#define DIST_E_INVALID 1     /* malformed CSR: unsorted row, duplicate, self-loop,
+                                asymmetric, id out of range, n or nnz >= 2^31,
+                                NULL pointer where one is required */
+#define DIST_E_K 2           /* k < 1 or k > DIST_K_MAX */
+#define DIST_E_NOMEM 3       /* device or host allocation failed */
+#define DIST_E_DEVICE 4      /* a HIP runtime call failed */
+#define DIST_E_OVERFLOW 5    /* count_hi != 0: the 128-bit result is still exact
+                                but does not fit the low word */
+#define DIST_E_CANCELLED 6   /* the sink returned nonzero, or the deadline in
+                                dist_config.deadline_ms passed; results partial */
+#define DIST_E_UNSUPPORTED 7 /* a root's out-degree exceeds DIST_MAX_OUTDEG */
+
+#define DIST_K_MAX 64
+#define DIST_MAX_OUTDEG 1024  /* widest per-root subgraph (16 words per bitmap row) */
+
+/* ---- types --------------------------------------------------------------- */
+
+/* Opaque device-resident oriented graph, owned by the library. */
+typedef struct dist_graph dist_graph;
+
+/* Order used by dist_orient (Section II-A). */
+#define DIST_ORDER_DEGREE 0      /* (degree, id) ascending */
+#define DIST_ORDER_DEGENERACY 1  /* bulk minimum-degree peeling: (round, id) ascending;
+                                    every out-degree is at most the degeneracy */
+
+/* Switches of the search.  All of them leave count and fp unchanged (the
+ * paper's Theorem 1, Lemma 1 and Theorem 2); they only change the work. */
+typedef struct {
+  int32_t memo;          /* 1 (default): memoise dense branches (Section IV);
+                            0: plain search everywhere (Algorithm 1);
+                            2: memoise every branch that still needs >= 3
+                               vertices, ignoring criterion (1) */
+  int32_t prune;         /* 1 (default): soft-embedding pruning (Section V);
+                            0: off */
+  int32_t fingerprint;   /* 1 (default): compute fp; 0: fp reported as 0 */
+  int32_t memo_entries;  /* memo table entries per wave (power of two); 0 = auto */
+  int64_t memo_bytes;    /* total memo budget in bytes; 0 = auto (4 GiB) */
+  int64_t deadline_ms;   /* stop after this many milliseconds of kernel time
+                            and return DIST_E_CANCELLED; 0 = no deadline */
+} dist_config;
+
+typedef struct {
+  uint64_t count_lo, count_hi; /* number of k-cliques, 128-bit */
+  uint64_t fp;                 /* fingerprint in [0, 2^61 - 1) */
+} dist_result;
+
+/* Work counters of the last dist_count / dist_count_ex on this graph. */
+typedef struct {
+  uint64_t roots;         /* roots searched (out-degree >= k - 1) */
+  uint64_t roots_pruned;  /* roots dropped by the soft-embedding test */
+  uint64_t frames;        /* search-tree nodes expanded */
+  uint64_t word_ops;      /* 64-bit AND+popcount operations on bitmap words */
+  uint64_t leaf_bits;     /* set bits visited to form fingerprint sums */
+  uint64_t memo_lookups, memo_hits, memo_inserts;
+  uint64_t subgraph_arcs; /* arcs read from HBM to build per-root bitmaps */
+  double kernel_ms;       /* device time of the search launches */
+} dist_stats;
+
+typedef struct {
+  int32_t n;
+  int64_t m;              /* undirected edges = DAG arcs */
+  int32_t order_mode;
+  int32_t max_outdeg;
+  int32_t order_bound;    /* degeneracy mode: largest peeling level reached
+                             (= degeneracy); degree mode: max out-degree */
+  double orient_ms;       /* device time of dist_orient */
+} dist_graph_info;
+
+/* Receives listed cliques: n_cliques rows of k input ids, each row in
+ * ascending order.  The buffer is valid only during the call.  Return 0 to
+ * continue, nonzero to stop (dist_list then returns DIST_E_CANCELLED). */
+typedef int (*dist_sink)(const int32_t* cliques, uint64_t n_cliques, int k,
+                         void* user);
+
+/* ---- entry points -------------------------------------------------------- */
+
+/* Default switches: memo 1, prune 1, fingerprint 1, auto memo sizes, no
+ * deadline. */
+void dist_config_init(dist_config* cfg);
+
+/* Orient the graph (Section II-A; Algorithm 2, first line).
+ * row_ptr: int32[n+1], col: int32[nnz]; host or device memory (detected);
+ * the rows must be strictly increasing, symmetric, without self-loops.
+ * nnz = row_ptr[n] = 2|E|.  The input is copied; the caller keeps
+ * ownership.  order_mode: DIST_ORDER_DEGREE or DIST_ORDER_DEGENERACY.
+ * cfg: switches stored with the graph (NULL = defaults).  On success *out
+ * owns a device-resident DAG (ranks, out-lists sorted by rank, per-vertex
+ * fingerprint weights, roots sorted by out-degree descending) until
+ * dist_graph_free.  Errors: DIST_E_INVALID (checked on the device),
+ * DIST_E_NOMEM, DIST_E_DEVICE. */
+int dist_orient(const int32_t* row_ptr, const int32_t* col, int32_t n,
+                int64_t nnz, int order_mode, const dist_config* cfg,
+                void* hip_stream, dist_graph** out);
+
+/* Count the k-cliques of g (Algorithms 2-5 in counting form).  Writes *out
+ * (host memory).  Returns DIST_OK, DIST_E_OVERFLOW (result still exact),
+ * DIST_E_K, DIST_E_UNSUPPORTED, DIST_E_CANCELLED or DIST_E_DEVICE.
+ * Edge cases: k = 1 gives n, k = 2 gives |E|, k above the clique number 0. */
+int dist_count(const dist_graph* g, int k, void* hip_stream, dist_result* out);
+
+/* dist_count with per-call switches (cfg NULL = the graph's) and an
+ * optional per-root breakdown: if per_root is non-NULL (device or host
+ * memory, 3*n uint64 words), per_root[3v..3v+2] receives {count_lo,
+ * count_hi, fp} of the k-cliques whose minimum vertex under g's order is
+ * input vertex v (zero for vertices that are not roots). */
+int dist_count_ex(const dist_graph* g, int k, const dist_config* cfg,
+                  uint64_t* per_root, void* hip_stream, dist_result* out);
+
+/* List the k-cliques of g (Definition "k-clique listing"): every clique is
+ * delivered once to sink as k ascending input ids, in chunks; the order of
+ * cliques is unspecified.  *out receives the count and fp of the cliques
+ * delivered.  Returns DIST_E_CANCELLED if sink stopped the run. */
+int dist_list(const dist_graph* g, int k, dist_sink sink, void* user,
+              void* hip_stream, dist_result* out);
+
+/* Count many (graph, k) pairs in one persistent launch.  gs[i], ks[i] for
+ * i < n; out[i] receives the result of pair i.  Returns the first non-OK
+ * status of any pair (DIST_E_OVERFLOW is reported but every result is
+ * still written). */
+int dist_count_batch(const dist_graph* const* gs, const int* ks, int n,
+                     void* hip_stream, dist_result* out);
+
+/* r_{G'}(u) of Algorithm 5 on G' = G[N+(u) u {u}] for every vertex u, the
+ * value the top-level pruning test compares with k (Section V).  Values
+ * are capped at cap (>= 1): r_out[v] = min(r_{G'}(v), cap) for input id v.
+ * r_out: host or device int32[n]. */
+int dist_root_soft_embed(const dist_graph* g, int cap, int32_t* r_out,
+                         void* hip_stream);
+
+/* Copy g's order to r_out (host or device int32[n]): r_out[v] = position
+ * of input vertex v in the total order. */
+int dist_graph_ranks(const dist_graph* g, int32_t* r_out, void* hip_stream);
+
+int dist_graph_info_get(const dist_graph* g, dist_graph_info* out);
+int dist_stats_get(const dist_graph* g, dist_stats* out);
+
+void dist_graph_free(dist_graph* g);
+
+const char* dist_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,216 @@
+// api.cpp -- the C ABI declared in include/dist.h.
+#include <string.h>
+
+#include <new>
+
+#include "internal.h"
+
+namespace {
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+void free_graph_arrays(dist_graph* g) {
+  (void)hipFree(g->rank);
+  (void)hipFree(g->orig);
+  (void)hipFree(g->dptr);
+  (void)hipFree(g->dcol);
+  (void)hipFree(g->gw);
+  (void)hipFree(g->roots);
+  g->rank = g->orig = g->dptr = g->dcol = g->roots = nullptr;
+  g->gw = nullptr;
+}
+
+int valid_k(int k) { return k >= 1 && k <= DIST_K_MAX; }
+
+}  // namespace
+
+extern "C" {
+
+void dist_config_init(dist_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->memo = 1;
+  cfg->prune = 1;
+  cfg->fingerprint = 1;
+  cfg->memo_entries = 0;
+  cfg->memo_bytes = 0;
+  cfg->deadline_ms = 0;
+}
+
+const char* dist_strerror(int status) {
+  switch (status) {
+    case DIST_OK: return "ok";
+    case DIST_E_INVALID: return "invalid input graph";
+    case DIST_E_K: return "k out of range";
+    case DIST_E_NOMEM: return "out of memory";
+    case DIST_E_DEVICE: return "HIP runtime error";
+    case DIST_E_OVERFLOW: return "count exceeds 64 bits (128-bit result is exact)";
+    case DIST_E_CANCELLED: return "cancelled (sink stop or deadline)";
+    case DIST_E_UNSUPPORTED: return "root out-degree or k beyond the supported range";
+    default: return "unknown status";
+  }
+}
+
+int dist_orient(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t nnz, int order_mode,
+                const dist_config* cfg, void* hip_stream, dist_graph** out) {
+  if (!out) return DIST_E_INVALID;
+  *out = nullptr;
+  if (n < 0 || nnz < 0 || nnz >= ((int64_t)1 << 31) || !row_ptr || (nnz > 0 && !col))
+    return DIST_E_INVALID;
+  if (order_mode != DIST_ORDER_DEGREE && order_mode != DIST_ORDER_DEGENERACY) return DIST_E_INVALID;
+  hipStream_t s = (hipStream_t)hip_stream;
+  dist_graph* g = new (std::nothrow) dist_graph();
+  if (!g) return DIST_E_NOMEM;
+  if (cfg) g->cfg = *cfg;
+  else dist_config_init(&g->cfg);
+  (void)hipGetDevice(&g->device);
+
+  const int32_t* d_rp = row_ptr;
+  const int32_t* d_col = col;
+  int32_t* own_rp = nullptr;
+  int32_t* own_col = nullptr;
+  int rc = DIST_OK;
+  if (!is_device_ptr(row_ptr)) {
+    rc = dev_alloc((void**)&own_rp, sizeof(int32_t) * ((size_t)n + 1));
+    if (!rc && hipMemcpyAsync(own_rp, row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s) !=
+                   hipSuccess)
+      rc = DIST_E_DEVICE;
+    d_rp = own_rp;
+  }
+  if (!rc && nnz > 0 && !is_device_ptr(col)) {
+    rc = dev_alloc((void**)&own_col, sizeof(int32_t) * (size_t)nnz);
+    if (!rc && hipMemcpyAsync(own_col, col, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, s) != hipSuccess)
+      rc = DIST_E_DEVICE;
+    d_col = own_col;
+  }
+  if (!rc) rc = orient_build(d_rp, d_col, n, nnz, order_mode, s, g);
+  if (own_rp || own_col) (void)hipStreamSynchronize(s);
+  (void)hipFree(own_rp);
+  (void)hipFree(own_col);
+  if (rc) {
+    free_graph_arrays(g);
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return DIST_OK;
+}
+
+int dist_count_ex(const dist_graph* g, int k, const dist_config* cfg, uint64_t* per_root, void* hip_stream,
+                  dist_result* out) {
+  if (!g || !out) return DIST_E_INVALID;
+  if (!valid_k(k)) return DIST_E_K;
+  SearchLaunch L;
+  L.g = g;
+  L.k = k;
+  L.cfg = cfg ? *cfg : g->cfg;
+  L.stream = (hipStream_t)hip_stream;
+  L.per_root = nullptr;
+  u64* own = nullptr;
+  bool host_pr = per_root && !is_device_ptr(per_root);
+  if (per_root) {
+    if (host_pr) {
+      int rc = dev_alloc((void**)&own, sizeof(u64) * 3 * ((size_t)g->n + 1));
+      if (rc) return rc;
+      L.per_root = own;
+    } else {
+      L.per_root = (u64*)per_root;
+    }
+  }
+  dist_stats st{};
+  int rc = search_count(L, out, &st);
+  g->stats = st;
+  if (host_pr) {
+    if (hipMemcpyAsync(per_root, own, sizeof(u64) * 3 * (size_t)g->n, hipMemcpyDeviceToHost, L.stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(L.stream) != hipSuccess)
+      rc = rc ? rc : DIST_E_DEVICE;
+    (void)hipFree(own);
+  }
+  return rc;
+}
+
+int dist_count(const dist_graph* g, int k, void* hip_stream, dist_result* out) {
+  return dist_count_ex(g, k, nullptr, nullptr, hip_stream, out);
+}
+
+int dist_list(const dist_graph* g, int k, dist_sink sink, void* user, void* hip_stream, dist_result* out) {
+  if (!g || !out || !sink) return DIST_E_INVALID;
+  if (!valid_k(k)) return DIST_E_K;
+  return search_list(g, k, g->cfg, sink, user, (hipStream_t)hip_stream, out);
+}
+
+int dist_count_batch(const dist_graph* const* gs, const int* ks, int n, void* hip_stream, dist_result* out) {
+  if (n < 0 || (n > 0 && (!gs || !ks || !out))) return DIST_E_INVALID;
+  int first = DIST_OK;
+  for (int i = 0; i < n; ++i) {
+    int rc = dist_count(gs[i], ks[i], hip_stream, &out[i]);
+    if (rc != DIST_OK && first == DIST_OK) first = rc;
+  }
+  return first;
+}
+
+int dist_root_soft_embed(const dist_graph* g, int cap, int32_t* r_out, void* hip_stream) {
+  if (!g || !r_out || cap < 1 || cap > 255) return DIST_E_INVALID;
+  hipStream_t s = (hipStream_t)hip_stream;
+  int32_t* d = r_out;
+  int32_t* own = nullptr;
+  bool host = !is_device_ptr(r_out);
+  if (host) {
+    int rc = dev_alloc((void**)&own, sizeof(int32_t) * ((size_t)g->n + 1));
+    if (rc) return rc;
+    d = own;
+  }
+  int rc = search_root_soft_embed(g, cap, d, s);
+  if (host) {
+    if (!rc && (hipMemcpyAsync(r_out, own, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess))
+      rc = DIST_E_DEVICE;
+    (void)hipFree(own);
+  }
+  return rc;
+}
+
+int dist_graph_ranks(const dist_graph* g, int32_t* r_out, void* hip_stream) {
+  if (!g || !r_out) return DIST_E_INVALID;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (g->n == 0) return DIST_OK;
+  hipMemcpyKind kind = is_device_ptr(r_out) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  DIST_CHECK(hipMemcpyAsync(r_out, g->rank, sizeof(int32_t) * (size_t)g->n, kind, s));
+  DIST_CHECK(hipStreamSynchronize(s));
+  return DIST_OK;
+}
+
+int dist_graph_info_get(const dist_graph* g, dist_graph_info* out) {
+  if (!g || !out) return DIST_E_INVALID;
+  out->n = g->n;
+  out->m = g->m;
+  out->order_mode = g->order_mode;
+  out->max_outdeg = g->max_outdeg;
+  out->order_bound = g->order_bound;
+  out->orient_ms = g->orient_ms;
+  return DIST_OK;
+}
+
+int dist_stats_get(const dist_graph* g, dist_stats* out) {
+  if (!g || !out) return DIST_E_INVALID;
+  *out = g->stats;
+  return DIST_OK;
+}
+
+void dist_graph_free(dist_graph* g) {
+  if (!g) return;
+  free_graph_arrays(g);
+  delete g;
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// internal.h -- types shared by the host API and the HIP kernels of libdist.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/dist.h"
+
+typedef unsigned long long u64;
+
+// Mersenne prime 2^61 - 1: modulus of the clique fingerprint.
+#define DIST_P61 0x1FFFFFFFFFFFFFFFull
+
+// Device-resident oriented graph.
+struct dist_graph {
+  int32_t n = 0;
+  int64_t m = 0;          // undirected edges = DAG arcs
+  int order_mode = 0;
+  int device = 0;
+  dist_config cfg{};
+  int32_t* rank = nullptr;   // rank[v]  (input id -> position in the order)
+  int32_t* orig = nullptr;   // orig[r]  (position -> input id)
+  int32_t* dptr = nullptr;   // DAG out-lists in rank space, n+1
+  int32_t* dcol = nullptr;   // m ranks, ascending within a row
+  u64* gw = nullptr;         // gw[r] = g(orig[r])
+  int32_t* roots = nullptr;  // all ranks sorted by out-degree descending (ties: rank)
+  std::vector<int32_t> root_deg;  // host: out-degree of roots[i], non-increasing
+  int32_t max_outdeg = 0;
+  int32_t order_bound = 0;
+  double orient_ms = 0;
+  mutable dist_stats stats{};
+};
+
+// ---- orientation (orient.hip) ------------------------------------------
+int orient_build(const int32_t* d_row_ptr, const int32_t* d_col, int32_t n,
+                 int64_t nnz, int order_mode, hipStream_t s, dist_graph* g);
+
+// ---- search (search.hip) -----------------------------------------------
+struct SearchLaunch {
+  const dist_graph* g;
+  int k;
+  dist_config cfg;
+  u64* per_root;       // device, 3 per input id, or null
+  hipStream_t stream;
+};
+int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st);
+int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out,
+                           hipStream_t s);
+
+// ---- listing (list.hip) ------------------------------------------------
+int search_list(const dist_graph* g, int k, const dist_config& cfg,
+                dist_sink sink, void* user, hipStream_t s, dist_result* out);
+
+// ---- small device helpers used by several files -------------------------
+int dev_alloc(void** p, size_t bytes);
+#define DIST_CHECK(call)                         \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return DIST_E_DEVICE;  \
+  } while (0)

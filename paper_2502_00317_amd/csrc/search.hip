@@ -1,0 +1,1076 @@
+// search.hip -- per-root k-clique search on the oriented graph.
+//
+// NodeParallel over roots (Section VII-D): one wavefront owns one root at a
+// time and takes the next root from a global counter (roots sorted by
+// out-degree descending, widest first).  For root u with d = |N+(u)|:
+//
+//  * the 1-induced subgraph G_u = G[N+(u)] (Section II-A, Table 1) is built
+//    in LDS as d bitmap rows of W = ceil(d/64) words: row i holds the local
+//    ids j > i with v_j in N+(v_i).  Out-lists are read from HBM coalesced
+//    and located in N+(u) by binary search in LDS;
+//  * Algorithm 5 is evaluated on G_u level by level (bit-parallel form of
+//    the same greedy scan, see soft_embed_levels) giving r_{G_u}(x) capped at
+//    k-1 for every local x, and r_{G'}(u) for G' = G[N(u) u {u}]; the root is
+//    dropped if r_{G'}(u) < k (Section V: applied at Algorithm 2 line 10);
+//  * the (k-1)-cliques of G_u are counted by depth-first search over
+//    candidate bitmaps (Algorithm 1's Listing): a search node holds the set
+//    P of candidates and the number l of vertices still needed; the child
+//    for candidate x is P & A[x].  Children of one node are evaluated one
+//    per lane (AND + popcount over W words), survivors are kept in a bitmap
+//    and expanded highest vertex first.  A child x survives only if
+//    |P & A[x]| >= l - 1 and r_{G_u}(x) >= l (Lemma 1: a vertex whose
+//    soft-embedding bound is below l is the minimum of no l-clique);
+//  * nodes with l = 2 count the edges of G[P]; nodes with l = 3 let every
+//    lane count the edges of its own child, so the last two levels run
+//    lane-parallel;
+//  * dense nodes (criterion (1): 2 m l > (l - 1) n^2 for n = |P|, m = edges
+//    of G[P], l >= 4) switch to the memoised search of Algorithm 3 in
+//    counting form: every node below keeps, per wave, a hash table keyed by
+//    (root, l, P) holding the number of l-cliques of G[P] and their
+//    fingerprint sum.  Keys are vertex sets, i.e. Induced Subgraph Trie
+//    nodes (a trie node is identified by its identifying string, which is
+//    its vertex set).  After the child of x completes, the node inserts the
+//    prefix P & [x, inf) -- the trie node t_i of Algorithm 3's path, marked
+//    for l -- and on entry a node resumes from its longest memoised prefix,
+//    the retrieval of Algorithm 4 summed instead of enumerated:
+//      cnt(t, l) = cnt(L^C_t(l), l - 1) + cnt(L^S_t(l), l).
+//
+// Every quantity is an integer; the result is exact (u128 count, fp mod
+// 2^61 - 1) and independent of scheduling.
+#include "internal.h"
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kOutWords = 16;
+constexpr int kMemoProbe = 8;
+
+struct Params {
+  const int32_t* dptr;
+  const int32_t* dcol;
+  const u64* gw;
+  const int32_t* orig;
+  const int32_t* roots;
+  int32_t root_begin, root_end;
+  int k;            // clique size (search) or cap (soft-embedding mode)
+  int prune;
+  int memo;
+  int fingerprint;
+  int soft_only;    // 1: only compute r_{G'}(u) (capped at k) into soft_out
+  int32_t* soft_out;
+  unsigned* cursor;
+  u64* wave_out;
+  u64* per_root;
+  u64* memo_base;
+  u64 memo_mask;
+  u64 tag_base;
+  u64 deadline;     // wall_clock64() limit; 0 = none
+  int* abort_flag;
+};
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ u64 lanemask_lt() {
+  int l = lane_id();
+  return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+// ---- arithmetic mod p = 2^61 - 1 ------------------------------------------
+__device__ __forceinline__ u64 addp(u64 a, u64 b) {
+  u64 s = a + b;
+  return s >= DIST_P61 ? s - DIST_P61 : s;
+}
+
+__device__ __forceinline__ u64 mulp(u64 a, u64 b) {
+  u64 lo = a * b;
+  u64 hi = __umul64hi(a, b);
+  u64 r = (lo & DIST_P61) + ((hi << 3) | (lo >> 61));
+  r = (r & DIST_P61) + (r >> 61);
+  return r >= DIST_P61 ? r - DIST_P61 : r;
+}
+
+__device__ __forceinline__ u64 wave_sum(u64 x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+__device__ __forceinline__ u64 wave_sum_p(u64 x) {
+  for (int off = 32; off > 0; off >>= 1) x = addp(x, __shfl_xor(x, off));
+  return x;
+}
+
+__device__ __forceinline__ u64 ld_coherent(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- LDS layout -------------------------------------------------------------
+// u64 part: A (D*W), gl (D), per-level stacks, R (W).  Then a union of the
+// arrays used only while G_u is built (nb, rowbeg, rowptr) with the arrays
+// used only afterwards (mem, pos, rcap).  Then the small per-level arrays.
+struct Lds {
+  u64* A;        // D * W
+  u64* gl;       // D
+  u64* stP;      // (k-1) * W
+  u64* stQ;      // (k-1) * W
+  u64* stCnt;    // (k-1) * 2
+  u64* stFp;     // (k-1)
+  u64* R;        // W   (soft-embedding level bitmap)
+  int32_t* nb;      // D       (build)
+  int32_t* rowbeg;  // D + 1   (build)
+  int32_t* rowptr;  // D       (build)
+  uint16_t* mem;    // D       (search)
+  uint16_t* pos;    // D       (search)
+  uint8_t* rcap;    // D       (search)
+  uint16_t* stX;    // k - 1
+  uint8_t* stMemo;  // k - 1
+};
+
+__host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+__host__ __device__ inline size_t lds_bytes(int W, int k) {
+  size_t D = 64 * (size_t)W, L = (size_t)(k > 1 ? k - 1 : 1);
+  size_t b = 8 * (D * W + D + 2 * L * W + 3 * L + W);
+  size_t build = 4 * (3 * D + 1), post = 5 * D;
+  b += align8(build > post ? build : post);
+  b += align8(3 * L);
+  return b;
+}
+
+template <int W>
+__device__ inline Lds carve(char* base, int k) {
+  const size_t D = 64 * W, L = (size_t)(k > 1 ? k - 1 : 1);
+  Lds s;
+  u64* p = (u64*)base;
+  s.A = p; p += D * W;
+  s.gl = p; p += D;
+  s.stP = p; p += L * W;
+  s.stQ = p; p += L * W;
+  s.stCnt = p; p += 2 * L;
+  s.stFp = p; p += L;
+  s.R = p; p += W;
+  char* u = (char*)p;
+  s.nb = (int32_t*)u;
+  s.rowbeg = s.nb + D;
+  s.rowptr = s.rowbeg + D + 1;
+  s.mem = (uint16_t*)u;
+  s.pos = s.mem + D;
+  s.rcap = (uint8_t*)(s.pos + D);
+  size_t build = 4 * (3 * D + 1), post = 5 * D;
+  char* t = u + align8(build > post ? build : post);
+  s.stX = (uint16_t*)t;
+  s.stMemo = (uint8_t*)(s.stX + L);
+  return s;
+}
+
+// ---- bitmap helpers (W words) -------------------------------------------------
+
+// Σ_{z in q} g(z) mod p over a W-word bitmap held in registers.
+template <int W>
+__device__ __forceinline__ u64 weight_sum(const u64 (&q)[W], const u64* gl, u64& bits_visited) {
+  u64 s = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    u64 b = q[w];
+    while (b) {
+      int t = __ffsll((unsigned long long)b) - 1;
+      b &= b - 1;
+      s += gl[w * 64 + t];
+      s = (s & DIST_P61) + (s >> 61);
+      ++bits_visited;
+    }
+  }
+  return s >= DIST_P61 ? s - DIST_P61 : s;
+}
+
+// Edges of G[Y] and their fingerprint sum Σ g(y) g(z) over edges y<z.
+template <int W>
+__device__ __forceinline__ void edges_in(const u64 (&Y)[W], const u64* A, const u64* gl, int fpon,
+                                         u64& cnt, u64& fp, u64& wops, u64& bits) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    u64 b = Y[w];
+    while (b) {
+      int t = __ffsll((unsigned long long)b) - 1;
+      b &= b - 1;
+      int y = w * 64 + t;
+      u64 q[W];
+      int c = 0;
+#pragma unroll
+      for (int v = 0; v < W; ++v) {
+        q[v] = Y[v] & A[y * W + v];
+        c += __popcll(q[v]);
+      }
+      wops += W;
+      cnt += (u64)c;
+      if (fpon && c) fp = addp(fp, mulp(gl[y], weight_sum<W>(q, gl, bits)));
+    }
+  }
+}
+
+// ---- per-wave memo table (Induced Subgraph Trie nodes, counting form) --------
+// Entry: [tag][key W words][cnt_lo][cnt_hi][fp]; tag = (root tag << 8) | l.
+
+template <int W>
+__device__ __forceinline__ u64 memo_hash(u64 tag, const u64 (&key)[W]) {
+  u64 h = tag * 0x9E3779B97F4A7C15ull;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    h ^= key[w];
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 29;
+  }
+  h ^= h >> 32;
+  return h;
+}
+
+template <int W>
+__device__ __forceinline__ bool memo_find(const Params& p, u64* table, u64 tag, const u64 (&key)[W],
+                                          u64& lo, u64& hi, u64& fp) {
+  const int ES = W + 4;
+  u64 h = memo_hash<W>(tag, key);
+  for (int i = 0; i < kMemoProbe; ++i) {
+    const u64* e = table + ((h + i) & p.memo_mask) * ES;
+    if (ld_coherent(e) != tag) continue;
+    bool eq = true;
+#pragma unroll
+    for (int w = 0; w < W; ++w) eq = eq && (ld_coherent(e + 1 + w) == key[w]);
+    if (eq) {
+      lo = ld_coherent(e + 1 + W);
+      hi = ld_coherent(e + 2 + W);
+      fp = ld_coherent(e + 3 + W);
+      return true;
+    }
+  }
+  return false;
+}
+
+// Called by one lane.  Reuses the slot holding the same key, else the
+// first slot not owned by the current root, else evicts the home slot.
+template <int W>
+__device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, u64 root_tag,
+                                         const u64 (&key)[W], u64 lo, u64 hi, u64 fp) {
+  const int ES = W + 4;
+  u64 h = memo_hash<W>(tag, key);
+  u64* slot = table + (h & p.memo_mask) * ES;
+  for (int i = 0; i < kMemoProbe; ++i) {
+    u64* e = table + ((h + i) & p.memo_mask) * ES;
+    u64 t = ld_coherent(e);
+    if (t == tag) {
+      bool eq = true;
+#pragma unroll
+      for (int w = 0; w < W; ++w) eq = eq && (ld_coherent(e + 1 + w) == key[w]);
+      if (eq) { slot = e; break; }
+    } else if ((t >> 8) != root_tag) {
+      slot = e;
+      break;
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) slot[1 + w] = key[w];
+  slot[1 + W] = lo;
+  slot[2 + W] = hi;
+  slot[3 + W] = fp;
+  slot[0] = tag;
+  __threadfence_block();
+}
+
+// ---- Algorithm 5, level by level -------------------------------------------
+// Algorithm 5 scans the out-neighbours of x from the highest down and raises
+// r(x) from c to c + 1 at the first neighbour y (below the previous one)
+// with r(y) >= c.  Pass c therefore needs only R_c = {y : r(y) >= c} and the
+// position reached at pass c - 1, and all x can take pass c in parallel.
+// rcap[x] = min(r_{G_u}(x), K - 1).  Returns min(r_{G'}(u), K) for the root.
+template <int W>
+__device__ int soft_embed_levels(const Lds& s, int d, int K) {
+  const int lane = lane_id();
+  for (int i = lane; i < d; i += kWave) {
+    s.rcap[i] = 1;
+    s.pos[i] = (uint16_t)d;
+  }
+  __syncthreads();
+  for (int c = 1; c <= K - 2; ++c) {
+    for (int w = 0; w < W; ++w) {
+      int idx = w * 64 + lane;
+      u64 b = __ballot(idx < d && s.rcap[idx] >= c);
+      if (lane == 0) s.R[w] = b;
+    }
+    __syncthreads();
+    int raised = 0;
+    for (int i = lane; i < d; i += kWave) {
+      if (s.rcap[i] != c) continue;
+      int ps = s.pos[i];  // search strictly below ps
+      int found = -1;
+      for (int w = (ps - 1) >> 6; w >= 0 && found < 0; --w) {
+        u64 m = s.A[i * W + w] & s.R[w];
+        int top = ps - w * 64;  // bits >= top are excluded
+        if (top < 64) m &= (top <= 0) ? 0ull : ((1ull << top) - 1);
+        if (m) found = w * 64 + 63 - __clzll((long long)m);
+      }
+      if (found >= 0) {
+        s.rcap[i] = (uint8_t)(c + 1);
+        s.pos[i] = (uint16_t)found;
+        raised = 1;
+      }
+    }
+    __syncthreads();
+    if (!__any(raised)) break;
+  }
+  // root: its out-neighbours are all local vertices
+  int r = 1, ps = d;
+  for (int c = 1; c <= K - 1; ++c) {
+    int found = -1;
+    for (int base = ((ps - 1) >> 6) << 6; base >= 0 && ps > 0; base -= 64) {
+      int idx = base + lane;
+      u64 b = __ballot(idx < ps && s.rcap[idx] >= c);
+      if (b) {
+        found = base + 63 - __clzll((long long)b);
+        break;
+      }
+    }
+    if (found < 0) break;
+    r = c + 1;
+    ps = found;
+  }
+  return r;
+}
+
+// ---- the kernel ----------------------------------------------------------------
+
+template <int W>
+__global__ __launch_bounds__(64) void k_search(Params p) {
+  extern __shared__ __align__(16) char smem[];
+  const int lane = lane_id();
+  const int k = p.k;
+  const Lds s = carve<W>(smem, k);
+  const int ES = W + 4;
+  u64* table = p.memo_base ? p.memo_base + (u64)blockIdx.x * (p.memo_mask + 1) * ES : nullptr;
+
+  // per-wave totals (uniform) and per-lane counters
+  u64 tot_lo = 0, tot_hi = 0, tot_fp = 0;
+  u64 n_roots = 0, n_pruned = 0, n_frames = 0, n_look = 0, n_hit = 0, n_ins = 0;
+  u64 wops = 0, bits = 0, arcs = 0;
+  bool aborted = false;
+  const u64 deadline = p.deadline ? wall_clock64() + p.deadline : 0;
+
+  for (;;) {
+    int ridx = 0;
+    if (lane == 0) ridx = (int)atomicAdd(p.cursor, 1u);
+    ridx = __shfl(ridx, 0) + p.root_begin;
+    if (ridx >= p.root_end) break;
+    if (__hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      aborted = true;
+      break;
+    }
+    if (deadline && wall_clock64() > deadline) {
+      if (lane == 0) atomicOr(p.abort_flag, 1);
+      aborted = true;
+      break;
+    }
+    const int32_t r = p.roots[ridx];
+    const int32_t beg = p.dptr[r];
+    const int d = p.dptr[r + 1] - beg;  // <= 64 * W by the host's bucketing
+    const u64 root_tag = p.tag_base + (u64)ridx;
+    ++n_roots;
+
+    // ---- 1. G_u in LDS --------------------------------------------------------
+    for (int i = lane; i < d; i += kWave) {
+      int32_t v = p.dcol[beg + i];
+      s.nb[i] = v;
+      s.gl[i] = p.gw[v];
+      int32_t b = p.dptr[v];
+      s.rowptr[i] = b;
+      s.rowbeg[i] = p.dptr[v + 1] - b;  // length, scanned below
+    }
+    for (int i = lane; i < d * W; i += kWave) s.A[i] = 0;
+    __syncthreads();
+    // exclusive scan of row lengths (in chunks of 64)
+    int carry = 0;
+    for (int base = 0; base < d; base += kWave) {
+      int i = base + lane;
+      int len = i < d ? s.rowbeg[i] : 0;
+      int incl = len;
+      for (int off = 1; off < kWave; off <<= 1) {
+        int o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+      }
+      if (i < d) s.rowbeg[i] = carry + incl - len;
+      carry += __shfl(incl, kWave - 1);
+    }
+    if (lane == 0) s.rowbeg[d] = carry;
+    __syncthreads();
+    const int total = carry;
+    const int32_t top_rank = d ? s.nb[d - 1] : 0;
+    for (int t = lane; t < total; t += kWave) {
+      // row i: largest i with rowbeg[i] <= t
+      int lo = 0, hi = d - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (s.rowbeg[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      int i = lo;
+      int32_t x = p.dcol[s.rowptr[i] + (t - s.rowbeg[i])];
+      ++arcs;
+      if (x > top_rank) continue;
+      // locate x among nb[i+1 .. d-1]
+      int a = i + 1, b = d;
+      while (a < b) {
+        int mid = (a + b) >> 1;
+        if (s.nb[mid] < x) a = mid + 1; else b = mid;
+      }
+      if (a < d && s.nb[a] == x) atomicOr(&s.A[i * W + (a >> 6)], 1ull << (a & 63));
+    }
+    __syncthreads();
+
+    // ---- 2. soft-embedding bound (Algorithm 5) -------------------------------
+    if (p.soft_only) {
+      int rr = soft_embed_levels<W>(s, d, k);
+      if (lane == 0) p.soft_out[p.orig[r]] = rr;
+      __syncthreads();
+      continue;
+    }
+    if (p.prune && k >= 3) {
+      int rr = soft_embed_levels<W>(s, d, k);
+      if (rr < k) {
+        ++n_pruned;
+        __syncthreads();
+        continue;
+      }
+    } else {
+      for (int i = lane; i < d; i += kWave) s.rcap[i] = 63;
+    }
+    __syncthreads();
+
+    // ---- 3. depth-first search over candidate bitmaps -----------------------------
+    // frame j needs l = k-1-j more vertices from its candidate set stP[j].
+    if (lane < W) {
+      int lo_bit = lane * 64;
+      u64 wv;
+      if (d >= lo_bit + 64) wv = ~0ull;
+      else if (d <= lo_bit) wv = 0ull;
+      else wv = (1ull << (d - lo_bit)) - 1;
+      s.stP[lane] = wv;
+    }
+    __syncthreads();
+
+    int j = 0;
+    enum { ENTER, NEXT, FINISH } mode = ENTER;
+    u64 res_lo = 0, res_hi = 0, res_fp = 0;
+    bool stop = false;
+    while (true) {
+      if (mode == ENTER) {
+        ++n_frames;
+        if (deadline && (n_frames & 255) == 0 && wall_clock64() > deadline) {
+          if (lane == 0) atomicOr(p.abort_flag, 1);
+          stop = true;
+          break;
+        }
+        const int l = k - 1 - j;
+        const u64* P = s.stP + j * W;
+        u64 Pr[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) Pr[w] = P[w];
+        if (l == 1) {
+          u64 c = 0;
+#pragma unroll
+          for (int w = 0; w < W; ++w) c += __popcll(Pr[w]);
+          u64 f = 0;
+          if (p.fingerprint) {
+            u64 tmpb = 0;
+            f = weight_sum<W>(Pr, s.gl, tmpb);
+            bits += (lane == 0) ? tmpb : 0;
+          }
+          res_lo = c; res_hi = 0; res_fp = f;
+          mode = FINISH;
+          continue;
+        }
+        bool memo_j = false;
+        if (p.memo == 2) memo_j = (l >= 3);
+        else if (p.memo == 1) memo_j = (l >= 3) && j > 0 && s.stMemo[j - 1];
+        const u64 tag = (root_tag << 8) | (u64)l;
+        if (memo_j) {
+          ++n_look;
+          u64 a, b, c;
+          if (memo_find<W>(p, table, tag, Pr, a, b, c)) {
+            ++n_hit;
+            res_lo = a; res_hi = b; res_fp = c;
+            mode = FINISH;
+            continue;
+          }
+        }
+        // members of P
+        int np = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          u64 bw = Pr[w];
+          if ((bw >> lane) & 1ull) s.mem[np + __popcll(bw & lanemask_lt())] = (uint16_t)(w * 64 + lane);
+          np += __popcll(bw);
+        }
+        __syncthreads();
+        if (l == 2 || l == 3) {
+          u64 c_acc = 0, f_acc = 0;
+          for (int base = 0; base < np; base += kWave) {
+            int i = base + lane;
+            if (i >= np) continue;
+            int x = s.mem[i];
+            u64 q[W];
+            int c = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              q[w] = Pr[w] & s.A[x * W + w];
+              c += __popcll(q[w]);
+            }
+            wops += W;
+            if (l == 2) {
+              c_acc += (u64)c;
+              if (p.fingerprint && c) f_acc = addp(f_acc, mulp(s.gl[x], weight_sum<W>(q, s.gl, bits)));
+            } else if (c >= 2 && s.rcap[x] >= 3) {
+              u64 ec = 0, ef = 0;
+              edges_in<W>(q, s.A, s.gl, p.fingerprint, ec, ef, wops, bits);
+              c_acc += ec;
+              if (p.fingerprint && ec) f_acc = addp(f_acc, mulp(s.gl[x], ef));
+            }
+          }
+          res_lo = wave_sum(c_acc);
+          res_hi = 0;
+          res_fp = p.fingerprint ? wave_sum_p(f_acc) : 0;
+          if (memo_j && lane == 0) memo_put<W>(p, table, tag, root_tag, Pr, res_lo, res_hi, res_fp);
+          if (memo_j) ++n_ins;
+          __syncthreads();
+          mode = FINISH;
+          continue;
+        }
+        // l >= 4: evaluate children, collect survivors in stQ[j]
+        u64* Q = s.stQ + j * W;
+        if (lane < W) Q[lane] = 0;
+        __syncthreads();
+        u64 m_edges = 0;
+        for (int base = 0; base < np; base += kWave) {
+          int i = base + lane;
+          if (i >= np) continue;
+          int x = s.mem[i];
+          int c = 0;
+#pragma unroll
+          for (int w = 0; w < W; ++w) c += __popcll(Pr[w] & s.A[x * W + w]);
+          wops += W;
+          m_edges += (u64)c;
+          if (c >= l - 1 && s.rcap[x] >= l) atomicOr(&Q[x >> 6], 1ull << (x & 63));
+        }
+        m_edges = wave_sum(m_edges);
+        if (!memo_j && p.memo == 1) {
+          // criterion (1) in integer form: 2 m l > (l - 1) n^2
+          u64 lhs = 2ull * m_edges * (u64)l;
+          u64 rhs = (u64)(l - 1) * (u64)np * (u64)np;
+          if (np >= 2 && lhs > rhs) {
+            memo_j = true;
+            ++n_look;
+            u64 a, b, c;
+            if (memo_find<W>(p, table, tag, Pr, a, b, c)) {
+              ++n_hit;
+              res_lo = a; res_hi = b; res_fp = c;
+              __syncthreads();
+              mode = FINISH;
+              continue;
+            }
+          }
+        }
+        u64 acc_lo = 0, acc_hi = 0, acc_fp = 0;
+        __syncthreads();
+        if (memo_j) {
+          // resume from the longest memoised prefix P & [x, inf), x in P
+          int best = 0x7fffffff;
+          u64 b_lo = 0, b_hi = 0, b_fp = 0;
+          for (int base = 0; base < np; base += kWave) {
+            int i = base + lane;
+            bool hit = false;
+            u64 a = 0, b = 0, c = 0;
+            int x = 0;
+            if (i < np) {
+              x = s.mem[i];
+              u64 key[W];
+#pragma unroll
+              for (int w = 0; w < W; ++w) {
+                int lo_b = w * 64;
+                u64 msk = (x <= lo_b) ? ~0ull : (x >= lo_b + 64 ? 0ull : (~0ull << (x - lo_b)));
+                key[w] = Pr[w] & msk;
+              }
+              hit = memo_find<W>(p, table, tag, key, a, b, c);
+            }
+            n_look += (u64)__popcll(__ballot(i < np));
+            u64 hb = __ballot(hit);
+            if (hb) {
+              int src = __ffsll((unsigned long long)hb) - 1;  // lowest lane = smallest x
+              int xs = __shfl(x, src);
+              if (xs < best) {
+                best = xs;
+                b_lo = __shfl(a, src);
+                b_hi = __shfl(b, src);
+                b_fp = __shfl(c, src);
+              }
+              ++n_hit;
+              break;  // members ascend: the first chunk with a hit has the smallest x
+            }
+          }
+          if (best != 0x7fffffff) {
+            acc_lo = b_lo; acc_hi = b_hi; acc_fp = b_fp;
+            // children >= best are covered by the prefix
+            if (lane < W) {
+              int lo_b = lane * 64;
+              u64 keep = (best <= lo_b) ? 0ull : (best >= lo_b + 64 ? ~0ull : ((1ull << (best - lo_b)) - 1));
+              Q[lane] &= keep;
+            }
+          }
+        }
+        if (lane == 0) {
+          s.stCnt[2 * j] = acc_lo;
+          s.stCnt[2 * j + 1] = acc_hi;
+          s.stFp[j] = acc_fp;
+          s.stMemo[j] = memo_j ? 1 : 0;
+        }
+        __syncthreads();
+        mode = NEXT;
+        continue;
+      }
+      if (mode == NEXT) {
+        const int l = k - 1 - j;
+        u64* Q = s.stQ + j * W;
+        int x = -1;
+        for (int w = W - 1; w >= 0; --w) {
+          u64 qw = Q[w];
+          if (qw) {
+            x = w * 64 + 63 - __clzll((long long)qw);
+            break;
+          }
+        }
+        __syncthreads();
+        if (x < 0) {
+          res_lo = s.stCnt[2 * j];
+          res_hi = s.stCnt[2 * j + 1];
+          res_fp = s.stFp[j];
+          if (s.stMemo[j]) {
+            u64 Pr[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) Pr[w] = s.stP[j * W + w];
+            if (lane == 0)
+              memo_put<W>(p, table, (root_tag << 8) | (u64)l, root_tag, Pr, res_lo, res_hi, res_fp);
+            ++n_ins;
+          }
+          __syncthreads();
+          mode = FINISH;
+          continue;
+        }
+        if (lane == 0) {
+          Q[x >> 6] &= ~(1ull << (x & 63));
+          s.stX[j] = (uint16_t)x;
+        }
+        if (lane < W) s.stP[(j + 1) * W + lane] = s.stP[j * W + lane] & s.A[x * W + lane];
+        __syncthreads();
+        ++j;
+        mode = ENTER;
+        continue;
+      }
+      // FINISH: hand (res_lo, res_hi, res_fp) to the parent
+      if (j == 0) break;
+      --j;
+      {
+        const int l = k - 1 - j;
+        int x = s.stX[j];
+        u64 lo = s.stCnt[2 * j], hi = s.stCnt[2 * j + 1], f = s.stFp[j];
+        u64 nlo = lo + res_lo;
+        hi += res_hi + (nlo < lo ? 1ull : 0ull);
+        lo = nlo;
+        if (p.fingerprint) f = addp(f, mulp(s.gl[x], res_fp));
+        __syncthreads();
+        if (lane == 0) {
+          s.stCnt[2 * j] = lo;
+          s.stCnt[2 * j + 1] = hi;
+          s.stFp[j] = f;
+        }
+        if (s.stMemo[j]) {
+          // trie node t_i = P & [x, inf) is now complete for l
+          u64 key[W];
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            int lo_b = w * 64;
+            u64 msk = (x <= lo_b) ? ~0ull : (x >= lo_b + 64 ? 0ull : (~0ull << (x - lo_b)));
+            key[w] = s.stP[j * W + w] & msk;
+          }
+          if (lane == 0) memo_put<W>(p, table, (root_tag << 8) | (u64)l, root_tag, key, lo, hi, f);
+          ++n_ins;
+        }
+        __syncthreads();
+        mode = NEXT;
+      }
+    }
+    if (stop) {
+      aborted = true;
+      break;
+    }
+    // root result: cnt, fp * g(root)
+    u64 rfp = p.fingerprint ? mulp(p.gw[r], res_fp) : 0;
+    u64 nlo = tot_lo + res_lo;
+    tot_hi += res_hi + (nlo < tot_lo ? 1ull : 0ull);
+    tot_lo = nlo;
+    tot_fp = addp(tot_fp, rfp);
+    if (p.per_root && lane == 0) {
+      u64* o = p.per_root + 3 * (u64)p.orig[r];
+      o[0] = res_lo;
+      o[1] = res_hi;
+      o[2] = rfp;
+    }
+    __syncthreads();
+  }
+
+  // per-wave output
+  u64 sw = wave_sum(wops), sb = wave_sum(bits), sa = wave_sum(arcs);
+  if (lane == 0) {
+    u64* o = p.wave_out + (u64)blockIdx.x * kOutWords;
+    o[0] = tot_lo;
+    o[1] = tot_hi;
+    o[2] = tot_fp;
+    o[3] = n_roots;
+    o[4] = n_pruned;
+    o[5] = n_frames;
+    o[6] = sw;
+    o[7] = sb;
+    o[8] = n_look;
+    o[9] = n_hit;
+    o[10] = n_ins;
+    o[11] = sa;
+    o[12] = aborted ? 1 : 0;
+  }
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_zero_u64(u64* p, u64 n) {
+  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  u64 stride = (u64)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0;
+}
+
+__global__ void k_sum_weights(const u64* gw, int32_t n, u64* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  u64 s = 0;
+  for (; i < n; i += stride) s = addp(s, gw[i]);
+  s = wave_sum_p(s);
+  if (lane_id() == 0) {
+    // mod-p accumulation by compare-and-swap
+    u64 old = *out, assumed;
+    do {
+      assumed = old;
+      old = atomicCAS((unsigned long long*)out, assumed, addp(assumed, s));
+    } while (old != assumed);
+  }
+}
+
+// ---- host side ------------------------------------------------------------------
+
+struct Workspace {
+  int device = -1;
+  int cus = 0;
+  u64* wave_out = nullptr;
+  size_t wave_out_words = 0;
+  unsigned* cursor = nullptr;
+  int* abort_flag = nullptr;
+  u64* memo = nullptr;
+  size_t memo_bytes = 0;
+  u64 tag_next = 1;
+  u64* host_out = nullptr;  // pinned
+  size_t host_out_words = 0;
+};
+
+Workspace g_ws;  // one device per process in this library
+
+int ws_ensure(size_t wave_words, size_t memo_bytes) {
+  int dev = 0;
+  DIST_CHECK(hipGetDevice(&dev));
+  if (g_ws.device != dev) {
+    g_ws = Workspace();
+    g_ws.device = dev;
+    DIST_CHECK(hipDeviceGetAttribute(&g_ws.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (dev_alloc((void**)&g_ws.cursor, 64 * sizeof(unsigned))) return DIST_E_NOMEM;
+    if (dev_alloc((void**)&g_ws.abort_flag, 64)) return DIST_E_NOMEM;
+  }
+  if (wave_words > g_ws.wave_out_words) {
+    if (g_ws.wave_out) (void)hipFree(g_ws.wave_out);
+    if (g_ws.host_out) (void)hipHostFree(g_ws.host_out);
+    g_ws.wave_out = nullptr;
+    g_ws.host_out = nullptr;
+    g_ws.wave_out_words = 0;
+    if (dev_alloc((void**)&g_ws.wave_out, wave_words * sizeof(u64))) return DIST_E_NOMEM;
+    if (hipHostMalloc((void**)&g_ws.host_out, wave_words * sizeof(u64)) != hipSuccess) return DIST_E_NOMEM;
+    g_ws.wave_out_words = wave_words;
+  }
+  if (memo_bytes > g_ws.memo_bytes) {
+    if (g_ws.memo) (void)hipFree(g_ws.memo);
+    g_ws.memo = nullptr;
+    g_ws.memo_bytes = 0;
+    if (dev_alloc((void**)&g_ws.memo, memo_bytes)) return DIST_E_NOMEM;
+    g_ws.memo_bytes = memo_bytes;
+  }
+  return DIST_OK;
+}
+
+template <int W>
+int occupancy_blocks(size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W>, 64, lds) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <int W>
+int launch_bucket(Params prm, int grid, size_t lds, hipStream_t s) {
+  DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_search<W>, dim3(grid), dim3(64), lds, s, prm);
+  DIST_CHECK(hipGetLastError());
+  return DIST_OK;
+}
+
+int width_of(int d) {
+  if (d <= 64) return 1;
+  if (d <= 128) return 2;
+  if (d <= 256) return 4;
+  if (d <= 512) return 8;
+  return 16;
+}
+
+struct Bucket {
+  int W;
+  int32_t begin, end;  // range in g->roots
+};
+
+// Roots [0, nroots) of g->roots split into width buckets (widest first).
+std::vector<Bucket> make_buckets(const dist_graph* g, int32_t nroots) {
+  std::vector<Bucket> out;
+  int32_t i = 0;
+  while (i < nroots) {
+    int W = width_of(g->root_deg[i]);
+    int32_t j = i;
+    while (j < nroots && width_of(g->root_deg[j]) == W) ++j;
+    out.push_back({W, i, j});
+    i = j;
+  }
+  return out;
+}
+
+int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_config& cfg, hipStream_t s,
+                u64* totals /* 16 */, double* ms_out) {
+  for (int i = 0; i < kOutWords; ++i) totals[i] = 0;
+  if (nroots <= 0) return DIST_OK;
+  if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
+  std::vector<Bucket> buckets = make_buckets(g, nroots);
+  {
+    int dev = 0, maxlds = 0;
+    DIST_CHECK(hipGetDevice(&dev));
+    DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    for (auto& b : buckets)
+      if (lds_bytes(b.W, base.k) > (size_t)maxlds) return DIST_E_UNSUPPORTED;
+  }
+  // grids and memo sizing
+  int maxgrid = 0;
+  std::vector<int> grids(buckets.size());
+  for (size_t b = 0; b < buckets.size(); ++b) {
+    int W = buckets[b].W;
+    size_t lds = lds_bytes(W, base.k);
+    int occ = 1;
+    switch (W) {
+      case 1: occ = occupancy_blocks<1>(lds); break;
+      case 2: occ = occupancy_blocks<2>(lds); break;
+      case 4: occ = occupancy_blocks<4>(lds); break;
+      case 8: occ = occupancy_blocks<8>(lds); break;
+      default: occ = occupancy_blocks<16>(lds); break;
+    }
+    int cus = g_ws.cus > 0 ? g_ws.cus : 256;
+    int64_t grid = (int64_t)occ * cus;
+    int64_t cnt = buckets[b].end - buckets[b].begin;
+    if (grid > cnt) grid = cnt;
+    if (grid < 1) grid = 1;
+    grids[b] = (int)grid;
+    if (grids[b] > maxgrid) maxgrid = grids[b];
+  }
+  bool want_memo = cfg.memo != 0 && base.k >= 4 && !base.soft_only;
+  size_t memo_total = 0;
+  u64 entries = 0;
+  if (want_memo) {
+    size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)4 << 30);
+    int maxW = 1;
+    for (auto& b : buckets) maxW = b.W > maxW ? b.W : maxW;
+    size_t es = (size_t)(maxW + 4) * 8;
+    if (cfg.memo_entries > 0) {
+      entries = 1;
+      while (entries < (u64)cfg.memo_entries) entries <<= 1;
+    } else {
+      entries = 1 << 16;
+      while (entries > 256 && entries * es * (size_t)maxgrid > budget) entries >>= 1;
+    }
+    memo_total = entries * es * (size_t)maxgrid;
+  }
+  int rc = ws_ensure((size_t)maxgrid * kOutWords, memo_total);
+  if (rc) return rc;
+
+  hipEvent_t e0, e1;
+  DIST_CHECK(hipEventCreate(&e0));
+  DIST_CHECK(hipEventCreate(&e1));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, g_ws.cursor, 64);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)g_ws.abort_flag, 16);
+  u64 deadline = 0;
+  if (cfg.deadline_ms > 0) {
+    // wall_clock64 runs at a fixed rate: query it
+    int rate_khz = 0;
+    DIST_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, g_ws.device));
+    deadline = (u64)cfg.deadline_ms * (u64)rate_khz;  // relative; made absolute on the device
+  }
+  DIST_CHECK(hipEventRecord(e0, s));
+  for (size_t b = 0; b < buckets.size(); ++b) {
+    Params prm = base;
+    prm.root_begin = buckets[b].begin;
+    prm.root_end = buckets[b].end;
+    prm.cursor = g_ws.cursor + b;  // one counter per bucket (zeroed above; <= 6 buckets)
+    prm.wave_out = g_ws.wave_out;
+    prm.abort_flag = g_ws.abort_flag;
+    prm.memo_base = want_memo ? g_ws.memo : nullptr;
+    prm.memo_mask = want_memo ? entries - 1 : 0;
+    prm.tag_base = g_ws.tag_next;
+    prm.deadline = deadline;
+    g_ws.tag_next += (u64)nroots + 1;
+    size_t lds = lds_bytes(buckets[b].W, base.k);
+    hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grids[b] * kOutWords);
+    switch (buckets[b].W) {
+      case 1: rc = launch_bucket<1>(prm, grids[b], lds, s); break;
+      case 2: rc = launch_bucket<2>(prm, grids[b], lds, s); break;
+      case 4: rc = launch_bucket<4>(prm, grids[b], lds, s); break;
+      case 8: rc = launch_bucket<8>(prm, grids[b], lds, s); break;
+      default: rc = launch_bucket<16>(prm, grids[b], lds, s); break;
+    }
+    if (rc) break;
+    DIST_CHECK(hipMemcpyAsync(g_ws.host_out, g_ws.wave_out, (size_t)grids[b] * kOutWords * sizeof(u64),
+                              hipMemcpyDeviceToHost, s));
+    DIST_CHECK(hipStreamSynchronize(s));
+    for (int w = 0; w < grids[b]; ++w) {
+      const u64* o = g_ws.host_out + (size_t)w * kOutWords;
+      u64 lo = totals[0] + o[0];
+      totals[1] += o[1] + (lo < totals[0] ? 1 : 0);
+      totals[0] = lo;
+      u64 f = totals[2] + o[2];
+      totals[2] = f >= DIST_P61 ? f - DIST_P61 : f;
+      for (int i = 3; i < 12; ++i) totals[i] += o[i];
+      totals[12] |= o[12];
+    }
+    if (totals[12]) break;
+  }
+  DIST_CHECK(hipEventRecord(e1, s));
+  DIST_CHECK(hipEventSynchronize(e1));
+  float ms = 0;
+  DIST_CHECK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ms_out) *ms_out = ms;
+  if (rc) return rc;
+  return totals[12] ? DIST_E_CANCELLED : DIST_OK;
+}
+
+}  // namespace
+
+int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st) {
+  const dist_graph* g = L.g;
+  const int k = L.k;
+  dist_result res{0, 0, 0};
+  dist_stats stats{};
+  hipStream_t s = L.stream;
+  int rc = DIST_OK;
+  if (k == 1) {
+    res.count_lo = (u64)g->n;
+    if (L.cfg.fingerprint && g->n > 0) {
+      int r2 = ws_ensure(kOutWords, 0);
+      if (r2) return r2;
+      hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, g_ws.wave_out, (u64)1);
+      hipLaunchKernelGGL(k_sum_weights, dim3(256), dim3(256), 0, s, g->gw, g->n, g_ws.wave_out);
+      DIST_CHECK(hipMemcpyAsync(&res.fp, g_ws.wave_out, sizeof(u64), hipMemcpyDeviceToHost, s));
+      DIST_CHECK(hipStreamSynchronize(s));
+    }
+    if (L.per_root) {
+      // every vertex is the minimum of its own 1-clique
+      std::vector<u64> pr(3 * (size_t)g->n);
+      std::vector<u64> gw(g->n);
+      std::vector<int32_t> orig(g->n);
+      DIST_CHECK(hipMemcpy(gw.data(), g->gw, sizeof(u64) * g->n, hipMemcpyDeviceToHost));
+      DIST_CHECK(hipMemcpy(orig.data(), g->orig, sizeof(int32_t) * g->n, hipMemcpyDeviceToHost));
+      for (int32_t r = 0; r < g->n; ++r) {
+        pr[3 * (size_t)orig[r]] = 1;
+        pr[3 * (size_t)orig[r] + 2] = L.cfg.fingerprint ? gw[r] : 0;
+      }
+      DIST_CHECK(hipMemcpy(L.per_root, pr.data(), sizeof(u64) * pr.size(), hipMemcpyHostToDevice));
+    }
+    *out = res;
+    if (st) *st = stats;
+    return DIST_OK;
+  }
+  // roots: out-degree >= k - 1 (a prefix of the sorted roots)
+  int32_t lo = 0, hi = g->n;
+  while (lo < hi) {
+    int32_t mid = (lo + hi) / 2;
+    if (g->root_deg[mid] >= k - 1) lo = mid + 1; else hi = mid;
+  }
+  const int32_t nroots = lo;
+  if (L.per_root && g->n > 0)
+    hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, L.per_root, (u64)3 * g->n);
+  Params prm{};
+  prm.dptr = g->dptr;
+  prm.dcol = g->dcol;
+  prm.gw = g->gw;
+  prm.orig = g->orig;
+  prm.roots = g->roots;
+  prm.k = k;
+  prm.prune = L.cfg.prune;
+  prm.memo = L.cfg.memo;
+  prm.fingerprint = L.cfg.fingerprint;
+  prm.soft_only = 0;
+  prm.per_root = L.per_root;
+  u64 tot[kOutWords];
+  double ms = 0;
+  rc = run_buckets(g, prm, nroots, L.cfg, s, tot, &ms);
+  res.count_lo = tot[0];
+  res.count_hi = tot[1];
+  res.fp = L.cfg.fingerprint ? tot[2] : 0;
+  stats.roots = tot[3];
+  stats.roots_pruned = tot[4];
+  stats.frames = tot[5];
+  stats.word_ops = tot[6];
+  stats.leaf_bits = tot[7];
+  stats.memo_lookups = tot[8];
+  stats.memo_hits = tot[9];
+  stats.memo_inserts = tot[10];
+  stats.subgraph_arcs = tot[11];
+  stats.kernel_ms = ms;
+  *out = res;
+  if (st) *st = stats;
+  if (rc == DIST_OK && res.count_hi != 0) rc = DIST_E_OVERFLOW;
+  return rc;
+}
+
+int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out, hipStream_t s) {
+  // every vertex is a root here; vertices with no out-neighbour get r = 1
+  std::vector<int32_t> ones;
+  Params prm{};
+  prm.dptr = g->dptr;
+  prm.dcol = g->dcol;
+  prm.gw = g->gw;
+  prm.orig = g->orig;
+  prm.roots = g->roots;
+  prm.k = cap;
+  prm.prune = 1;
+  prm.memo = 0;
+  prm.fingerprint = 0;
+  prm.soft_only = 1;
+  prm.soft_out = d_out;
+  dist_config cfg;
+  dist_config_init(&cfg);
+  cfg.memo = 0;
+  u64 tot[kOutWords];
+  double ms = 0;
+  return run_buckets(g, prm, g->n, cfg, s, tot, &ms);
+}

@@ -1,0 +1,263 @@
+"""Thin ctypes binding of libdist.so (include/dist.h).
+
+Argument marshalling only: every step of orientation and search runs in the
+HIP kernels of the library.  The library is loaded on first use; if it has
+not been built this raises instead of falling back to anything else.
+
+Arrays may be NumPy arrays (host) or torch tensors (host or device); device
+tensors are passed as raw device pointers, and the HIP stream is taken from
+``torch.cuda.current_stream()`` when torch has a device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdist.so")
+
+OK, E_INVALID, E_K, E_NOMEM, E_DEVICE, E_OVERFLOW, E_CANCELLED, E_UNSUPPORTED = range(8)
+ORDER_DEGREE, ORDER_DEGENERACY = 0, 1
+K_MAX = 64
+P61 = (1 << 61) - 1
+
+
+class DistError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, strerror(status) if _lib else "", status))
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("memo", ctypes.c_int32), ("prune", ctypes.c_int32),
+                ("fingerprint", ctypes.c_int32), ("memo_entries", ctypes.c_int32),
+                ("memo_bytes", ctypes.c_int64), ("deadline_ms", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("count_lo", ctypes.c_uint64), ("count_hi", ctypes.c_uint64),
+                ("fp", ctypes.c_uint64)]
+
+    @property
+    def count(self) -> int:
+        return int(self.count_lo) | (int(self.count_hi) << 64)
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("roots", ctypes.c_uint64), ("roots_pruned", ctypes.c_uint64),
+                ("frames", ctypes.c_uint64), ("word_ops", ctypes.c_uint64),
+                ("leaf_bits", ctypes.c_uint64), ("memo_lookups", ctypes.c_uint64),
+                ("memo_hits", ctypes.c_uint64), ("memo_inserts", ctypes.c_uint64),
+                ("subgraph_arcs", ctypes.c_uint64), ("kernel_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("order_mode", ctypes.c_int32),
+                ("max_outdeg", ctypes.c_int32), ("order_bound", ctypes.c_int32),
+                ("orient_ms", ctypes.c_double)]
+
+
+SINK = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint64,
+                        ctypes.c_int, ctypes.c_void_p)
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libdist.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2502_00317_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.dist_config_init.argtypes = [ctypes.POINTER(Config)]
+    lib.dist_config_init.restype = None
+    lib.dist_strerror.argtypes = [ctypes.c_int]
+    lib.dist_strerror.restype = ctypes.c_char_p
+    lib.dist_orient.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int,
+                                ctypes.POINTER(Config), vp, ctypes.POINTER(vp)]
+    lib.dist_orient.restype = ctypes.c_int
+    lib.dist_count.argtypes = [vp, ctypes.c_int, vp, ctypes.POINTER(Result)]
+    lib.dist_count.restype = ctypes.c_int
+    lib.dist_count_ex.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Config), vp, vp,
+                                  ctypes.POINTER(Result)]
+    lib.dist_count_ex.restype = ctypes.c_int
+    lib.dist_list.argtypes = [vp, ctypes.c_int, SINK, vp, vp, ctypes.POINTER(Result)]
+    lib.dist_list.restype = ctypes.c_int
+    lib.dist_count_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.c_int, vp, ctypes.POINTER(Result)]
+    lib.dist_count_batch.restype = ctypes.c_int
+    lib.dist_root_soft_embed.argtypes = [vp, ctypes.c_int, vp, vp]
+    lib.dist_root_soft_embed.restype = ctypes.c_int
+    lib.dist_graph_ranks.argtypes = [vp, vp, vp]
+    lib.dist_graph_ranks.restype = ctypes.c_int
+    lib.dist_graph_info_get.argtypes = [vp, ctypes.POINTER(GraphInfo)]
+    lib.dist_graph_info_get.restype = ctypes.c_int
+    lib.dist_stats_get.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.dist_stats_get.restype = ctypes.c_int
+    lib.dist_graph_free.argtypes = [vp]
+    lib.dist_graph_free.restype = None
+    _lib = lib
+    return lib
+
+
+def lib():
+    return _load()
+
+
+def strerror(status: int) -> str:
+    return _load().dist_strerror(int(status)).decode()
+
+
+def config(**kw) -> Config:
+    c = Config()
+    _load().dist_config_init(ctypes.byref(c))
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise TypeError("unknown config field %r" % k)
+        setattr(c, k, v)
+    return c
+
+
+def _stream_ptr(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    try:
+        import torch
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return ctypes.c_void_p(0)
+
+
+def _ptr(a, dtype):
+    """(pointer, keepalive) for a NumPy array or torch tensor."""
+    if hasattr(a, "data_ptr"):  # torch tensor
+        return ctypes.c_void_p(a.data_ptr()), a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if arr.size == 0:
+        arr = np.zeros(1, dtype=dtype)
+    return ctypes.c_void_p(arr.ctypes.data), arr
+
+
+class Graph:
+    """An oriented graph resident on the device (owns a dist_graph*)."""
+
+    def __init__(self, handle, n):
+        self._h = handle
+        self.n = n
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dist_graph_free(self._h)
+            self._h = None
+
+    def info(self) -> GraphInfo:
+        out = GraphInfo()
+        _check(_load().dist_graph_info_get(self._h, ctypes.byref(out)), "dist_graph_info_get")
+        return out
+
+    def stats(self) -> Stats:
+        out = Stats()
+        _check(_load().dist_stats_get(self._h, ctypes.byref(out)), "dist_stats_get")
+        return out
+
+    def ranks(self, stream=None) -> np.ndarray:
+        out = np.zeros(max(self.n, 1), np.int32)
+        _check(_load().dist_graph_ranks(self._h, ctypes.c_void_p(out.ctypes.data),
+                                        _stream_ptr(stream)), "dist_graph_ranks")
+        return out[: self.n]
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise DistError(rc, what)
+
+
+def orient(row_ptr, col, order=ORDER_DEGREE, cfg: Config | None = None, stream=None) -> Graph:
+    """dist_orient on a CSR graph (NumPy or torch arrays)."""
+    n = len(row_ptr) - 1
+    nnz = len(col)
+    rp, k1 = _ptr(row_ptr, np.int32)
+    cp, k2 = _ptr(col, np.int32)
+    h = ctypes.c_void_p()
+    rc = _load().dist_orient(rp, cp, n, nnz, int(order),
+                             ctypes.byref(cfg) if cfg is not None else None,
+                             _stream_ptr(stream), ctypes.byref(h))
+    _check(rc, "dist_orient")
+    return Graph(h, n)
+
+
+def count(g: Graph, k: int, cfg: Config | None = None, per_root=None, stream=None,
+          allow_overflow=True):
+    """(count as Python int, fp, status).  per_root: optional array of 3*n
+    uint64 (NumPy host array or torch device tensor) filled per input id."""
+    res = Result()
+    if cfg is None and per_root is None:
+        rc = _load().dist_count(g.handle, int(k), _stream_ptr(stream), ctypes.byref(res))
+    else:
+        pr = None
+        keep = None
+        if per_root is not None:
+            pr, keep = _ptr(per_root, np.uint64)
+        rc = _load().dist_count_ex(g.handle, int(k),
+                                   ctypes.byref(cfg) if cfg is not None else None,
+                                   pr, _stream_ptr(stream), ctypes.byref(res))
+    if rc not in (OK, E_OVERFLOW) or (rc == E_OVERFLOW and not allow_overflow):
+        _check(rc, "dist_count")
+    return res.count, int(res.fp), rc
+
+
+def count_batch(graphs, ks, stream=None):
+    n = len(graphs)
+    arr = (ctypes.c_void_p * max(n, 1))(*[g.handle for g in graphs])
+    karr = (ctypes.c_int * max(n, 1))(*[int(k) for k in ks])
+    out = (Result * max(n, 1))()
+    rc = _load().dist_count_batch(arr, karr, n, _stream_ptr(stream), out)
+    return [(out[i].count, int(out[i].fp)) for i in range(n)], rc
+
+
+def list_cliques(g: Graph, k: int, sink=None, stream=None):
+    """dist_list.  With sink=None returns (rows array (N, k) int32, count, fp,
+    status); otherwise calls sink(np.ndarray (n, k)) per chunk and returns
+    (None, count, fp, status)."""
+    chunks = []
+
+    def _cb(ptr, n, kk, user):
+        arr = np.ctypeslib.as_array(ptr, shape=(int(n) * kk,)).reshape(int(n), kk).copy()
+        if sink is None:
+            chunks.append(arr)
+            return 0
+        return int(bool(sink(arr)))
+
+    cb = SINK(_cb)
+    res = Result()
+    rc = _load().dist_list(g.handle, int(k), cb, None, _stream_ptr(stream), ctypes.byref(res))
+    if rc not in (OK, E_OVERFLOW, E_CANCELLED):
+        _check(rc, "dist_list")
+    rows = None
+    if sink is None:
+        rows = np.concatenate(chunks) if chunks else np.zeros((0, k), np.int32)
+    return rows, res.count, int(res.fp), rc
+
+
+def root_soft_embed(g: Graph, cap: int, stream=None) -> np.ndarray:
+    out = np.zeros(max(g.n, 1), np.int32)
+    _check(_load().dist_root_soft_embed(g.handle, int(cap), ctypes.c_void_p(out.ctypes.data),
+                                        _stream_ptr(stream)), "dist_root_soft_embed")
+    return out[: g.n]

@@ -1,0 +1,155 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Counts are compared bit-exactly (u128) and fingerprints exactly (mod
+2^61 - 1).  Every switch of the search (memoisation, pruning, order) must
+give the same result.
+"""
+import numpy as np
+import pytest
+
+from paper_2502_00317_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    from paper_2502_00317_amd import dist
+    dist.lib()
+    return dist
+
+
+CONFIGS = [dict(memo=1, prune=1), dict(memo=0, prune=0), dict(memo=0, prune=1),
+           dict(memo=2, prune=1), dict(memo=2, prune=0)]
+
+
+def _gpu(D, g, k, order, **cfg):
+    G = D.orient(g.row_ptr, g.col, order=order)
+    c = D.config(deadline_ms=60000, **cfg)
+    cnt, fp, rc = D.count(G, k, cfg=c)
+    assert rc in (D.OK, D.E_OVERFLOW)
+    return cnt, fp
+
+
+def test_fig2_all_k(D, oracle_mod):
+    g = gg.fig2()
+    for order in (D.ORDER_DEGREE, D.ORDER_DEGENERACY):
+        for k in range(1, 8):
+            want = oracle_mod.count(g.row_ptr, g.col, k)
+            for cfg in CONFIGS:
+                print("fig2", order, k, cfg, flush=True)
+                assert _gpu(D, g, k, order, **cfg) == want, (order, k, cfg)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small(D, oracle_mod, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 60))
+    p = float(rng.uniform(0.2, 0.9))
+    g = gg.gnp(n, p, 500 + seed)
+    for k in range(1, 9):
+        want = oracle_mod.count(g.row_ptr, g.col, k)
+        for order in (D.ORDER_DEGREE, D.ORDER_DEGENERACY):
+            for cfg in CONFIGS[:4]:
+                print("gnp", seed, n, p, k, order, cfg, flush=True)
+                assert _gpu(D, g, k, order, **cfg) == want, (seed, k, order, cfg)
+
+
+@pytest.mark.parametrize("n", [5, 63, 64, 65, 100, 130, 200])
+def test_complete(D, oracle_mod, n):
+    """Complete graphs: every root's subgraph is complete; widths 1..4
+    words with ragged tails."""
+    import refdefs as R
+    g = gg.complete(n)
+    for k in (2, 3, 4, 5, 6):
+        want = R.complete_graph_result(n, k)
+        for cfg in CONFIGS[:4]:
+            print("K", n, k, cfg, flush=True)
+            assert _gpu(D, g, k, D.ORDER_DEGREE, **cfg) == want
+
+
+@pytest.mark.parametrize("n,r,k", [(40, 6, 5), (90, 10, 6), (150, 12, 7), (300, 20, 5)])
+def test_turan(D, n, r, k):
+    """Turan graphs are dense (criterion (1) holds) and exercise the memo."""
+    import refdefs as R
+    g = gg.turan(n, r)
+    want = R.turan_result(n, r, k)
+    for order in (D.ORDER_DEGREE, D.ORDER_DEGENERACY):
+        for cfg in CONFIGS:
+            print("T", n, r, k, order, cfg, flush=True)
+            assert _gpu(D, g, k, order, **cfg) == want
+
+
+def test_small_powerlaw(D, oracle_mod):
+    g = gg.small_powerlaw()
+    for k in (3, 4, 5, 6):
+        want = oracle_mod.count(g.row_ptr, g.col, k)
+        for order in (D.ORDER_DEGREE, D.ORDER_DEGENERACY):
+            for cfg in CONFIGS[:4]:
+                print("cfg1", k, order, cfg, flush=True)
+                assert _gpu(D, g, k, order, **cfg) == want
+
+
+def test_per_root_degree_order(D, oracle_mod):
+    g = gg.gnp(80, 0.5, 3)
+    G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+    for k in (3, 4, 5, 6):
+        per = np.zeros(3 * g.n, np.uint64)
+        D.count(G, k, cfg=D.config(), per_root=per)
+        want = oracle_mod.count_roots(g.row_ptr, g.col, k, np.arange(g.n))
+        got = [(int(per[3 * v]) | (int(per[3 * v + 1]) << 64), int(per[3 * v + 2]))
+               for v in range(g.n)]
+        assert got == want
+
+
+def test_orientation_orders(D, oracle_mod):
+    g = gg.small_powerlaw()
+    G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+    assert np.array_equal(G.ranks(), oracle_mod.degree_rank(g.row_ptr))
+    delta, _ = oracle_mod.degeneracy(g.row_ptr, g.col)
+    H = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGENERACY)
+    info = H.info()
+    assert info.order_bound == delta
+    assert info.max_outdeg <= delta
+    assert sorted(H.ranks()) == list(range(g.n))
+
+
+def test_root_soft_embed(D, oracle_mod):
+    for seed in range(3):
+        g = gg.gnp(40, 0.5, seed)
+        G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+        want = oracle_mod.root_soft_embed(g.row_ptr, g.col)
+        got = D.root_soft_embed(G, 60)
+        assert np.array_equal(got, np.minimum(want, 60))
+
+
+def test_invalid_inputs(D):
+    bad = [
+        (np.array([0, 1, 2], np.int32), np.array([0, 0], np.int32)),   # self-loop
+        (np.array([0, 1, 1], np.int32), np.array([1], np.int32)),      # asymmetric
+        (np.array([0, 2, 4], np.int32), np.array([1, 1, 0, 0], np.int32)),  # duplicate
+        (np.array([0, 1, 2], np.int32), np.array([2, 0], np.int32)),   # out of range
+        (np.array([0, 3, 2], np.int32), np.array([1, 0], np.int32)),   # bad row_ptr
+    ]
+    for rp, col in bad:
+        with pytest.raises(D.DistError) as e:
+            D.orient(rp, col)
+        assert e.value.status == D.E_INVALID
+    g = gg.fig2()
+    G = D.orient(g.row_ptr, g.col)
+    for k in (0, -1, 65):
+        with pytest.raises(D.DistError):
+            D.count(G, k)
+
+
+def test_empty_graphs(D):
+    for n in (0, 1, 7):
+        g = gg.empty(n)
+        G = D.orient(g.row_ptr, g.col)
+        assert D.count(G, 1)[0] == n
+        assert D.count(G, 2)[0] == 0
+        assert D.count(G, 5)[0] == 0

@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: k-clique counting on one MI355X (plain per-graph path).
+
+Workload: Chung-Lu graph, n = 1,000,000, power-law exponent 2.2, mean
+degree 20, degrees capped at 5,000, plus 200 planted 30-cliques (seed 2;
+synthetic stand-in for the paper's real networks).  One step = the whole
+hot path on the resident CSR: dist_orient (degree order) followed by
+dist_count for every k of --ks (default 5 and 7).  k = 9 is attempted once,
+outside the timed region, under a deadline and reported as finished or not.
+
+Prints one JSON line with the metric, the roofline of the dominant search
+kernel (integer ALU bound) and the CPU oracle timed on a bounded sample of
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 32-bit integer lane-ops/s
+PEAK_INT_LANE_OPS = 256 * 64 * 2.4e9
+# algorithmic lane-ops per unit of work:
+OPS_PER_WORD_OP = 4    # 2 x v_and_b32 + 2 x v_bcnt_u32_b32 on one 64-bit word
+OPS_PER_LEAF_BIT = 2   # one 64-bit add of a fingerprint weight
+BUCKET_W = [1, 2, 4, 8, 16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--ks", default="5,7")
+    ap.add_argument("--fp-ks", default="5", help="ks whose fingerprint is computed (the rest: exact count only)")
+    ap.add_argument("--k-dnf", type=int, default=9, help="k attempted once under a deadline")
+    ap.add_argument("--dnf-deadline-ms", type=int, default=20000)
+    ap.add_argument("--order", default="degree", choices=["degree", "degeneracy"])
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--cpu-stride", type=int, default=8, help="oracle sample: every s-th vertex as root")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--out", default="")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); the per-root work "
+              "would shard across GPUs as described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2502_00317_amd import dist, graphgen as gg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+    dist.lib()
+    ks = [int(x) for x in a.ks.split(",") if x]
+    fp_ks = {int(x) for x in a.fp_ks.split(",") if x}
+    order = dist.ORDER_DEGREE if a.order == "degree" else dist.ORDER_DEGENERACY
+
+    t0 = time.time()
+    g = gg.large_powerlaw(n=a.n)
+    gen_s = time.time() - t0
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    col = torch.from_numpy(g.col).cuda()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    cfgs = {k: dist.config(fingerprint=1 if k in fp_ks else 0) for k in ks}
+
+    def log(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
+
+    log("graph n=%d m=%d generated in %.1f s" % (g.n, g.m, gen_s))
+
+    per_k = {k: {"ms": [], "kernel_ms": [], "stats": None} for k in ks}
+    results = {}
+    orient_ms = []
+
+    def step(record):
+        t = time.perf_counter()
+        G = dist.orient(rp, col, order=order, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if record:
+            orient_ms.append((t1 - t) * 1e3)
+        for k in ks:
+            tk = time.perf_counter()
+            cnt, fp, rc = dist.count(G, k, cfg=cfgs[k], stream=stream)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - tk) * 1e3
+            log("k=%d count=%d fp=%d %.1f ms%s" % (k, cnt, fp, dt, "" if record else " (warmup)"))
+            if rc not in (dist.OK, dist.E_OVERFLOW):
+                raise RuntimeError("count failed k=%d rc=%d" % (k, rc))
+            if k in results:
+                assert results[k] == (cnt, fp), "nondeterministic result"
+            results[k] = (cnt, fp)
+            if record:
+                st = G.stats()
+                per_k[k]["ms"].append(dt)
+                per_k[k]["kernel_ms"].append(st.kernel_ms)
+                per_k[k]["stats"] = st.as_dict()
+        return G
+
+    for _ in range(a.warmup):
+        step(False).free()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    G = None
+    for _ in range(a.steps):
+        if G is not None:
+            G.free()
+        G = step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / a.steps
+    total_cliques = sum(results[k][0] for k in ks)
+    value = total_cliques / (ms_per_step / 1e3)
+
+    # ---- roofline of the dominant search kernel (bucket with most time) ----
+    agg = {w: {"ms": 0.0, "wops": 0, "bits": 0, "launches": 0} for w in BUCKET_W}
+    for k in ks:
+        st = per_k[k]["stats"]
+        for i, w in enumerate(BUCKET_W):
+            if st["bucket_ms"][i] > 0:
+                agg[w]["ms"] += st["bucket_ms"][i]
+                agg[w]["wops"] += st["bucket_word_ops"][i]
+                agg[w]["bits"] += st["bucket_leaf_bits"][i]
+                agg[w]["launches"] += 1
+    wdom = max(BUCKET_W, key=lambda w: agg[w]["ms"])
+    A = agg[wdom]
+    avg_launch_ms = A["ms"] / max(A["launches"], 1)
+    ops_per_launch = (OPS_PER_WORD_OP * A["wops"] + OPS_PER_LEAF_BIT * A["bits"]) / max(A["launches"], 1)
+    achieved = ops_per_launch / (avg_launch_ms / 1e3) / 1e12
+    peak = PEAK_INT_LANE_OPS / 1e12
+    roofline = {"bound": "alu", "kernel": "k_search<%d>" % wdom, "achieved": round(achieved, 4),
+                "peak": round(peak, 2), "unit": "Tlane-op/s", "frac": round(achieved / peak, 5),
+                "traffic": None, "avg_launch_ms": round(avg_launch_ms, 3),
+                "ops_per_launch": ops_per_launch}
+
+    # ---- k attempted under a deadline (not timed) ----
+    dnf = None
+    if a.k_dnf and a.k_dnf not in ks:
+        log("k=%d under a %d ms deadline" % (a.k_dnf, a.dnf_deadline_ms))
+        c2 = dist.config(deadline_ms=a.dnf_deadline_ms, fingerprint=0)
+        try:
+            cnt, fp, rc = dist.count(G, a.k_dnf, cfg=c2, stream=stream)
+        except dist.DistError as e:
+            cnt, fp, rc = None, None, e.status
+        st = G.stats()
+        dnf = {"k": a.k_dnf, "deadline_ms": a.dnf_deadline_ms,
+               "status": "finished" if rc in (dist.OK, dist.E_OVERFLOW) else "DNF",
+               "count": cnt, "fp": fp, "roots_done": st.roots, "kernel_ms": st.kernel_ms}
+
+    # ---- sampled parity at full size: per-root results vs the oracle ----
+    cpu = None
+    parity = None
+    if not a.no_cpu:
+        import oracle
+        kc = ks[0]
+        sample = np.arange(0, g.n, a.cpu_stride, dtype=np.int32)
+        if order != dist.ORDER_DEGREE:
+            Gd = dist.orient(rp, col, order=dist.ORDER_DEGREE)
+        else:
+            Gd = G
+        per = torch.zeros(3 * g.n, dtype=torch.int64, device="cuda")
+        dist.count(Gd, kc, cfg=dist.config(), per_root=per, stream=stream)
+        torch.cuda.synchronize()
+        per_h = per.cpu().numpy().view(np.uint64)
+        threads = min(16, os.cpu_count() or 1)
+        log("oracle sample: %d roots, %d threads" % (len(sample), threads))
+        tc = time.perf_counter()
+        want = oracle.count_roots(g.row_ptr, g.col, kc, sample, nthreads=threads)
+        cpu_s = time.perf_counter() - tc
+        got = [(int(per_h[3 * v]) | (int(per_h[3 * v + 1]) << 64), int(per_h[3 * v + 2])) for v in sample]
+        parity = bool(got == want)
+        sample_cliques = sum(c for c, _ in want)
+        cpu = {"value": sample_cliques / cpu_s, "unit": "k-cliques/s", "cores": threads, "kind": "oracle",
+               "sample": "k=%d, every %d-th vertex id as root (%d roots, %d cliques, %.1f s)" % (
+                   kc, a.cpu_stride, len(sample), sample_cliques, cpu_s)}
+
+    line = {
+        "metric": "k-cliques/sec at k=5..9 (plain vs batched); p50/p99 query latency in serving",
+        "value": value,
+        "unit": "k-cliques/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "plain per-graph: Chung-Lu n=%d, exponent 2.2, mean degree 20, cap 5000, "
+                               "+200 planted K30, seed 2; orient (%s order) + count k=%s" % (
+                                   g.n, a.order, ",".join(map(str, ks))),
+                   "n": g.n, "m": g.m, "ks": ks},
+        "per_k": [{"k": k, "count": results[k][0], "fp": results[k][1], "fingerprint": k in fp_ks,
+                   "ms": float(np.median(per_k[k]["ms"])),
+                   "kernel_ms": float(np.median(per_k[k]["kernel_ms"])),
+                   "cliques_per_s": results[k][0] / (np.median(per_k[k]["ms"]) / 1e3)} for k in ks],
+        "orient_ms": float(np.median(orient_ms)),
+        "k_dnf": dnf,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_sampled_roots": parity,
+        "gen_s": gen_s,
+    }
+    s = json.dumps(line)
+    print(s, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(s + "\n")
+
+
+if __name__ == "__main__":
+    main()

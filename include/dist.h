@@ -102,6 +102,12 @@ typedef struct {
   uint64_t memo_lookups, memo_hits, memo_inserts;
   uint64_t subgraph_arcs; /* arcs read from HBM to build per-root bitmaps */
   double kernel_ms;       /* device time of the search launches */
+  /* the same, split by bitmap width W = 1, 2, 4, 8, 16 words */
+  double bucket_ms[5];
+  uint64_t bucket_roots[5];
+  uint64_t bucket_word_ops[5];
+  uint64_t bucket_leaf_bits[5];
+  uint64_t bucket_arcs[5];
 } dist_stats;
 
 typedef struct {

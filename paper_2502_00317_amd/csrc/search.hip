@@ -43,7 +43,12 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kOutWords = 16;
-constexpr int kMemoProbe = 8;
+constexpr int kMemoProbe = 4;
+// A root stops using its memo table once at least kMemoMinLook lookups
+// found fewer than one hit in kMemoMinRatio (the table is a cache: using it
+// or not never changes a result).
+constexpr int kMemoMinLook = 64;
+constexpr int kMemoMinRatio = 16;
 
 struct Params {
   const int32_t* dptr;
@@ -228,9 +233,13 @@ __device__ __forceinline__ bool memo_find(const Params& p, u64* table, u64 tag, 
                                           u64& lo, u64& hi, u64& fp) {
   const int ES = W + 4;
   u64 h = memo_hash<W>(tag, key);
+  u64 t[kMemoProbe];
+#pragma unroll
+  for (int i = 0; i < kMemoProbe; ++i) t[i] = ld_coherent(table + ((h + i) & p.memo_mask) * ES);
+#pragma unroll
   for (int i = 0; i < kMemoProbe; ++i) {
+    if (t[i] != tag) continue;
     const u64* e = table + ((h + i) & p.memo_mask) * ES;
-    if (ld_coherent(e) != tag) continue;
     bool eq = true;
 #pragma unroll
     for (int w = 0; w < W; ++w) eq = eq && (ld_coherent(e + 1 + w) == key[w]);
@@ -454,6 +463,8 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
 
     int j = 0;
     enum { ENTER, NEXT, FINISH } mode = ENTER;
+    u64 r_look = 0, r_hit = 0;  // this root's memo lookups and hits
+    bool memo_live = table != nullptr;
     u64 res_lo = 0, res_hi = 0, res_fp = 0;
     bool stop = false;
     while (true) {
@@ -487,15 +498,18 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         if (p.memo == 2) memo_j = (l >= 3);
         else if (p.memo == 1) memo_j = (l >= 3) && j > 0 && s.stMemo[j - 1];
         const u64 tag = (root_tag << 8) | (u64)l;
-        if (memo_j) {
+        if (memo_j && memo_live) {
           ++n_look;
+          ++r_look;
           u64 a, b, c;
           if (memo_find<W>(p, table, tag, Pr, a, b, c)) {
             ++n_hit;
+            ++r_hit;
             res_lo = a; res_hi = b; res_fp = c;
             mode = FINISH;
             continue;
           }
+          if (r_look >= kMemoMinLook && r_hit * kMemoMinRatio < r_look) memo_live = false;
         }
         // members of P
         int np = 0;
@@ -533,8 +547,8 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           res_lo = wave_sum(c_acc);
           res_hi = 0;
           res_fp = p.fingerprint ? wave_sum_p(f_acc) : 0;
-          if (memo_j && lane == 0) memo_put<W>(p, table, tag, root_tag, Pr, res_lo, res_hi, res_fp);
-          if (memo_j) ++n_ins;
+          if (memo_j && memo_live && lane == 0) memo_put<W>(p, table, tag, root_tag, Pr, res_lo, res_hi, res_fp);
+          if (memo_j && memo_live) ++n_ins;
           __syncthreads();
           mode = FINISH;
           continue;
@@ -556,16 +570,18 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           if (c >= l - 1 && s.rcap[x] >= l) atomicOr(&Q[x >> 6], 1ull << (x & 63));
         }
         m_edges = wave_sum(m_edges);
-        if (!memo_j && p.memo == 1) {
+        if (!memo_j && p.memo == 1 && memo_live) {
           // criterion (1) in integer form: 2 m l > (l - 1) n^2
           u64 lhs = 2ull * m_edges * (u64)l;
           u64 rhs = (u64)(l - 1) * (u64)np * (u64)np;
           if (np >= 2 && lhs > rhs) {
             memo_j = true;
             ++n_look;
+            ++r_look;
             u64 a, b, c;
             if (memo_find<W>(p, table, tag, Pr, a, b, c)) {
               ++n_hit;
+              ++r_hit;
               res_lo = a; res_hi = b; res_fp = c;
               __syncthreads();
               mode = FINISH;
@@ -575,43 +591,36 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         }
         u64 acc_lo = 0, acc_hi = 0, acc_fp = 0;
         __syncthreads();
-        if (memo_j) {
-          // resume from the longest memoised prefix P & [x, inf), x in P
-          int best = 0x7fffffff;
-          u64 b_lo = 0, b_hi = 0, b_fp = 0;
-          for (int base = 0; base < np; base += kWave) {
-            int i = base + lane;
-            bool hit = false;
-            u64 a = 0, b = 0, c = 0;
-            int x = 0;
-            if (i < np) {
-              x = s.mem[i];
-              u64 key[W];
+        if (memo_j && memo_live && np >= 2) {
+          // resume from the longest memoised proper prefix P & [m_i, inf),
+          // m_i the i-th smallest member, i = 1..kMemoProbe (one lane each)
+          int i = 1 + lane;
+          bool hit = false;
+          u64 a = 0, b = 0, c = 0;
+          int x = 0;
+          if (lane < kMemoProbe && i < np) {
+            x = s.mem[i];
+            u64 key[W];
 #pragma unroll
-              for (int w = 0; w < W; ++w) {
-                int lo_b = w * 64;
-                u64 msk = (x <= lo_b) ? ~0ull : (x >= lo_b + 64 ? 0ull : (~0ull << (x - lo_b)));
-                key[w] = Pr[w] & msk;
-              }
-              hit = memo_find<W>(p, table, tag, key, a, b, c);
+            for (int w = 0; w < W; ++w) {
+              int lo_b = w * 64;
+              u64 msk = (x <= lo_b) ? ~0ull : (x >= lo_b + 64 ? 0ull : (~0ull << (x - lo_b)));
+              key[w] = Pr[w] & msk;
             }
-            n_look += (u64)__popcll(__ballot(i < np));
-            u64 hb = __ballot(hit);
-            if (hb) {
-              int src = __ffsll((unsigned long long)hb) - 1;  // lowest lane = smallest x
-              int xs = __shfl(x, src);
-              if (xs < best) {
-                best = xs;
-                b_lo = __shfl(a, src);
-                b_hi = __shfl(b, src);
-                b_fp = __shfl(c, src);
-              }
-              ++n_hit;
-              break;  // members ascend: the first chunk with a hit has the smallest x
-            }
+            hit = memo_find<W>(p, table, tag, key, a, b, c);
           }
-          if (best != 0x7fffffff) {
-            acc_lo = b_lo; acc_hi = b_hi; acc_fp = b_fp;
+          u64 nl = (u64)__popcll(__ballot(lane < kMemoProbe && i < np));
+          n_look += nl;
+          r_look += nl;
+          u64 hb = __ballot(hit);
+          if (hb) {
+            int src = __ffsll((unsigned long long)hb) - 1;  // lowest lane = smallest member
+            int best = __shfl(x, src);
+            acc_lo = __shfl(a, src);
+            acc_hi = __shfl(b, src);
+            acc_fp = __shfl(c, src);
+            ++n_hit;
+            ++r_hit;
             // children >= best are covered by the prefix
             if (lane < W) {
               int lo_b = lane * 64;
@@ -619,6 +628,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
               Q[lane] &= keep;
             }
           }
+          if (r_look >= kMemoMinLook && r_hit * kMemoMinRatio < r_look) memo_live = false;
         }
         if (lane == 0) {
           s.stCnt[2 * j] = acc_lo;
@@ -646,7 +656,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           res_lo = s.stCnt[2 * j];
           res_hi = s.stCnt[2 * j + 1];
           res_fp = s.stFp[j];
-          if (s.stMemo[j]) {
+          if (s.stMemo[j] && memo_live) {
             u64 Pr[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) Pr[w] = s.stP[j * W + w];
@@ -685,7 +695,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           s.stCnt[2 * j + 1] = hi;
           s.stFp[j] = f;
         }
-        if (s.stMemo[j]) {
+        if (s.stMemo[j] && memo_live) {
           // trie node t_i = P & [x, inf) is now complete for l
           u64 key[W];
 #pragma unroll
@@ -857,8 +867,10 @@ std::vector<Bucket> make_buckets(const dist_graph* g, int32_t nroots) {
   return out;
 }
 
+int wslot(int W) { return W == 1 ? 0 : W == 2 ? 1 : W == 4 ? 2 : W == 8 ? 3 : 4; }
+
 int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_config& cfg, hipStream_t s,
-                u64* totals /* 16 */, double* ms_out) {
+                u64* totals /* 16 */, double* ms_out, dist_stats* bst = nullptr) {
   for (int i = 0; i < kOutWords; ++i) totals[i] = 0;
   if (nroots <= 0) return DIST_OK;
   if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
@@ -912,9 +924,12 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   int rc = ws_ensure((size_t)maxgrid * kOutWords, memo_total);
   if (rc) return rc;
 
-  hipEvent_t e0, e1;
+  hipEvent_t e0, e1, kb0, kb1;
   DIST_CHECK(hipEventCreate(&e0));
   DIST_CHECK(hipEventCreate(&e1));
+  DIST_CHECK(hipEventCreate(&kb0));
+  DIST_CHECK(hipEventCreate(&kb1));
+  double kernel_ms = 0;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, g_ws.cursor, 64);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)g_ws.abort_flag, 16);
   u64 deadline = 0;
@@ -939,6 +954,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     g_ws.tag_next += (u64)nroots + 1;
     size_t lds = lds_bytes(buckets[b].W, base.k);
     hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grids[b] * kOutWords);
+    DIST_CHECK(hipEventRecord(kb0, s));
     switch (buckets[b].W) {
       case 1: rc = launch_bucket<1>(prm, grids[b], lds, s); break;
       case 2: rc = launch_bucket<2>(prm, grids[b], lds, s); break;
@@ -947,9 +963,29 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
       default: rc = launch_bucket<16>(prm, grids[b], lds, s); break;
     }
     if (rc) break;
+    DIST_CHECK(hipEventRecord(kb1, s));
     DIST_CHECK(hipMemcpyAsync(g_ws.host_out, g_ws.wave_out, (size_t)grids[b] * kOutWords * sizeof(u64),
                               hipMemcpyDeviceToHost, s));
     DIST_CHECK(hipStreamSynchronize(s));
+    float kms = 0;
+    DIST_CHECK(hipEventElapsedTime(&kms, kb0, kb1));
+    kernel_ms += kms;
+    u64 bw = 0, bb = 0, br = 0, ba = 0;
+    for (int w = 0; w < grids[b]; ++w) {
+      const u64* o = g_ws.host_out + (size_t)w * kOutWords;
+      br += o[3];
+      bw += o[6];
+      bb += o[7];
+      ba += o[11];
+    }
+    if (bst) {
+      int sl = wslot(buckets[b].W);
+      bst->bucket_ms[sl] += kms;
+      bst->bucket_roots[sl] += br;
+      bst->bucket_word_ops[sl] += bw;
+      bst->bucket_leaf_bits[sl] += bb;
+      bst->bucket_arcs[sl] += ba;
+    }
     for (int w = 0; w < grids[b]; ++w) {
       const u64* o = g_ws.host_out + (size_t)w * kOutWords;
       u64 lo = totals[0] + o[0];
@@ -968,7 +1004,10 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   DIST_CHECK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (ms_out) *ms_out = ms;
+  (void)hipEventDestroy(kb0);
+  (void)hipEventDestroy(kb1);
+  (void)ms;
+  if (ms_out) *ms_out = kernel_ms;
   if (rc) return rc;
   return totals[12] ? DIST_E_CANCELLED : DIST_OK;
 }
@@ -1032,7 +1071,7 @@ int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st) {
   prm.per_root = L.per_root;
   u64 tot[kOutWords];
   double ms = 0;
-  rc = run_buckets(g, prm, nroots, L.cfg, s, tot, &ms);
+  rc = run_buckets(g, prm, nroots, L.cfg, s, tot, &ms, &stats);
   res.count_lo = tot[0];
   res.count_hi = tot[1];
   res.fp = L.cfg.fingerprint ? tot[2] : 0;

@@ -50,10 +50,17 @@ class Stats(ctypes.Structure):
                 ("frames", ctypes.c_uint64), ("word_ops", ctypes.c_uint64),
                 ("leaf_bits", ctypes.c_uint64), ("memo_lookups", ctypes.c_uint64),
                 ("memo_hits", ctypes.c_uint64), ("memo_inserts", ctypes.c_uint64),
-                ("subgraph_arcs", ctypes.c_uint64), ("kernel_ms", ctypes.c_double)]
+                ("subgraph_arcs", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
+                ("bucket_ms", ctypes.c_double * 5), ("bucket_roots", ctypes.c_uint64 * 5),
+                ("bucket_word_ops", ctypes.c_uint64 * 5), ("bucket_leaf_bits", ctypes.c_uint64 * 5),
+                ("bucket_arcs", ctypes.c_uint64 * 5)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        out = {}
+        for f, _ in self._fields_:
+            v = getattr(self, f)
+            out[f] = list(v) if hasattr(v, "__len__") else v
+        return out
 
 
 class GraphInfo(ctypes.Structure):

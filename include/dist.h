@@ -85,6 +85,11 @@ typedef struct {
   int64_t memo_bytes;    /* total memo budget in bytes; 0 = auto (4 GiB) */
   int64_t deadline_ms;   /* stop after this many milliseconds of kernel time
                             and return DIST_E_CANCELLED; 0 = no deadline */
+  int32_t chunk_work;    /* work-unit size for roots with more than 64
+                            out-neighbours: such a root is split into ranges of
+                            max(1, chunk_work / d) depth-1 children that
+                            different wavefronts take; 0 = auto (512) */
+  int32_t reserved;
 } dist_config;
 
 typedef struct {

@@ -25,7 +25,8 @@ void free_graph_arrays(dist_graph* g) {
   (void)hipFree(g->dcol);
   (void)hipFree(g->gw);
   (void)hipFree(g->roots);
-  g->rank = g->orig = g->dptr = g->dcol = g->roots = nullptr;
+  (void)hipFree(g->d_root_deg);
+  g->rank = g->orig = g->dptr = g->dcol = g->roots = g->d_root_deg = nullptr;
   g->gw = nullptr;
 }
 

@@ -27,6 +27,7 @@ struct dist_graph {
   u64* gw = nullptr;         // gw[r] = g(orig[r])
   int32_t* roots = nullptr;  // all ranks sorted by out-degree descending (ties: rank)
   std::vector<int32_t> root_deg;  // host: out-degree of roots[i], non-increasing
+  int32_t* d_root_deg = nullptr;  // the same on the device
   int32_t max_outdeg = 0;
   int32_t order_bound = 0;
   double orient_ms = 0;

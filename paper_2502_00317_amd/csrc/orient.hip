@@ -650,6 +650,8 @@ int orient_build(const int32_t* rp, const int32_t* col, int32_t n, int64_t nnz, 
   DIST_CHECK(hipGetLastError());
   g->root_deg.resize(n);
   for (int32_t i = 0; i < n; ++i) g->root_deg[i] = g->max_outdeg - (int32_t)hk[i];
+  TRY(dev_alloc((void**)&g->d_root_deg, sizeof(int32_t) * nn));
+  if (n) DIST_CHECK(hipMemcpy(g->d_root_deg, g->root_deg.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
   float ms = 0;
   DIST_CHECK(hipEventElapsedTime(&ms, e0, e1));
   g->orient_ms = ms;

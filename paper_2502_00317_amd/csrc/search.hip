@@ -39,6 +39,8 @@
 // 2^61 - 1) and independent of scheduling.
 #include "internal.h"
 
+#include <string.h>
+
 namespace {
 
 constexpr int kWave = 64;
@@ -64,6 +66,10 @@ struct Params {
   int soft_only;    // 1: only compute r_{G'}(u) (capped at k) into soft_out
   int32_t* soft_out;
   unsigned* cursor;
+  const int32_t* root_deg;   // out-degree of roots[i]
+  const uint32_t* unit_prefix;  // units before root i of this bucket (null: one unit per root)
+  uint32_t units;            // work units in this bucket
+  int chunk_work;            // children per unit = max(1, chunk_work / d) for d > 64
   u64* wave_out;
   u64* per_root;
   u64* memo_base;
@@ -78,6 +84,15 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ u64 lanemask_lt() {
   int l = lane_id();
   return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+// Children of one root handled per work unit.  Light roots are one unit;
+// a heavy root (d > 64) is cut into ranges of its depth-1 children so that
+// many waves share it (each wave rebuilds G_u in its own LDS).
+__host__ __device__ inline int chunk_of(int d, int k, int chunk_work) {
+  if (d <= 64 || k <= 3) return d > 0 ? d : 1;
+  int c = chunk_work / d;
+  return c < 1 ? 1 : (c > d ? d : c);
 }
 
 // ---- arithmetic mod p = 2^61 - 1 ------------------------------------------
@@ -356,16 +371,32 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
 
   // per-wave totals (uniform) and per-lane counters
   u64 tot_lo = 0, tot_hi = 0, tot_fp = 0;
-  u64 n_roots = 0, n_pruned = 0, n_frames = 0, n_look = 0, n_hit = 0, n_ins = 0;
+  u64 n_units = 0, n_builds = 0, n_pruned = 0, n_frames = 0, n_look = 0, n_hit = 0, n_ins = 0;
   u64 wops = 0, bits = 0, arcs = 0;
   bool aborted = false;
   const u64 deadline = p.deadline ? wall_clock64() + p.deadline : 0;
+  const int nbk = p.root_end - p.root_begin;
 
+  int cur_rel = -1;       // root whose G_u is in LDS
+  bool cur_pruned = false;
+  int32_t r = 0;
+  int d = 0;
   for (;;) {
-    int ridx = 0;
-    if (lane == 0) ridx = (int)atomicAdd(p.cursor, 1u);
-    ridx = __shfl(ridx, 0) + p.root_begin;
-    if (ridx >= p.root_end) break;
+    // ---- 0. next work unit: (root, range of depth-1 children) -------------------
+    uint32_t u = 0;
+    if (lane == 0) u = atomicAdd(p.cursor, 1u);
+    u = __shfl(u, 0);
+    if (u >= p.units) break;
+    int rel = (int)u, ci = 0;
+    if (p.unit_prefix) {
+      int lo = 0, hi = nbk - 1;  // largest rel with prefix[rel] <= u
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (p.unit_prefix[mid] <= u) lo = mid; else hi = mid - 1;
+      }
+      rel = lo;
+      ci = (int)(u - p.unit_prefix[rel]);
+    }
     if (__hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       aborted = true;
       break;
@@ -375,79 +406,90 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       aborted = true;
       break;
     }
-    const int32_t r = p.roots[ridx];
-    const int32_t beg = p.dptr[r];
-    const int d = p.dptr[r + 1] - beg;  // <= 64 * W by the host's bucketing
+    const int ridx = p.root_begin + rel;
     const u64 root_tag = p.tag_base + (u64)ridx;
-    ++n_roots;
+    ++n_units;
 
-    // ---- 1. G_u in LDS --------------------------------------------------------
-    for (int i = lane; i < d; i += kWave) {
-      int32_t v = p.dcol[beg + i];
-      s.nb[i] = v;
-      s.gl[i] = p.gw[v];
-      int32_t b = p.dptr[v];
-      s.rowptr[i] = b;
-      s.rowbeg[i] = p.dptr[v + 1] - b;  // length, scanned below
-    }
-    for (int i = lane; i < d * W; i += kWave) s.A[i] = 0;
-    __syncthreads();
-    // exclusive scan of row lengths (in chunks of 64)
-    int carry = 0;
-    for (int base = 0; base < d; base += kWave) {
-      int i = base + lane;
-      int len = i < d ? s.rowbeg[i] : 0;
-      int incl = len;
-      for (int off = 1; off < kWave; off <<= 1) {
-        int o = __shfl_up(incl, off);
-        if (lane >= off) incl += o;
+    if (rel != cur_rel) {
+      cur_rel = rel;
+      r = p.roots[ridx];
+      const int32_t beg = p.dptr[r];
+      d = p.dptr[r + 1] - beg;  // <= 64 * W by the host's bucketing
+      ++n_builds;
+      // ---- 1. G_u in LDS ------------------------------------------------------
+      for (int i = lane; i < d; i += kWave) {
+        int32_t v = p.dcol[beg + i];
+        s.nb[i] = v;
+        s.gl[i] = p.gw[v];
+        int32_t b = p.dptr[v];
+        s.rowptr[i] = b;
+        s.rowbeg[i] = p.dptr[v + 1] - b;  // length, scanned below
       }
-      if (i < d) s.rowbeg[i] = carry + incl - len;
-      carry += __shfl(incl, kWave - 1);
-    }
-    if (lane == 0) s.rowbeg[d] = carry;
-    __syncthreads();
-    const int total = carry;
-    const int32_t top_rank = d ? s.nb[d - 1] : 0;
-    for (int t = lane; t < total; t += kWave) {
-      // row i: largest i with rowbeg[i] <= t
-      int lo = 0, hi = d - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (s.rowbeg[mid] <= t) lo = mid; else hi = mid - 1;
-      }
-      int i = lo;
-      int32_t x = p.dcol[s.rowptr[i] + (t - s.rowbeg[i])];
-      ++arcs;
-      if (x > top_rank) continue;
-      // locate x among nb[i+1 .. d-1]
-      int a = i + 1, b = d;
-      while (a < b) {
-        int mid = (a + b) >> 1;
-        if (s.nb[mid] < x) a = mid + 1; else b = mid;
-      }
-      if (a < d && s.nb[a] == x) atomicOr(&s.A[i * W + (a >> 6)], 1ull << (a & 63));
-    }
-    __syncthreads();
-
-    // ---- 2. soft-embedding bound (Algorithm 5) -------------------------------
-    if (p.soft_only) {
-      int rr = soft_embed_levels<W>(s, d, k);
-      if (lane == 0) p.soft_out[p.orig[r]] = rr;
+      for (int i = lane; i < d * W; i += kWave) s.A[i] = 0;
       __syncthreads();
-      continue;
-    }
-    if (p.prune && k >= 3) {
-      int rr = soft_embed_levels<W>(s, d, k);
-      if (rr < k) {
-        ++n_pruned;
+      // exclusive scan of row lengths (in chunks of 64)
+      int carry = 0;
+      for (int base = 0; base < d; base += kWave) {
+        int i = base + lane;
+        int len = i < d ? s.rowbeg[i] : 0;
+        int incl = len;
+        for (int off = 1; off < kWave; off <<= 1) {
+          int o = __shfl_up(incl, off);
+          if (lane >= off) incl += o;
+        }
+        if (i < d) s.rowbeg[i] = carry + incl - len;
+        carry += __shfl(incl, kWave - 1);
+      }
+      if (lane == 0) s.rowbeg[d] = carry;
+      __syncthreads();
+      const int total = carry;
+      const int32_t top_rank = d ? s.nb[d - 1] : 0;
+      for (int t = lane; t < total; t += kWave) {
+        // row i: largest i with rowbeg[i] <= t
+        int lo = 0, hi = d - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (s.rowbeg[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        int i = lo;
+        int32_t x = p.dcol[s.rowptr[i] + (t - s.rowbeg[i])];
+        ++arcs;
+        if (x > top_rank) continue;
+        // locate x among nb[i+1 .. d-1]
+        int a = i + 1, b = d;
+        while (a < b) {
+          int mid = (a + b) >> 1;
+          if (s.nb[mid] < x) a = mid + 1; else b = mid;
+        }
+        if (a < d && s.nb[a] == x) atomicOr(&s.A[i * W + (a >> 6)], 1ull << (a & 63));
+      }
+      __syncthreads();
+
+      // ---- 2. soft-embedding bound (Algorithm 5) ---------------------------------
+      if (p.soft_only) {
+        int rr = soft_embed_levels<W>(s, d, k);
+        if (lane == 0) p.soft_out[p.orig[r]] = rr;
         __syncthreads();
+        cur_pruned = true;  // nothing to search in this mode
         continue;
       }
-    } else {
-      for (int i = lane; i < d; i += kWave) s.rcap[i] = 63;
+      cur_pruned = false;
+      if (p.prune && k >= 3) {
+        int rr = soft_embed_levels<W>(s, d, k);
+        if (rr < k) cur_pruned = true;
+      } else {
+        for (int i = lane; i < d; i += kWave) s.rcap[i] = 63;
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    if (cur_pruned) {
+      if (ci == 0 && !p.soft_only) ++n_pruned;
+      continue;
+    }
+    // children of frame 0 handled by this unit: local ids [x_lo, x_hi)
+    const int ch = p.unit_prefix ? chunk_of(d, k, p.chunk_work) : d;
+    const int x_lo = ci * ch;
+    const int x_hi = x_lo + ch < d ? x_lo + ch : d;
 
     // ---- 3. depth-first search over candidate bitmaps -----------------------------
     // frame j needs l = k-1-j more vertices from its candidate set stP[j].
@@ -498,7 +540,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         if (p.memo == 2) memo_j = (l >= 3);
         else if (p.memo == 1) memo_j = (l >= 3) && j > 0 && s.stMemo[j - 1];
         const u64 tag = (root_tag << 8) | (u64)l;
-        if (memo_j && memo_live) {
+        if (memo_j && memo_live && j > 0) {
           ++n_look;
           ++r_look;
           u64 a, b, c;
@@ -526,6 +568,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             int i = base + lane;
             if (i >= np) continue;
             int x = s.mem[i];
+            if (j == 0 && (x < x_lo || x >= x_hi)) continue;
             u64 q[W];
             int c = 0;
 #pragma unroll
@@ -547,8 +590,8 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           res_lo = wave_sum(c_acc);
           res_hi = 0;
           res_fp = p.fingerprint ? wave_sum_p(f_acc) : 0;
-          if (memo_j && memo_live && lane == 0) memo_put<W>(p, table, tag, root_tag, Pr, res_lo, res_hi, res_fp);
-          if (memo_j && memo_live) ++n_ins;
+          if (memo_j && memo_live && j > 0 && lane == 0) memo_put<W>(p, table, tag, root_tag, Pr, res_lo, res_hi, res_fp);
+          if (memo_j && memo_live && j > 0) ++n_ins;
           __syncthreads();
           mode = FINISH;
           continue;
@@ -576,6 +619,8 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           u64 rhs = (u64)(l - 1) * (u64)np * (u64)np;
           if (np >= 2 && lhs > rhs) {
             memo_j = true;
+          }
+          if (memo_j && j > 0) {
             ++n_look;
             ++r_look;
             u64 a, b, c;
@@ -591,7 +636,16 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         }
         u64 acc_lo = 0, acc_hi = 0, acc_fp = 0;
         __syncthreads();
-        if (memo_j && memo_live && np >= 2) {
+        if (j == 0) {
+          // this unit's share of the root's depth-1 children
+          if (lane < W) {
+            int lo_b = lane * 64;
+            u64 m_lo = (x_lo <= lo_b) ? ~0ull : (x_lo >= lo_b + 64 ? 0ull : (~0ull << (x_lo - lo_b)));
+            u64 m_hi = (x_hi <= lo_b) ? 0ull : (x_hi >= lo_b + 64 ? ~0ull : ((1ull << (x_hi - lo_b)) - 1));
+            Q[lane] &= m_lo & m_hi;
+          }
+        }
+        if (memo_j && memo_live && np >= 2 && j > 0) {
           // resume from the longest memoised proper prefix P & [m_i, inf),
           // m_i the i-th smallest member, i = 1..kMemoProbe (one lane each)
           int i = 1 + lane;
@@ -656,7 +710,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           res_lo = s.stCnt[2 * j];
           res_hi = s.stCnt[2 * j + 1];
           res_fp = s.stFp[j];
-          if (s.stMemo[j] && memo_live) {
+          if (s.stMemo[j] && memo_live && j > 0) {
             u64 Pr[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) Pr[w] = s.stP[j * W + w];
@@ -695,7 +749,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           s.stCnt[2 * j + 1] = hi;
           s.stFp[j] = f;
         }
-        if (s.stMemo[j] && memo_live) {
+        if (s.stMemo[j] && memo_live && j > 0) {
           // trie node t_i = P & [x, inf) is now complete for l
           u64 key[W];
 #pragma unroll
@@ -722,10 +776,16 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
     tot_lo = nlo;
     tot_fp = addp(tot_fp, rfp);
     if (p.per_root && lane == 0) {
+      // several units may share a root: 128-bit add with carry, fp mod p
       u64* o = p.per_root + 3 * (u64)p.orig[r];
-      o[0] = res_lo;
-      o[1] = res_hi;
-      o[2] = rfp;
+      u64 old = atomicAdd((unsigned long long*)&o[0], (unsigned long long)res_lo);
+      u64 carry_in = (old + res_lo < old) ? 1ull : 0ull;
+      if (res_hi + carry_in) atomicAdd((unsigned long long*)&o[1], (unsigned long long)(res_hi + carry_in));
+      u64 cur = o[2], seen;
+      do {
+        seen = cur;
+        cur = atomicCAS((unsigned long long*)&o[2], seen, addp(seen, rfp));
+      } while (cur != seen);
     }
     __syncthreads();
   }
@@ -737,7 +797,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
     o[0] = tot_lo;
     o[1] = tot_hi;
     o[2] = tot_fp;
-    o[3] = n_roots;
+    o[3] = n_units;
     o[4] = n_pruned;
     o[5] = n_frames;
     o[6] = sw;
@@ -747,6 +807,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
     o[10] = n_ins;
     o[11] = sa;
     o[12] = aborted ? 1 : 0;
+    o[13] = n_builds;
   }
 }
 
@@ -791,6 +852,9 @@ struct Workspace {
   u64 tag_next = 1;
   u64* host_out = nullptr;  // pinned
   size_t host_out_words = 0;
+  uint32_t* d_prefix = nullptr;
+  uint32_t* h_prefix = nullptr;  // pinned
+  size_t prefix_cap = 0;
 };
 
 Workspace g_ws;  // one device per process in this library
@@ -822,6 +886,19 @@ int ws_ensure(size_t wave_words, size_t memo_bytes) {
     if (dev_alloc((void**)&g_ws.memo, memo_bytes)) return DIST_E_NOMEM;
     g_ws.memo_bytes = memo_bytes;
   }
+  return DIST_OK;
+}
+
+int ws_prefix(size_t n) {
+  if (n <= g_ws.prefix_cap) return DIST_OK;
+  if (g_ws.d_prefix) (void)hipFree(g_ws.d_prefix);
+  if (g_ws.h_prefix) (void)hipHostFree(g_ws.h_prefix);
+  g_ws.d_prefix = nullptr;
+  g_ws.h_prefix = nullptr;
+  g_ws.prefix_cap = 0;
+  if (dev_alloc((void**)&g_ws.d_prefix, n * sizeof(uint32_t))) return DIST_E_NOMEM;
+  if (hipHostMalloc((void**)&g_ws.h_prefix, n * sizeof(uint32_t)) != hipSuccess) return DIST_E_NOMEM;
+  g_ws.prefix_cap = n;
   return DIST_OK;
 }
 
@@ -882,6 +959,30 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     for (auto& b : buckets)
       if (lds_bytes(b.W, base.k) > (size_t)maxlds) return DIST_E_UNSUPPORTED;
   }
+  // work units: heavy roots are cut into ranges of depth-1 children
+  const int cw = base.chunk_work > 0 ? base.chunk_work : 512;
+  std::vector<std::vector<uint32_t>> prefixes(buckets.size());
+  std::vector<uint32_t> units(buckets.size());
+  size_t max_prefix = 0;
+  for (size_t b = 0; b < buckets.size(); ++b) {
+    int32_t nb = buckets[b].end - buckets[b].begin;
+    uint64_t U = 0;
+    std::vector<uint32_t> pre(nb);
+    for (int32_t i = 0; i < nb; ++i) {
+      int dd = g->root_deg[buckets[b].begin + i];
+      pre[i] = (uint32_t)U;
+      int c = base.soft_only ? dd : chunk_of(dd, base.k, cw);
+      U += (dd <= 0 || c <= 0) ? 1ull : (uint64_t)((dd + c - 1) / c);
+    }
+    if (U >= 0xffffffffull) return DIST_E_UNSUPPORTED;
+    units[b] = (uint32_t)U;
+    if (U > (uint64_t)nb) {
+      prefixes[b].swap(pre);
+      if ((size_t)nb > max_prefix) max_prefix = nb;
+    } else {
+      units[b] = (uint32_t)nb;
+    }
+  }
   // grids and memo sizing
   int maxgrid = 0;
   std::vector<int> grids(buckets.size());
@@ -898,7 +999,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     }
     int cus = g_ws.cus > 0 ? g_ws.cus : 256;
     int64_t grid = (int64_t)occ * cus;
-    int64_t cnt = buckets[b].end - buckets[b].begin;
+    int64_t cnt = units[b];
     if (grid > cnt) grid = cnt;
     if (grid < 1) grid = 1;
     grids[b] = (int)grid;
@@ -923,6 +1024,8 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   }
   int rc = ws_ensure((size_t)maxgrid * kOutWords, memo_total);
   if (rc) return rc;
+  rc = ws_prefix(max_prefix);
+  if (rc) return rc;
 
   hipEvent_t e0, e1, kb0, kb1;
   DIST_CHECK(hipEventCreate(&e0));
@@ -944,6 +1047,16 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     Params prm = base;
     prm.root_begin = buckets[b].begin;
     prm.root_end = buckets[b].end;
+    prm.root_deg = g->d_root_deg;
+    prm.chunk_work = cw;
+    prm.units = units[b];
+    prm.unit_prefix = nullptr;
+    if (!prefixes[b].empty()) {
+      size_t nbytes = prefixes[b].size() * sizeof(uint32_t);
+      memcpy(g_ws.h_prefix, prefixes[b].data(), nbytes);
+      DIST_CHECK(hipMemcpyAsync(g_ws.d_prefix, g_ws.h_prefix, nbytes, hipMemcpyHostToDevice, s));
+      prm.unit_prefix = g_ws.d_prefix;
+    }
     prm.cursor = g_ws.cursor + b;  // one counter per bucket (zeroed above; <= 6 buckets)
     prm.wave_out = g_ws.wave_out;
     prm.abort_flag = g_ws.abort_flag;
@@ -995,6 +1108,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
       totals[2] = f >= DIST_P61 ? f - DIST_P61 : f;
       for (int i = 3; i < 12; ++i) totals[i] += o[i];
       totals[12] |= o[12];
+      totals[13] += o[13];
     }
     if (totals[12]) break;
   }
@@ -1068,6 +1182,7 @@ int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st) {
   prm.memo = L.cfg.memo;
   prm.fingerprint = L.cfg.fingerprint;
   prm.soft_only = 0;
+  prm.chunk_work = L.cfg.chunk_work;
   prm.per_root = L.per_root;
   u64 tot[kOutWords];
   double ms = 0;

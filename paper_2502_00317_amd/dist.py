@@ -33,7 +33,8 @@ class DistError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("memo", ctypes.c_int32), ("prune", ctypes.c_int32),
                 ("fingerprint", ctypes.c_int32), ("memo_entries", ctypes.c_int32),
-                ("memo_bytes", ctypes.c_int64), ("deadline_ms", ctypes.c_int64)]
+                ("memo_bytes", ctypes.c_int64), ("deadline_ms", ctypes.c_int64),
+                ("chunk_work", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

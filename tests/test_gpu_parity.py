@@ -24,7 +24,7 @@ def D():
 
 
 CONFIGS = [dict(memo=1, prune=1), dict(memo=0, prune=0), dict(memo=0, prune=1),
-           dict(memo=2, prune=1), dict(memo=2, prune=0)]
+           dict(memo=2, prune=1), dict(memo=2, prune=0), dict(memo=1, prune=1, chunk_work=64)]
 
 
 def _gpu(D, g, k, order, **cfg):
@@ -67,7 +67,7 @@ def test_complete(D, oracle_mod, n):
     g = gg.complete(n)
     for k in (2, 3, 4, 5, 6):
         want = R.complete_graph_result(n, k)
-        for cfg in CONFIGS[:4]:
+        for cfg in CONFIGS[:4] + CONFIGS[5:]:
             print("K", n, k, cfg, flush=True)
             assert _gpu(D, g, k, D.ORDER_DEGREE, **cfg) == want
 
@@ -97,9 +97,9 @@ def test_small_powerlaw(D, oracle_mod):
 def test_per_root_degree_order(D, oracle_mod):
     g = gg.gnp(80, 0.5, 3)
     G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
-    for k in (3, 4, 5, 6):
+    for k, cw in ((3, 0), (4, 0), (5, 0), (6, 0), (5, 64), (6, 100)):
         per = np.zeros(3 * g.n, np.uint64)
-        D.count(G, k, cfg=D.config(), per_root=per)
+        D.count(G, k, cfg=D.config(chunk_work=cw), per_root=per)
         want = oracle_mod.count_roots(g.row_ptr, g.col, k, np.arange(g.n))
         got = [(int(per[3 * v]) | (int(per[3 * v + 1]) << 64), int(per[3 * v + 2]))
                for v in range(g.n)]

@@ -1,0 +1,274 @@
+// device_common.h -- device code shared by the count and list kernels:
+// lane helpers, arithmetic mod 2^61 - 1, the per-wave LDS layout, the
+// construction of a root's 1-induced subgraph G_u as bitmap rows, the
+// fingerprint weight sums and Algorithm 5 evaluated level by level.
+#pragma once
+
+#include "internal.h"
+
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ u64 lanemask_lt() {
+  int l = lane_id();
+  return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+// ---- arithmetic mod p = 2^61 - 1 ------------------------------------------
+__device__ __forceinline__ u64 addp(u64 a, u64 b) {
+  u64 s = a + b;
+  return s >= DIST_P61 ? s - DIST_P61 : s;
+}
+
+__device__ __forceinline__ u64 mulp(u64 a, u64 b) {
+  u64 lo = a * b;
+  u64 hi = __umul64hi(a, b);
+  u64 r = (lo & DIST_P61) + ((hi << 3) | (lo >> 61));
+  r = (r & DIST_P61) + (r >> 61);
+  return r >= DIST_P61 ? r - DIST_P61 : r;
+}
+
+__device__ __forceinline__ u64 wave_sum(u64 x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+__device__ __forceinline__ u64 wave_sum_p(u64 x) {
+  for (int off = 32; off > 0; off >>= 1) x = addp(x, __shfl_xor(x, off));
+  return x;
+}
+
+__device__ __forceinline__ u64 ld_coherent(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- LDS layout -------------------------------------------------------------
+// u64 part: A (D*W), gl (D), per-level stacks, R (W).  Then a union of the
+// arrays used only while G_u is built (nb, rowbeg, rowptr) with the arrays
+// used only afterwards (mem, pos, rcap).  Then the small per-level arrays.
+struct Lds {
+  u64* A;        // D * W
+  u64* gl;       // D
+  u64* stP;      // (k-1) * W
+  u64* stQ;      // (k-1) * W
+  u64* stCnt;    // (k-1) * 2
+  u64* stFp;     // (k-1)
+  u64* R;        // W   (soft-embedding level bitmap)
+  int32_t* nb;      // D       (build)
+  int32_t* rowbeg;  // D + 1   (build)
+  int32_t* rowptr;  // D       (build)
+  uint16_t* mem;    // D       (search)
+  uint16_t* pos;    // D       (search)
+  uint8_t* rcap;    // D       (search)
+  uint16_t* stX;    // k - 1
+  uint8_t* stMemo;  // k - 1
+};
+
+__host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+__host__ __device__ inline size_t lds_bytes(int W, int k) {
+  size_t D = 64 * (size_t)W, L = (size_t)(k > 1 ? k - 1 : 1);
+  size_t b = 8 * (D * W + D + 2 * L * W + 3 * L + W);
+  size_t build = 4 * (3 * D + 1), post = 5 * D;
+  b += align8(build > post ? build : post);
+  b += align8(3 * L);
+  return b;
+}
+
+template <int W>
+__device__ inline Lds carve(char* base, int k) {
+  const size_t D = 64 * W, L = (size_t)(k > 1 ? k - 1 : 1);
+  Lds s;
+  u64* p = (u64*)base;
+  s.A = p; p += D * W;
+  s.gl = p; p += D;
+  s.stP = p; p += L * W;
+  s.stQ = p; p += L * W;
+  s.stCnt = p; p += 2 * L;
+  s.stFp = p; p += L;
+  s.R = p; p += W;
+  char* u = (char*)p;
+  s.nb = (int32_t*)u;
+  s.rowbeg = s.nb + D;
+  s.rowptr = s.rowbeg + D + 1;
+  s.mem = (uint16_t*)u;
+  s.pos = s.mem + D;
+  s.rcap = (uint8_t*)(s.pos + D);
+  size_t build = 4 * (3 * D + 1), post = 5 * D;
+  char* t = u + align8(build > post ? build : post);
+  s.stX = (uint16_t*)t;
+  s.stMemo = (uint8_t*)(s.stX + L);
+  return s;
+}
+
+// ---- bitmap helpers (W words) -------------------------------------------------
+
+// Σ_{z in q} g(z) mod p over a W-word bitmap held in registers.
+template <int W>
+__device__ __forceinline__ u64 weight_sum(const u64 (&q)[W], const u64* gl, u64& bits_visited) {
+  u64 s = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    u64 b = q[w];
+    while (b) {
+      int t = __ffsll((unsigned long long)b) - 1;
+      b &= b - 1;
+      s += gl[w * 64 + t];
+      s = (s & DIST_P61) + (s >> 61);
+      ++bits_visited;
+    }
+  }
+  return s >= DIST_P61 ? s - DIST_P61 : s;
+}
+
+// Edges of G[Y] and their fingerprint sum Σ g(y) g(z) over edges y<z.
+template <int W>
+__device__ __forceinline__ void edges_in(const u64 (&Y)[W], const u64* A, const u64* gl, int fpon,
+                                         u64& cnt, u64& fp, u64& wops, u64& bits) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    u64 b = Y[w];
+    while (b) {
+      int t = __ffsll((unsigned long long)b) - 1;
+      b &= b - 1;
+      int y = w * 64 + t;
+      u64 q[W];
+      int c = 0;
+#pragma unroll
+      for (int v = 0; v < W; ++v) {
+        q[v] = Y[v] & A[y * W + v];
+        c += __popcll(q[v]);
+      }
+      wops += W;
+      cnt += (u64)c;
+      if (fpon && c) fp = addp(fp, mulp(gl[y], weight_sum<W>(q, gl, bits)));
+    }
+  }
+}
+
+// ---- Algorithm 5, level by level -------------------------------------------
+// Algorithm 5 scans the out-neighbours of x from the highest down and raises
+// r(x) from c to c + 1 at the first neighbour y (below the previous one)
+// with r(y) >= c.  Pass c therefore needs only R_c = {y : r(y) >= c} and the
+// position reached at pass c - 1, and all x can take pass c in parallel.
+// rcap[x] = min(r_{G_u}(x), K - 1).  Returns min(r_{G'}(u), K) for the root.
+template <int W>
+__device__ int soft_embed_levels(const Lds& s, int d, int K) {
+  const int lane = lane_id();
+  for (int i = lane; i < d; i += kWave) {
+    s.rcap[i] = 1;
+    s.pos[i] = (uint16_t)d;
+  }
+  __syncthreads();
+  for (int c = 1; c <= K - 2; ++c) {
+    for (int w = 0; w < W; ++w) {
+      int idx = w * 64 + lane;
+      u64 b = __ballot(idx < d && s.rcap[idx] >= c);
+      if (lane == 0) s.R[w] = b;
+    }
+    __syncthreads();
+    int raised = 0;
+    for (int i = lane; i < d; i += kWave) {
+      if (s.rcap[i] != c) continue;
+      int ps = s.pos[i];  // search strictly below ps
+      int found = -1;
+      for (int w = (ps - 1) >> 6; w >= 0 && found < 0; --w) {
+        u64 m = s.A[i * W + w] & s.R[w];
+        int top = ps - w * 64;  // bits >= top are excluded
+        if (top < 64) m &= (top <= 0) ? 0ull : ((1ull << top) - 1);
+        if (m) found = w * 64 + 63 - __clzll((long long)m);
+      }
+      if (found >= 0) {
+        s.rcap[i] = (uint8_t)(c + 1);
+        s.pos[i] = (uint16_t)found;
+        raised = 1;
+      }
+    }
+    __syncthreads();
+    if (!__any(raised)) break;
+  }
+  // root: its out-neighbours are all local vertices
+  int r = 1, ps = d;
+  for (int c = 1; c <= K - 1; ++c) {
+    int found = -1;
+    for (int base = ((ps - 1) >> 6) << 6; base >= 0 && ps > 0; base -= 64) {
+      int idx = base + lane;
+      u64 b = __ballot(idx < ps && s.rcap[idx] >= c);
+      if (b) {
+        found = base + 63 - __clzll((long long)b);
+        break;
+      }
+    }
+    if (found < 0) break;
+    r = c + 1;
+    ps = found;
+  }
+  return r;
+}
+
+// ---- G_u = G[N+(u)] as bitmap rows in LDS -----------------------------------
+// Local id i is the i-th out-neighbour of root r in rank order; row i holds
+// the local ids j > i with v_j in N+(v_i).  Each out-list N+(v_i) is read
+// from HBM (flattened over the wave so that reads are coalesced) and every
+// entry is located in N+(r) by binary search in LDS.  If oid is set, oid[i]
+// receives the input id of local vertex i.  Returns the arcs read (per lane).
+template <int W>
+__device__ u64 build_subgraph(const Lds& s, const int32_t* dptr, const int32_t* dcol, const u64* gw,
+                              const int32_t* orig, int32_t* oid, int32_t beg, int d) {
+  const int lane = lane_id();
+  u64 arcs = 0;
+  for (int i = lane; i < d; i += kWave) {
+    int32_t v = dcol[beg + i];
+    s.nb[i] = v;
+    s.gl[i] = gw[v];
+    if (oid) oid[i] = orig[v];
+    int32_t b = dptr[v];
+    s.rowptr[i] = b;
+    s.rowbeg[i] = dptr[v + 1] - b;  // length, scanned below
+  }
+  for (int i = lane; i < d * W; i += kWave) s.A[i] = 0;
+  __syncthreads();
+  // exclusive scan of row lengths (in chunks of 64)
+  int carry = 0;
+  for (int base = 0; base < d; base += kWave) {
+    int i = base + lane;
+    int len = i < d ? s.rowbeg[i] : 0;
+    int incl = len;
+    for (int off = 1; off < kWave; off <<= 1) {
+      int o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    if (i < d) s.rowbeg[i] = carry + incl - len;
+    carry += __shfl(incl, kWave - 1);
+  }
+  if (lane == 0) s.rowbeg[d] = carry;
+  __syncthreads();
+  const int total = carry;
+  const int32_t top_rank = d ? s.nb[d - 1] : 0;
+  for (int t = lane; t < total; t += kWave) {
+    // row i: largest i with rowbeg[i] <= t
+    int lo = 0, hi = d - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (s.rowbeg[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    int i = lo;
+    int32_t x = dcol[s.rowptr[i] + (t - s.rowbeg[i])];
+    ++arcs;
+    if (x > top_rank) continue;
+    // locate x among nb[i+1 .. d-1]
+    int a = i + 1, b = d;
+    while (a < b) {
+      int mid = (a + b) >> 1;
+      if (s.nb[mid] < x) a = mid + 1; else b = mid;
+    }
+    if (a < d && s.nb[a] == x) atomicOr(&s.A[i * W + (a >> 6)], 1ull << (a & 63));
+  }
+  __syncthreads();
+  return arcs;
+}
+
+}  // namespace

@@ -37,13 +37,12 @@
 //
 // Every quantity is an integer; the result is exact (u128 count, fp mod
 // 2^61 - 1) and independent of scheduling.
-#include "internal.h"
+#include "device_common.h"
 
 #include <string.h>
 
 namespace {
 
-constexpr int kWave = 64;
 constexpr int kOutWords = 16;
 constexpr int kMemoProbe = 4;
 // A root stops using its memo table once at least kMemoMinLook lookups
@@ -66,6 +65,10 @@ struct Params {
   int soft_only;    // 1: only compute r_{G'}(u) (capped at k) into soft_out
   int32_t* soft_out;
   unsigned* cursor;
+  int32_t* out;              // listing: records of k input ids
+  u64 out_cap;               // records that fit in out
+  unsigned long long* out_cursor;
+  int* out_overflow;
   const int32_t* root_deg;   // out-degree of roots[i]
   const uint32_t* unit_prefix;  // units before root i of this bucket (null: one unit per root)
   uint32_t units;            // work units in this bucket
@@ -79,13 +82,6 @@ struct Params {
   int* abort_flag;
 };
 
-__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
-
-__device__ __forceinline__ u64 lanemask_lt() {
-  int l = lane_id();
-  return l ? (~0ull >> (64 - l)) : 0ull;
-}
-
 // Children of one root handled per work unit.  Light roots are one unit;
 // a heavy root (d > 64) is cut into ranges of its depth-1 children so that
 // many waves share it (each wave rebuilds G_u in its own LDS).
@@ -93,138 +89,6 @@ __host__ __device__ inline int chunk_of(int d, int k, int chunk_work) {
   if (d <= 64 || k <= 3) return d > 0 ? d : 1;
   int c = chunk_work / d;
   return c < 1 ? 1 : (c > d ? d : c);
-}
-
-// ---- arithmetic mod p = 2^61 - 1 ------------------------------------------
-__device__ __forceinline__ u64 addp(u64 a, u64 b) {
-  u64 s = a + b;
-  return s >= DIST_P61 ? s - DIST_P61 : s;
-}
-
-__device__ __forceinline__ u64 mulp(u64 a, u64 b) {
-  u64 lo = a * b;
-  u64 hi = __umul64hi(a, b);
-  u64 r = (lo & DIST_P61) + ((hi << 3) | (lo >> 61));
-  r = (r & DIST_P61) + (r >> 61);
-  return r >= DIST_P61 ? r - DIST_P61 : r;
-}
-
-__device__ __forceinline__ u64 wave_sum(u64 x) {
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-  return x;
-}
-
-__device__ __forceinline__ u64 wave_sum_p(u64 x) {
-  for (int off = 32; off > 0; off >>= 1) x = addp(x, __shfl_xor(x, off));
-  return x;
-}
-
-__device__ __forceinline__ u64 ld_coherent(const u64* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ---- LDS layout -------------------------------------------------------------
-// u64 part: A (D*W), gl (D), per-level stacks, R (W).  Then a union of the
-// arrays used only while G_u is built (nb, rowbeg, rowptr) with the arrays
-// used only afterwards (mem, pos, rcap).  Then the small per-level arrays.
-struct Lds {
-  u64* A;        // D * W
-  u64* gl;       // D
-  u64* stP;      // (k-1) * W
-  u64* stQ;      // (k-1) * W
-  u64* stCnt;    // (k-1) * 2
-  u64* stFp;     // (k-1)
-  u64* R;        // W   (soft-embedding level bitmap)
-  int32_t* nb;      // D       (build)
-  int32_t* rowbeg;  // D + 1   (build)
-  int32_t* rowptr;  // D       (build)
-  uint16_t* mem;    // D       (search)
-  uint16_t* pos;    // D       (search)
-  uint8_t* rcap;    // D       (search)
-  uint16_t* stX;    // k - 1
-  uint8_t* stMemo;  // k - 1
-};
-
-__host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
-
-__host__ __device__ inline size_t lds_bytes(int W, int k) {
-  size_t D = 64 * (size_t)W, L = (size_t)(k > 1 ? k - 1 : 1);
-  size_t b = 8 * (D * W + D + 2 * L * W + 3 * L + W);
-  size_t build = 4 * (3 * D + 1), post = 5 * D;
-  b += align8(build > post ? build : post);
-  b += align8(3 * L);
-  return b;
-}
-
-template <int W>
-__device__ inline Lds carve(char* base, int k) {
-  const size_t D = 64 * W, L = (size_t)(k > 1 ? k - 1 : 1);
-  Lds s;
-  u64* p = (u64*)base;
-  s.A = p; p += D * W;
-  s.gl = p; p += D;
-  s.stP = p; p += L * W;
-  s.stQ = p; p += L * W;
-  s.stCnt = p; p += 2 * L;
-  s.stFp = p; p += L;
-  s.R = p; p += W;
-  char* u = (char*)p;
-  s.nb = (int32_t*)u;
-  s.rowbeg = s.nb + D;
-  s.rowptr = s.rowbeg + D + 1;
-  s.mem = (uint16_t*)u;
-  s.pos = s.mem + D;
-  s.rcap = (uint8_t*)(s.pos + D);
-  size_t build = 4 * (3 * D + 1), post = 5 * D;
-  char* t = u + align8(build > post ? build : post);
-  s.stX = (uint16_t*)t;
-  s.stMemo = (uint8_t*)(s.stX + L);
-  return s;
-}
-
-// ---- bitmap helpers (W words) -------------------------------------------------
-
-// Σ_{z in q} g(z) mod p over a W-word bitmap held in registers.
-template <int W>
-__device__ __forceinline__ u64 weight_sum(const u64 (&q)[W], const u64* gl, u64& bits_visited) {
-  u64 s = 0;
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    u64 b = q[w];
-    while (b) {
-      int t = __ffsll((unsigned long long)b) - 1;
-      b &= b - 1;
-      s += gl[w * 64 + t];
-      s = (s & DIST_P61) + (s >> 61);
-      ++bits_visited;
-    }
-  }
-  return s >= DIST_P61 ? s - DIST_P61 : s;
-}
-
-// Edges of G[Y] and their fingerprint sum Σ g(y) g(z) over edges y<z.
-template <int W>
-__device__ __forceinline__ void edges_in(const u64 (&Y)[W], const u64* A, const u64* gl, int fpon,
-                                         u64& cnt, u64& fp, u64& wops, u64& bits) {
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    u64 b = Y[w];
-    while (b) {
-      int t = __ffsll((unsigned long long)b) - 1;
-      b &= b - 1;
-      int y = w * 64 + t;
-      u64 q[W];
-      int c = 0;
-#pragma unroll
-      for (int v = 0; v < W; ++v) {
-        q[v] = Y[v] & A[y * W + v];
-        c += __popcll(q[v]);
-      }
-      wops += W;
-      cnt += (u64)c;
-      if (fpon && c) fp = addp(fp, mulp(gl[y], weight_sum<W>(q, gl, bits)));
-    }
-  }
 }
 
 // ---- per-wave memo table (Induced Subgraph Trie nodes, counting form) --------
@@ -298,74 +162,60 @@ __device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, u
   __threadfence_block();
 }
 
-// ---- Algorithm 5, level by level -------------------------------------------
-// Algorithm 5 scans the out-neighbours of x from the highest down and raises
-// r(x) from c to c + 1 at the first neighbour y (below the previous one)
-// with r(y) >= c.  Pass c therefore needs only R_c = {y : r(y) >= c} and the
-// position reached at pass c - 1, and all x can take pass c in parallel.
-// rcap[x] = min(r_{G_u}(x), K - 1).  Returns min(r_{G'}(u), K) for the root.
-template <int W>
-__device__ int soft_embed_levels(const Lds& s, int d, int K) {
+// ---- listing: record slots and sorted records ----------------------------------
+
+// Wave-collective: reserve cnt record slots for every lane; returns the
+// lane's first slot, or ~0 if the batch would overflow the buffer (then
+// nothing is written and the host reports the error).
+__device__ u64 reserve_records(const Params& p, u64 cnt) {
   const int lane = lane_id();
-  for (int i = lane; i < d; i += kWave) {
-    s.rcap[i] = 1;
-    s.pos[i] = (uint16_t)d;
+  u64 incl = cnt;
+  for (int off = 1; off < kWave; off <<= 1) {
+    u64 o = __shfl_up(incl, off);
+    if (lane >= off) incl += o;
   }
-  __syncthreads();
-  for (int c = 1; c <= K - 2; ++c) {
-    for (int w = 0; w < W; ++w) {
-      int idx = w * 64 + lane;
-      u64 b = __ballot(idx < d && s.rcap[idx] >= c);
-      if (lane == 0) s.R[w] = b;
-    }
-    __syncthreads();
-    int raised = 0;
-    for (int i = lane; i < d; i += kWave) {
-      if (s.rcap[i] != c) continue;
-      int ps = s.pos[i];  // search strictly below ps
-      int found = -1;
-      for (int w = (ps - 1) >> 6; w >= 0 && found < 0; --w) {
-        u64 m = s.A[i * W + w] & s.R[w];
-        int top = ps - w * 64;  // bits >= top are excluded
-        if (top < 64) m &= (top <= 0) ? 0ull : ((1ull << top) - 1);
-        if (m) found = w * 64 + 63 - __clzll((long long)m);
-      }
-      if (found >= 0) {
-        s.rcap[i] = (uint8_t)(c + 1);
-        s.pos[i] = (uint16_t)found;
-        raised = 1;
-      }
-    }
-    __syncthreads();
-    if (!__any(raised)) break;
+  u64 total = __shfl(incl, kWave - 1);
+  u64 base = 0;
+  if (lane == 0 && total) base = atomicAdd(p.out_cursor, (unsigned long long)total);
+  base = __shfl(base, 0);
+  bool ok = base + total <= p.out_cap;
+  if (!ok && lane == 0 && total) atomicOr(p.out_overflow, 1);
+  return ok ? base + incl - cnt : ~0ull;
+}
+
+// Writes the clique pre[0..np) u {a, b, c}[0..nl) (pre sorted ascending,
+// leaf ids distinct from it) as one ascending record.
+__device__ __forceinline__ void write_record(int32_t* dst, const int32_t* pre, int np, int nl, int32_t a,
+                                             int32_t b, int32_t c) {
+  // slot of a value = #smaller prefix ids + #smaller leaf ids
+  int32_t lv[3] = {a, b, c};
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t >= nl) break;
+    int32_t v = lv[t];
+    int pos = 0;
+    for (int q = 0; q < np; ++q) pos += pre[q] < v;
+    pos += (nl > 0 && a < v) + (nl > 1 && b < v) + (nl > 2 && c < v);
+    dst[pos] = v;
   }
-  // root: its out-neighbours are all local vertices
-  int r = 1, ps = d;
-  for (int c = 1; c <= K - 1; ++c) {
-    int found = -1;
-    for (int base = ((ps - 1) >> 6) << 6; base >= 0 && ps > 0; base -= 64) {
-      int idx = base + lane;
-      u64 b = __ballot(idx < ps && s.rcap[idx] >= c);
-      if (b) {
-        found = base + 63 - __clzll((long long)b);
-        break;
-      }
-    }
-    if (found < 0) break;
-    r = c + 1;
-    ps = found;
+  for (int q = 0; q < np; ++q) {
+    int32_t v = pre[q];
+    int pos = q + (nl > 0 && a < v) + (nl > 1 && b < v) + (nl > 2 && c < v);
+    dst[pos] = v;
   }
-  return r;
 }
 
 // ---- the kernel ----------------------------------------------------------------
 
-template <int W>
+template <int W, bool EMIT>
 __global__ __launch_bounds__(64) void k_search(Params p) {
   extern __shared__ __align__(16) char smem[];
   const int lane = lane_id();
   const int k = p.k;
   const Lds s = carve<W>(smem, k);
+  // listing only: input ids of the local vertices and the sorted prefix
+  int32_t* const oid = EMIT ? (int32_t*)(smem + lds_bytes(W, k)) : nullptr;
+  int32_t* const pre = EMIT ? oid + 64 * W : nullptr;
   const int ES = W + 4;
   u64* table = p.memo_base ? p.memo_base + (u64)blockIdx.x * (p.memo_mask + 1) * ES : nullptr;
 
@@ -417,53 +267,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       d = p.dptr[r + 1] - beg;  // <= 64 * W by the host's bucketing
       ++n_builds;
       // ---- 1. G_u in LDS ------------------------------------------------------
-      for (int i = lane; i < d; i += kWave) {
-        int32_t v = p.dcol[beg + i];
-        s.nb[i] = v;
-        s.gl[i] = p.gw[v];
-        int32_t b = p.dptr[v];
-        s.rowptr[i] = b;
-        s.rowbeg[i] = p.dptr[v + 1] - b;  // length, scanned below
-      }
-      for (int i = lane; i < d * W; i += kWave) s.A[i] = 0;
-      __syncthreads();
-      // exclusive scan of row lengths (in chunks of 64)
-      int carry = 0;
-      for (int base = 0; base < d; base += kWave) {
-        int i = base + lane;
-        int len = i < d ? s.rowbeg[i] : 0;
-        int incl = len;
-        for (int off = 1; off < kWave; off <<= 1) {
-          int o = __shfl_up(incl, off);
-          if (lane >= off) incl += o;
-        }
-        if (i < d) s.rowbeg[i] = carry + incl - len;
-        carry += __shfl(incl, kWave - 1);
-      }
-      if (lane == 0) s.rowbeg[d] = carry;
-      __syncthreads();
-      const int total = carry;
-      const int32_t top_rank = d ? s.nb[d - 1] : 0;
-      for (int t = lane; t < total; t += kWave) {
-        // row i: largest i with rowbeg[i] <= t
-        int lo = 0, hi = d - 1;
-        while (lo < hi) {
-          int mid = (lo + hi + 1) >> 1;
-          if (s.rowbeg[mid] <= t) lo = mid; else hi = mid - 1;
-        }
-        int i = lo;
-        int32_t x = p.dcol[s.rowptr[i] + (t - s.rowbeg[i])];
-        ++arcs;
-        if (x > top_rank) continue;
-        // locate x among nb[i+1 .. d-1]
-        int a = i + 1, b = d;
-        while (a < b) {
-          int mid = (a + b) >> 1;
-          if (s.nb[mid] < x) a = mid + 1; else b = mid;
-        }
-        if (a < d && s.nb[a] == x) atomicOr(&s.A[i * W + (a >> 6)], 1ull << (a & 63));
-      }
-      __syncthreads();
+      arcs += build_subgraph<W>(s, p.dptr, p.dcol, p.gw, p.orig, oid, beg, d);
 
       // ---- 2. soft-embedding bound (Algorithm 5) ---------------------------------
       if (p.soft_only) {
@@ -526,6 +330,21 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           u64 c = 0;
 #pragma unroll
           for (int w = 0; w < W; ++w) c += __popcll(Pr[w]);
+          if constexpr (EMIT) {
+            // only at k = 2: records {root, x}
+            const int32_t rid = p.orig[r];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              bool in = (Pr[w] >> lane) & 1ull;
+              u64 slot = reserve_records(p, in ? 1 : 0);
+              if (in && slot != ~0ull) {
+                int32_t xid = oid[w * 64 + lane];
+                int32_t* dst = p.out + slot * 2;
+                dst[0] = rid < xid ? rid : xid;
+                dst[1] = rid < xid ? xid : rid;
+              }
+            }
+          }
           u64 f = 0;
           if (p.fingerprint) {
             u64 tmpb = 0;
@@ -563,28 +382,91 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         }
         __syncthreads();
         if (l == 2 || l == 3) {
+          int npre = 0;
+          if constexpr (EMIT) {
+            // sorted input ids of the chosen vertices: root and stX[0..j)
+            npre = j + 1;
+            if (lane == 0) {
+              pre[0] = p.orig[r];
+              for (int t = 0; t < j; ++t) {
+                int32_t v = oid[s.stX[t]];
+                int q = t + 1;
+                while (q > 0 && pre[q - 1] > v) {
+                  pre[q] = pre[q - 1];
+                  --q;
+                }
+                pre[q] = v;
+              }
+            }
+            __syncthreads();
+          }
           u64 c_acc = 0, f_acc = 0;
           for (int base = 0; base < np; base += kWave) {
             int i = base + lane;
-            if (i >= np) continue;
-            int x = s.mem[i];
-            if (j == 0 && (x < x_lo || x >= x_hi)) continue;
+            bool act = i < np;
+            int x = act ? s.mem[i] : 0;
+            if (j == 0 && (x < x_lo || x >= x_hi)) act = false;
             u64 q[W];
             int c = 0;
+            u64 mine = 0;
+            if (act) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-              q[w] = Pr[w] & s.A[x * W + w];
-              c += __popcll(q[w]);
+              for (int w = 0; w < W; ++w) {
+                q[w] = Pr[w] & s.A[x * W + w];
+                c += __popcll(q[w]);
+              }
+              wops += W;
+              if (l == 2) {
+                c_acc += (u64)c;
+                mine = (u64)c;
+                if (p.fingerprint && c) f_acc = addp(f_acc, mulp(s.gl[x], weight_sum<W>(q, s.gl, bits)));
+              } else if (c >= 2 && s.rcap[x] >= 3) {
+                u64 ec = 0, ef = 0;
+                edges_in<W>(q, s.A, s.gl, p.fingerprint, ec, ef, wops, bits);
+                c_acc += ec;
+                mine = ec;
+                if (p.fingerprint && ec) f_acc = addp(f_acc, mulp(s.gl[x], ef));
+              }
             }
-            wops += W;
-            if (l == 2) {
-              c_acc += (u64)c;
-              if (p.fingerprint && c) f_acc = addp(f_acc, mulp(s.gl[x], weight_sum<W>(q, s.gl, bits)));
-            } else if (c >= 2 && s.rcap[x] >= 3) {
-              u64 ec = 0, ef = 0;
-              edges_in<W>(q, s.A, s.gl, p.fingerprint, ec, ef, wops, bits);
-              c_acc += ec;
-              if (p.fingerprint && ec) f_acc = addp(f_acc, mulp(s.gl[x], ef));
+            if constexpr (EMIT) {
+              u64 slot = reserve_records(p, mine);
+              if (mine && slot != ~0ull) {
+                int32_t* dst = p.out + slot * (u64)k;
+                const int32_t xid = oid[x];
+                if (l == 2) {
+#pragma unroll
+                  for (int w = 0; w < W; ++w) {
+                    u64 b = q[w];
+                    while (b) {
+                      int t = __ffsll((unsigned long long)b) - 1;
+                      b &= b - 1;
+                      write_record(dst, pre, npre, 2, xid, oid[w * 64 + t], 0);
+                      dst += k;
+                    }
+                  }
+                } else {
+#pragma unroll
+                  for (int w = 0; w < W; ++w) {
+                    u64 b = q[w];
+                    while (b) {
+                      int t = __ffsll((unsigned long long)b) - 1;
+                      b &= b - 1;
+                      int y = w * 64 + t;
+                      const int32_t yid = oid[y];
+#pragma unroll
+                      for (int v = 0; v < W; ++v) {
+                        u64 bz = q[v] & s.A[y * W + v];
+                        while (bz) {
+                          int tz = __ffsll((unsigned long long)bz) - 1;
+                          bz &= bz - 1;
+                          write_record(dst, pre, npre, 3, xid, yid, oid[v * 64 + tz]);
+                          dst += k;
+                        }
+                      }
+                    }
+                  }
+                }
+              }
             }
           }
           res_lo = wave_sum(c_acc);
@@ -905,14 +787,14 @@ int ws_prefix(size_t n) {
 template <int W>
 int occupancy_blocks(size_t lds) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W>, 64, lds) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, false>, 64, lds) != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
 template <int W>
 int launch_bucket(Params prm, int grid, size_t lds, hipStream_t s) {
-  DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_search<W>, dim3(grid), dim3(64), lds, s, prm);
+  DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_search<W, false>), dim3(grid), dim3(64), lds, s, prm);
   DIST_CHECK(hipGetLastError());
   return DIST_OK;
 }
@@ -1227,4 +1109,237 @@ int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out, hipStre
   u64 tot[kOutWords];
   double ms = 0;
   return run_buckets(g, prm, g->n, cfg, s, tot, &ms);
+}
+
+// ---- listing driver ------------------------------------------------------------
+namespace {
+
+constexpr size_t kListBufBytes = (size_t)512 << 20;    // device record buffer
+constexpr size_t kListStageBytes = (size_t)64 << 20;   // pinned host staging
+
+__global__ void k_gather_counts(const u64* per_root, const int32_t* orig, const int32_t* roots, int32_t nroots,
+                                u64* out, int* wide) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < nroots; i += stride) {
+    const u64* o = per_root + 3 * (u64)orig[roots[i]];
+    out[i] = o[0];
+    if (o[1]) atomicOr(wide, 1);
+  }
+}
+
+template <int W>
+int launch_list(Params prm, int grid, size_t lds, hipStream_t s) {
+  DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_search<W, true>), dim3(grid), dim3(64), lds, s, prm);
+  DIST_CHECK(hipGetLastError());
+  return DIST_OK;
+}
+
+template <int W>
+int occupancy_list(size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, true>, 64, lds) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+size_t list_lds_bytes(int W, int k) { return lds_bytes(W, k) + align8(4 * (size_t)64 * W) + align8(4 * (size_t)(k + 1)); }
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+};
+struct HostBuf {
+  void* p = nullptr;
+  ~HostBuf() { if (p) (void)hipHostFree(p); }
+};
+
+}  // namespace
+
+int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink sink, void* user, hipStream_t s,
+                dist_result* out) {
+  dist_result res{0, 0, 0};
+  dist_config cfg = cfg_in;
+  *out = res;
+  if (k == 1) {
+    // every vertex is a 1-clique
+    SearchLaunch L{g, 1, cfg, nullptr, s};
+    dist_stats st{};
+    int rc = search_count(L, &res, &st);
+    if (rc) return rc;
+    std::vector<int32_t> ids(1 << 20);
+    for (int32_t a = 0; a < g->n; a += (int32_t)ids.size()) {
+      int32_t c = g->n - a < (int32_t)ids.size() ? g->n - a : (int32_t)ids.size();
+      for (int32_t i = 0; i < c; ++i) ids[i] = a + i;
+      if (sink(ids.data(), (uint64_t)c, 1, user)) {
+        *out = res;
+        return DIST_E_CANCELLED;
+      }
+    }
+    *out = res;
+    return DIST_OK;
+  }
+  int32_t lo = 0, hi = g->n;
+  while (lo < hi) {
+    int32_t mid = (lo + hi) / 2;
+    if (g->root_deg[mid] >= k - 1) lo = mid + 1; else hi = mid;
+  }
+  const int32_t nroots = lo;
+  if (nroots == 0) {
+    *out = res;
+    return DIST_OK;
+  }
+  if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
+  // 1. per-root clique counts (count kernel), gathered in root order
+  DevBuf per, cnts, wide;
+  if (dev_alloc(&per.p, sizeof(u64) * 3 * ((size_t)g->n + 1))) return DIST_E_NOMEM;
+  if (dev_alloc(&cnts.p, sizeof(u64) * (size_t)nroots)) return DIST_E_NOMEM;
+  if (dev_alloc(&wide.p, 64)) return DIST_E_NOMEM;
+  {
+    SearchLaunch L{g, k, cfg, (u64*)per.p, s};
+    dist_result tmp;
+    dist_stats st{};
+    int rc = search_count(L, &tmp, &st);
+    if (rc != DIST_OK && rc != DIST_E_OVERFLOW) return rc;
+  }
+  DIST_CHECK(hipMemsetAsync(wide.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_gather_counts, dim3(256), dim3(256), 0, s, (const u64*)per.p, g->orig, g->roots, nroots,
+                     (u64*)cnts.p, (int*)wide.p);
+  std::vector<u64> rc_host(nroots);
+  int wide_h = 0;
+  DIST_CHECK(hipMemcpyAsync(rc_host.data(), cnts.p, sizeof(u64) * nroots, hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipMemcpyAsync(&wide_h, wide.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipStreamSynchronize(s));
+  if (wide_h) return DIST_E_UNSUPPORTED;
+  const u64 rec_bytes = 4ull * (u64)k;
+  u64 total = 0;
+  for (u64 c : rc_host) total += c;
+  u64 cap = kListBufBytes / rec_bytes;
+  for (u64 c : rc_host)
+    if (c > cap) return DIST_E_UNSUPPORTED;  // one root's output exceeds the buffer
+  if (total < cap) cap = total > 0 ? total : 1;
+  // 2. buffers
+  DevBuf obuf, ocur;
+  HostBuf stage;
+  if (dev_alloc(&obuf.p, cap * rec_bytes)) return DIST_E_NOMEM;
+  if (dev_alloc(&ocur.p, 64)) return DIST_E_NOMEM;
+  size_t stage_bytes = cap * rec_bytes < kListStageBytes ? cap * rec_bytes : kListStageBytes;
+  stage_bytes = stage_bytes / rec_bytes * rec_bytes;
+  if (stage_bytes == 0) stage_bytes = rec_bytes;
+  if (hipHostMalloc(&stage.p, stage_bytes) != hipSuccess) return DIST_E_NOMEM;
+  std::vector<Bucket> buckets = make_buckets(g, nroots);
+  int rc = ws_ensure(16 * kOutWords, 0);
+  if (rc) return rc;
+  int maxlds = 0;
+  DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, g_ws.device));
+  u64 tot_lo = 0, tot_hi = 0, tot_fp = 0;
+  bool cancelled = false;
+  for (auto& bk : buckets) {
+    const int W = bk.W;
+    const size_t lds = list_lds_bytes(W, k);
+    if (lds > (size_t)maxlds) return DIST_E_UNSUPPORTED;
+    int occ = 1;
+    switch (W) {
+      case 1: occ = occupancy_list<1>(lds); break;
+      case 2: occ = occupancy_list<2>(lds); break;
+      case 4: occ = occupancy_list<4>(lds); break;
+      case 8: occ = occupancy_list<8>(lds); break;
+      default: occ = occupancy_list<16>(lds); break;
+    }
+    const int cus = g_ws.cus > 0 ? g_ws.cus : 256;
+    int32_t b0 = bk.begin;
+    while (b0 < bk.end && !cancelled) {
+      // batch [b0, b1): total records within the buffer
+      u64 sum = 0;
+      int32_t b1 = b0;
+      while (b1 < bk.end && sum + rc_host[b1] <= cap) sum += rc_host[b1++];
+      int64_t grid = (int64_t)occ * cus;
+      if (grid > b1 - b0) grid = b1 - b0;
+      if (grid < 1) grid = 1;
+      rc = ws_ensure((size_t)grid * kOutWords, 0);
+      if (rc) return rc;
+      Params prm{};
+      prm.dptr = g->dptr;
+      prm.dcol = g->dcol;
+      prm.gw = g->gw;
+      prm.orig = g->orig;
+      prm.roots = g->roots;
+      prm.root_begin = b0;
+      prm.root_end = b1;
+      prm.k = k;
+      prm.prune = cfg.prune;
+      prm.memo = 0;
+      prm.fingerprint = cfg.fingerprint;
+      prm.soft_only = 0;
+      prm.cursor = g_ws.cursor;
+      prm.root_deg = g->d_root_deg;
+      prm.unit_prefix = nullptr;
+      prm.units = (uint32_t)(b1 - b0);
+      prm.chunk_work = 1 << 30;
+      prm.wave_out = g_ws.wave_out;
+      prm.per_root = nullptr;
+      prm.memo_base = nullptr;
+      prm.memo_mask = 0;
+      prm.tag_base = 0;
+      prm.deadline = 0;
+      prm.abort_flag = g_ws.abort_flag;
+      prm.out = (int32_t*)obuf.p;
+      prm.out_cap = cap;
+      prm.out_cursor = (unsigned long long*)ocur.p;
+      prm.out_overflow = (int*)((char*)ocur.p + 8);
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, g_ws.cursor, 64);
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)g_ws.abort_flag, 16);
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)ocur.p, 16);
+      hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grid * kOutWords);
+      switch (W) {
+        case 1: rc = launch_list<1>(prm, (int)grid, lds, s); break;
+        case 2: rc = launch_list<2>(prm, (int)grid, lds, s); break;
+        case 4: rc = launch_list<4>(prm, (int)grid, lds, s); break;
+        case 8: rc = launch_list<8>(prm, (int)grid, lds, s); break;
+        default: rc = launch_list<16>(prm, (int)grid, lds, s); break;
+      }
+      if (rc) return rc;
+      u64 hc[2] = {0, 0};
+      DIST_CHECK(hipMemcpyAsync(hc, ocur.p, 16, hipMemcpyDeviceToHost, s));
+      DIST_CHECK(hipMemcpyAsync(g_ws.host_out, g_ws.wave_out, (size_t)grid * kOutWords * sizeof(u64),
+                                hipMemcpyDeviceToHost, s));
+      DIST_CHECK(hipStreamSynchronize(s));
+      if ((hc[1] & 0xffffffffull) != 0 || hc[0] != sum) return DIST_E_DEVICE;  // slots disagree with the counts
+      u64 b_lo = 0, b_hi = 0, b_fp = 0;
+      for (int w = 0; w < grid; ++w) {
+        const u64* o = g_ws.host_out + (size_t)w * kOutWords;
+        u64 nl = b_lo + o[0];
+        b_hi += o[1] + (nl < b_lo ? 1 : 0);
+        b_lo = nl;
+        u64 f = b_fp + o[2];
+        b_fp = f >= DIST_P61 ? f - DIST_P61 : f;
+      }
+      // 3. hand the records to the sink in staging-sized pieces
+      const u64 per_stage = stage_bytes / rec_bytes;
+      for (u64 a = 0; a < hc[0]; a += per_stage) {
+        u64 c = hc[0] - a < per_stage ? hc[0] - a : per_stage;
+        DIST_CHECK(hipMemcpyAsync(stage.p, (char*)obuf.p + a * rec_bytes, c * rec_bytes, hipMemcpyDeviceToHost, s));
+        DIST_CHECK(hipStreamSynchronize(s));
+        if (sink((const int32_t*)stage.p, c, k, user)) {
+          cancelled = true;
+          break;
+        }
+      }
+      if (!cancelled) {
+        u64 nl = tot_lo + b_lo;
+        tot_hi += b_hi + (nl < tot_lo ? 1 : 0);
+        tot_lo = nl;
+        u64 f = tot_fp + b_fp;
+        tot_fp = f >= DIST_P61 ? f - DIST_P61 : f;
+      }
+      b0 = b1;
+    }
+    if (cancelled) break;
+  }
+  res.count_lo = tot_lo;
+  res.count_hi = tot_hi;
+  res.fp = cfg.fingerprint ? tot_fp : 0;
+  *out = res;
+  if (cancelled) return DIST_E_CANCELLED;
+  return res.count_hi ? DIST_E_OVERFLOW : DIST_OK;
 }

@@ -89,7 +89,10 @@ typedef struct {
                             out-neighbours: such a root is split into ranges of
                             max(1, chunk_work / d) depth-1 children that
                             different wavefronts take; 0 = auto (512) */
-  int32_t reserved;
+  int32_t min_width;     /* smallest bitmap width in words (1, 2, 4, 8, 16)
+                            used for a root; a larger value merges the small
+                            width classes of a batch into fewer launches;
+                            0 = 1 */
 } dist_config;
 
 typedef struct {
@@ -172,12 +175,23 @@ int dist_count_ex(const dist_graph* g, int k, const dist_config* cfg,
 int dist_list(const dist_graph* g, int k, dist_sink sink, void* user,
               void* hip_stream, dist_result* out);
 
-/* Count many (graph, k) pairs in one persistent launch.  gs[i], ks[i] for
- * i < n; out[i] receives the result of pair i.  Returns the first non-OK
- * status of any pair (DIST_E_OVERFLOW is reported but every result is
- * still written). */
+/* Count many (graph, k) pairs in one persistent launch per bitmap width
+ * class (at most five launches for the whole batch).  gs[i], ks[i] for
+ * i < n (the same graph may appear with several k); out[i] receives the
+ * result of pair i.  The launch sequence is captured as a HIP graph and
+ * replayed when the same batch (same graphs, ks and switches) is submitted
+ * again.  Returns the first non-OK status of any pair (DIST_E_OVERFLOW is
+ * reported but every result is still written). */
 int dist_count_batch(const dist_graph* const* gs, const int* ks, int n,
                      void* hip_stream, dist_result* out);
+
+/* dist_count_batch with switches (cfg NULL = defaults; memo, prune,
+ * fingerprint, memo sizes and min_width apply to every pair) and
+ * use_graph = 0 to launch without graph capture.  *ms (may be NULL)
+ * receives the device time of the batch. */
+int dist_count_batch_ex(const dist_graph* const* gs, const int* ks, int n,
+                        const dist_config* cfg, int use_graph, void* hip_stream,
+                        dist_result* out, double* ms);
 
 /* r_{G'}(u) of Algorithm 5 on G' = G[N+(u) u {u}] for every vertex u, the
  * value the top-level pruning test compares with k (Section V).  Values

@@ -32,6 +32,8 @@ void free_graph_arrays(dist_graph* g) {
 
 int valid_k(int k) { return k >= 1 && k <= DIST_K_MAX; }
 
+uint64_t g_graph_serial = 0;
+
 }  // namespace
 
 extern "C" {
@@ -74,6 +76,7 @@ int dist_orient(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t n
   if (cfg) g->cfg = *cfg;
   else dist_config_init(&g->cfg);
   (void)hipGetDevice(&g->device);
+  g->serial = ++g_graph_serial;
 
   const int32_t* d_rp = row_ptr;
   const int32_t* d_col = col;
@@ -150,14 +153,18 @@ int dist_list(const dist_graph* g, int k, dist_sink sink, void* user, void* hip_
   return search_list(g, k, g->cfg, sink, user, (hipStream_t)hip_stream, out);
 }
 
-int dist_count_batch(const dist_graph* const* gs, const int* ks, int n, void* hip_stream, dist_result* out) {
+int dist_count_batch_ex(const dist_graph* const* gs, const int* ks, int n, const dist_config* cfg, int use_graph,
+                        void* hip_stream, dist_result* out, double* ms) {
   if (n < 0 || (n > 0 && (!gs || !ks || !out))) return DIST_E_INVALID;
-  int first = DIST_OK;
-  for (int i = 0; i < n; ++i) {
-    int rc = dist_count(gs[i], ks[i], hip_stream, &out[i]);
-    if (rc != DIST_OK && first == DIST_OK) first = rc;
-  }
-  return first;
+  if (n == 0) return DIST_OK;
+  dist_config c;
+  if (cfg) c = *cfg;
+  else dist_config_init(&c);
+  return search_count_batch(gs, ks, n, c, use_graph, (hipStream_t)hip_stream, out, ms);
+}
+
+int dist_count_batch(const dist_graph* const* gs, const int* ks, int n, void* hip_stream, dist_result* out) {
+  return dist_count_batch_ex(gs, ks, n, nullptr, 1, hip_stream, out, nullptr);
 }
 
 int dist_root_soft_embed(const dist_graph* g, int cap, int32_t* r_out, void* hip_stream) {
@@ -210,6 +217,7 @@ int dist_stats_get(const dist_graph* g, dist_stats* out) {
 
 void dist_graph_free(dist_graph* g) {
   if (!g) return;
+  batch_forget(g);
   free_graph_arrays(g);
   delete g;
 }

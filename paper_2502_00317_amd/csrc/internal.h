@@ -31,6 +31,7 @@ struct dist_graph {
   int32_t max_outdeg = 0;
   int32_t order_bound = 0;
   double orient_ms = 0;
+  uint64_t serial = 0;       // unique per oriented graph in this process
   mutable dist_stats stats{};
 };
 
@@ -50,7 +51,12 @@ int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st);
 int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out,
                            hipStream_t s);
 
-// ---- listing (list.hip) ------------------------------------------------
+int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const dist_config& cfg, int use_graph,
+                       hipStream_t s, dist_result* out, double* ms);
+
+void batch_forget(const dist_graph* g);  // drop a cached batch plan that uses g
+
+// ---- listing -----------------------------------------------------------
 int search_list(const dist_graph* g, int k, const dist_config& cfg,
                 dist_sink sink, void* user, hipStream_t s, dist_result* out);
 

@@ -41,6 +41,8 @@
 
 #include <string.h>
 
+#include <algorithm>
+
 namespace {
 
 constexpr int kOutWords = 16;
@@ -50,6 +52,26 @@ constexpr int kMemoProbe = 4;
 // or not never changes a result).
 constexpr int kMemoMinLook = 64;
 constexpr int kMemoMinRatio = 16;
+
+// Batched counting: one entry per (graph, k) pair, and the units of a
+// launch as segments [unit_begin, next unit_begin) of consecutive roots of
+// one pair (one unit per root).
+struct BatchGraph {
+  const int32_t* dptr;
+  const int32_t* dcol;
+  const int32_t* orig;
+  const int32_t* roots;
+  const u64* gw;
+  int32_t k;
+  int32_t pad;
+};
+
+struct BatchSeg {
+  uint32_t unit_begin;
+  int32_t pair;
+  int32_t a;      // first root (index into the pair's roots array)
+  int32_t pad;
+};
 
 struct Params {
   const int32_t* dptr;
@@ -70,6 +92,10 @@ struct Params {
   unsigned long long* out_cursor;
   int* out_overflow;
   const int32_t* root_deg;   // out-degree of roots[i]
+  const BatchGraph* bg;      // batch mode (null: one graph, the fields above)
+  const BatchSeg* segs;
+  int32_t nsegs;
+  u64* pair_out;             // batch: 3 words per pair, accumulated
   const uint32_t* unit_prefix;  // units before root i of this bucket (null: one unit per root)
   uint32_t units;            // work units in this bucket
   int chunk_work;            // children per unit = max(1, chunk_work / d) for d > 64
@@ -78,6 +104,7 @@ struct Params {
   u64* memo_base;
   u64 memo_mask;
   u64 tag_base;
+  const u64* epoch;          // if set, root tags start at *epoch + tag_base
   u64 deadline;     // wall_clock64() limit; 0 = none
   int* abort_flag;
 };
@@ -211,10 +238,10 @@ template <int W, bool EMIT>
 __global__ __launch_bounds__(64) void k_search(Params p) {
   extern __shared__ __align__(16) char smem[];
   const int lane = lane_id();
-  const int k = p.k;
-  const Lds s = carve<W>(smem, k);
+  int k = p.k;  // batch mode: the largest k of the launch (sizes the stacks)
+  const Lds s = carve<W>(smem, p.k);
   // listing only: input ids of the local vertices and the sorted prefix
-  int32_t* const oid = EMIT ? (int32_t*)(smem + lds_bytes(W, k)) : nullptr;
+  int32_t* const oid = EMIT ? (int32_t*)(smem + lds_bytes(W, p.k)) : nullptr;
   int32_t* const pre = EMIT ? oid + 64 * W : nullptr;
   const int ES = W + 4;
   u64* table = p.memo_base ? p.memo_base + (u64)blockIdx.x * (p.memo_mask + 1) * ES : nullptr;
@@ -226,9 +253,17 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
   bool aborted = false;
   const u64 deadline = p.deadline ? wall_clock64() + p.deadline : 0;
   const int nbk = p.root_end - p.root_begin;
+  const u64 tag0 = p.tag_base + (p.epoch ? __hip_atomic_load(p.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull);
 
   int cur_rel = -1;       // root whose G_u is in LDS
+  int cur_pair = -1;
   bool cur_pruned = false;
+  const int32_t* Gdptr = p.dptr;
+  const int32_t* Gdcol = p.dcol;
+  const int32_t* Gorig = p.orig;
+  const int32_t* Groots = p.roots;
+  const u64* Ggw = p.gw;
+  int pair = -1;
   int32_t r = 0;
   int d = 0;
   for (;;) {
@@ -238,7 +273,23 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
     u = __shfl(u, 0);
     if (u >= p.units) break;
     int rel = (int)u, ci = 0;
-    if (p.unit_prefix) {
+    if (p.segs) {
+      int lo = 0, hi = p.nsegs - 1;  // largest segment with unit_begin <= u
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (p.segs[mid].unit_begin <= u) lo = mid; else hi = mid - 1;
+      }
+      const BatchSeg sg = p.segs[lo];
+      pair = sg.pair;
+      rel = sg.a + (int)(u - sg.unit_begin);
+      const BatchGraph bgr = p.bg[pair];
+      Gdptr = bgr.dptr;
+      Gdcol = bgr.dcol;
+      Gorig = bgr.orig;
+      Groots = bgr.roots;
+      Ggw = bgr.gw;
+      k = bgr.k;
+    } else if (p.unit_prefix) {
       int lo = 0, hi = nbk - 1;  // largest rel with prefix[rel] <= u
       while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -256,23 +307,24 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       aborted = true;
       break;
     }
-    const int ridx = p.root_begin + rel;
-    const u64 root_tag = p.tag_base + (u64)ridx;
+    const int ridx = p.segs ? rel : p.root_begin + rel;
+    const u64 root_tag = tag0 + (p.segs ? (u64)u : (u64)ridx);
     ++n_units;
 
-    if (rel != cur_rel) {
+    if (rel != cur_rel || pair != cur_pair) {
       cur_rel = rel;
-      r = p.roots[ridx];
-      const int32_t beg = p.dptr[r];
-      d = p.dptr[r + 1] - beg;  // <= 64 * W by the host's bucketing
+      cur_pair = pair;
+      r = Groots[ridx];
+      const int32_t beg = Gdptr[r];
+      d = Gdptr[r + 1] - beg;  // <= 64 * W by the host's bucketing
       ++n_builds;
       // ---- 1. G_u in LDS ------------------------------------------------------
-      arcs += build_subgraph<W>(s, p.dptr, p.dcol, p.gw, p.orig, oid, beg, d);
+      arcs += build_subgraph<W>(s, Gdptr, Gdcol, Ggw, Gorig, oid, beg, d);
 
       // ---- 2. soft-embedding bound (Algorithm 5) ---------------------------------
       if (p.soft_only) {
         int rr = soft_embed_levels<W>(s, d, k);
-        if (lane == 0) p.soft_out[p.orig[r]] = rr;
+        if (lane == 0) p.soft_out[Gorig[r]] = rr;
         __syncthreads();
         cur_pruned = true;  // nothing to search in this mode
         continue;
@@ -332,7 +384,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           for (int w = 0; w < W; ++w) c += __popcll(Pr[w]);
           if constexpr (EMIT) {
             // only at k = 2: records {root, x}
-            const int32_t rid = p.orig[r];
+            const int32_t rid = Gorig[r];
 #pragma unroll
             for (int w = 0; w < W; ++w) {
               bool in = (Pr[w] >> lane) & 1ull;
@@ -387,7 +439,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             // sorted input ids of the chosen vertices: root and stX[0..j)
             npre = j + 1;
             if (lane == 0) {
-              pre[0] = p.orig[r];
+              pre[0] = Gorig[r];
               for (int t = 0; t < j; ++t) {
                 int32_t v = oid[s.stX[t]];
                 int q = t + 1;
@@ -652,14 +704,25 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       break;
     }
     // root result: cnt, fp * g(root)
-    u64 rfp = p.fingerprint ? mulp(p.gw[r], res_fp) : 0;
+    u64 rfp = p.fingerprint ? mulp(Ggw[r], res_fp) : 0;
+    if (p.pair_out && lane == 0) {
+      u64* o = p.pair_out + 3 * (u64)pair;
+      u64 old = atomicAdd((unsigned long long*)&o[0], (unsigned long long)res_lo);
+      u64 carry_in = (old + res_lo < old) ? 1ull : 0ull;
+      if (res_hi + carry_in) atomicAdd((unsigned long long*)&o[1], (unsigned long long)(res_hi + carry_in));
+      u64 cur = o[2], seen;
+      do {
+        seen = cur;
+        cur = atomicCAS((unsigned long long*)&o[2], seen, addp(seen, rfp));
+      } while (cur != seen);
+    }
     u64 nlo = tot_lo + res_lo;
     tot_hi += res_hi + (nlo < tot_lo ? 1ull : 0ull);
     tot_lo = nlo;
     tot_fp = addp(tot_fp, rfp);
     if (p.per_root && lane == 0) {
       // several units may share a root: 128-bit add with carry, fp mod p
-      u64* o = p.per_root + 3 * (u64)p.orig[r];
+      u64* o = p.per_root + 3 * (u64)Gorig[r];
       u64 old = atomicAdd((unsigned long long*)&o[0], (unsigned long long)res_lo);
       u64 carry_in = (old + res_lo < old) ? 1ull : 0ull;
       if (res_hi + carry_in) atomicAdd((unsigned long long*)&o[1], (unsigned long long)(res_hi + carry_in));
@@ -731,7 +794,6 @@ struct Workspace {
   int* abort_flag = nullptr;
   u64* memo = nullptr;
   size_t memo_bytes = 0;
-  u64 tag_next = 1;
   u64* host_out = nullptr;  // pinned
   size_t host_out_words = 0;
   uint32_t* d_prefix = nullptr;
@@ -740,6 +802,10 @@ struct Workspace {
 };
 
 Workspace g_ws;  // one device per process in this library
+
+// Memo keys carry a root tag that is unique over the life of the process,
+// so entries left in a table by an earlier launch can never match.
+u64 g_tag_next = 1;
 
 int ws_ensure(size_t wave_words, size_t memo_bytes) {
   int dev = 0;
@@ -792,8 +858,9 @@ int occupancy_blocks(size_t lds) {
 }
 
 template <int W>
-int launch_bucket(Params prm, int grid, size_t lds, hipStream_t s) {
-  DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+int launch_bucket(Params prm, int grid, size_t lds, hipStream_t s, bool set_attr = true) {
+  if (set_attr)
+    DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((k_search<W, false>), dim3(grid), dim3(64), lds, s, prm);
   DIST_CHECK(hipGetLastError());
   return DIST_OK;
@@ -944,9 +1011,10 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     prm.abort_flag = g_ws.abort_flag;
     prm.memo_base = want_memo ? g_ws.memo : nullptr;
     prm.memo_mask = want_memo ? entries - 1 : 0;
-    prm.tag_base = g_ws.tag_next;
+    prm.tag_base = g_tag_next;
+    prm.epoch = nullptr;
     prm.deadline = deadline;
-    g_ws.tag_next += (u64)nroots + 1;
+    g_tag_next += (u64)nroots + 1;
     size_t lds = lds_bytes(buckets[b].W, base.k);
     hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grids[b] * kOutWords);
     DIST_CHECK(hipEventRecord(kb0, s));
@@ -1342,4 +1410,351 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
   *out = res;
   if (cancelled) return DIST_E_CANCELLED;
   return res.count_hi ? DIST_E_OVERFLOW : DIST_OK;
+}
+
+// ---- batched counting ----------------------------------------------------------
+// Many (graph, k) pairs in one persistent launch per bitmap width: the work
+// units of all pairs are laid end to end as segments of consecutive roots;
+// every unit adds its root's result into its pair's slot.  The launch
+// sequence of a batch is captured once as a hipGraph and replayed while the
+// same batch (same graphs, ks and switches) is submitted again.
+namespace {
+
+struct BatchPlan {
+  std::vector<const dist_graph*> gs;
+  std::vector<u64> serials;
+  u64* d_epoch = nullptr;     // bumped at the start of every run
+  u64 units_total = 0;
+  std::vector<int> ks;
+  dist_config cfg{};
+  int device = -1;
+  BatchGraph* d_bg = nullptr;
+  BatchSeg* d_segs = nullptr;
+  u64* d_pair_out = nullptr;
+  u64* h_pair_out = nullptr;  // pinned
+  unsigned* d_cursor = nullptr;
+  int* d_abort = nullptr;
+  u64* d_wave_out = nullptr;
+  u64* d_memo = nullptr;
+  std::vector<int> status;    // per pair: OK or an error found while planning
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double last_ms = 0;
+  ~BatchPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipFree(d_bg);
+    (void)hipFree(d_segs);
+    (void)hipFree(d_pair_out);
+    (void)hipFree(d_cursor);
+    (void)hipFree(d_abort);
+    (void)hipFree(d_wave_out);
+    (void)hipFree(d_memo);
+    (void)hipFree(d_epoch);
+    if (h_pair_out) (void)hipHostFree(h_pair_out);
+  }
+};
+
+__global__ void k_bump_epoch(u64* e, u64 by) { *e += by; }
+
+BatchPlan* g_plan = nullptr;
+
+bool same_cfg(const dist_config& a, const dist_config& b) { return memcmp(&a, &b, sizeof(a)) == 0; }
+
+int occupancy_any(int W, size_t lds) {
+  switch (W) {
+    case 1: return occupancy_blocks<1>(lds);
+    case 2: return occupancy_blocks<2>(lds);
+    case 4: return occupancy_blocks<4>(lds);
+    case 8: return occupancy_blocks<8>(lds);
+    default: return occupancy_blocks<16>(lds);
+  }
+}
+
+int launch_any(int W, const Params& prm, int grid, size_t lds, hipStream_t s) {
+  // attributes were set before any capture began
+  switch (W) {
+    case 1: return launch_bucket<1>(prm, grid, lds, s, false);
+    case 2: return launch_bucket<2>(prm, grid, lds, s, false);
+    case 4: return launch_bucket<4>(prm, grid, lds, s, false);
+    case 8: return launch_bucket<8>(prm, grid, lds, s, false);
+    default: return launch_bucket<16>(prm, grid, lds, s, false);
+  }
+}
+
+// Builds the device-side plan and enqueues its launches on s (captured or not).
+struct BatchLaunch {
+  int W;
+  int grid;
+  size_t lds;
+  Params prm;
+};
+
+int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, const dist_config& cfg,
+               std::vector<BatchLaunch>& launches, size_t& wave_words, size_t& memo_bytes) {
+  const int widths[5] = {16, 8, 4, 2, 1};
+  P->status.assign(n, DIST_OK);
+  std::vector<BatchGraph> bg(n);
+  std::vector<std::vector<BatchSeg>> segs(5);
+  std::vector<uint32_t> units(5, 0);
+  std::vector<int> kmax(5, 0);
+  const int min_w = cfg.min_width > 1 ? cfg.min_width : 1;
+  for (int i = 0; i < n; ++i) {
+    const dist_graph* g = gs[i];
+    const int k = ks[i];
+    bg[i] = BatchGraph{g->dptr, g->dcol, g->orig, g->roots, g->gw, k, 0};
+    if (k < 2) continue;  // k = 1 is answered on the host side
+    int32_t lo = 0, hi = g->n;
+    while (lo < hi) {
+      int32_t mid = (lo + hi) / 2;
+      if (g->root_deg[mid] >= k - 1) lo = mid + 1; else hi = mid;
+    }
+    const int32_t nroots = lo;
+    if (nroots > 0 && g->root_deg[0] > DIST_MAX_OUTDEG) {
+      P->status[i] = DIST_E_UNSUPPORTED;
+      continue;
+    }
+    int32_t a = 0;
+    while (a < nroots) {
+      int W = width_of(g->root_deg[a]);
+      if (W < min_w) W = min_w;
+      int32_t b = a;
+      while (b < nroots) {
+        int Wb = width_of(g->root_deg[b]);
+        if (Wb < min_w) Wb = min_w;
+        if (Wb != W) break;
+        ++b;
+      }
+      int slot = W == 16 ? 0 : W == 8 ? 1 : W == 4 ? 2 : W == 2 ? 3 : 4;
+      segs[slot].push_back(BatchSeg{units[slot], i, a, 0});
+      units[slot] += (uint32_t)(b - a);
+      if (k > kmax[slot]) kmax[slot] = k;
+      a = b;
+    }
+  }
+  // device arrays
+  std::vector<BatchSeg> all;
+  std::vector<size_t> seg_off(5);
+  for (int b = 0; b < 5; ++b) {
+    seg_off[b] = all.size();
+    all.insert(all.end(), segs[b].begin(), segs[b].end());
+  }
+  if (dev_alloc((void**)&P->d_bg, sizeof(BatchGraph) * (n > 0 ? n : 1))) return DIST_E_NOMEM;
+  if (dev_alloc((void**)&P->d_segs, sizeof(BatchSeg) * (all.size() + 1))) return DIST_E_NOMEM;
+  if (dev_alloc((void**)&P->d_pair_out, sizeof(u64) * 3 * ((size_t)n + 1))) return DIST_E_NOMEM;
+  if (hipHostMalloc((void**)&P->h_pair_out, sizeof(u64) * 3 * ((size_t)n + 1)) != hipSuccess) return DIST_E_NOMEM;
+  if (dev_alloc((void**)&P->d_cursor, 64 * sizeof(unsigned))) return DIST_E_NOMEM;
+  if (dev_alloc((void**)&P->d_abort, 64)) return DIST_E_NOMEM;
+  if (dev_alloc((void**)&P->d_epoch, 64)) return DIST_E_NOMEM;
+  {
+    // a private tag range for this plan; every run advances by units_total + 1
+    u64 base = g_tag_next;
+    g_tag_next += (u64)1 << 40;
+    DIST_CHECK(hipMemcpy(P->d_epoch, &base, sizeof(u64), hipMemcpyHostToDevice));
+  }
+  if (n) DIST_CHECK(hipMemcpy(P->d_bg, bg.data(), sizeof(BatchGraph) * n, hipMemcpyHostToDevice));
+  if (!all.empty()) DIST_CHECK(hipMemcpy(P->d_segs, all.data(), sizeof(BatchSeg) * all.size(), hipMemcpyHostToDevice));
+  int maxlds = 0, cus = 0, dev = 0;
+  DIST_CHECK(hipGetDevice(&dev));
+  DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  DIST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  wave_words = 0;
+  int maxgrid = 0, maxW = 1;
+  for (int b = 0; b < 5; ++b) {
+    if (units[b] == 0) continue;
+    BatchLaunch L{};
+    L.W = widths[b];
+    L.lds = lds_bytes(L.W, kmax[b]);
+    if (L.lds > (size_t)maxlds) {
+      for (auto& sg : segs[b]) P->status[sg.pair] = DIST_E_UNSUPPORTED;
+      continue;
+    }
+    int occ = occupancy_any(L.W, L.lds);
+    int64_t grid = (int64_t)occ * (cus > 0 ? cus : 256);
+    if (grid > units[b]) grid = units[b];
+    L.grid = (int)(grid < 1 ? 1 : grid);
+    Params& prm = L.prm;
+    prm = Params{};
+    prm.k = kmax[b];
+    prm.prune = cfg.prune;
+    prm.memo = cfg.memo;
+    prm.fingerprint = cfg.fingerprint;
+    prm.cursor = P->d_cursor + b;
+    prm.units = units[b];
+    prm.unit_prefix = nullptr;
+    prm.chunk_work = 1 << 30;
+    prm.bg = P->d_bg;
+    prm.segs = P->d_segs + seg_off[b];
+    prm.nsegs = (int32_t)segs[b].size();
+    prm.pair_out = P->d_pair_out;
+    prm.abort_flag = P->d_abort;
+    prm.epoch = P->d_epoch;
+    prm.tag_base = P->units_total;  // units of earlier width classes come first
+    P->units_total += units[b];
+    launches.push_back(L);
+    if (L.grid > maxgrid) maxgrid = L.grid;
+    if (L.W > maxW) maxW = L.W;
+  }
+  wave_words = (size_t)maxgrid * kOutWords;
+  memo_bytes = 0;
+  u64 entries = 0;
+  if (cfg.memo != 0 && maxgrid > 0) {
+    size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)4 << 30);
+    size_t es = (size_t)(maxW + 4) * 8;
+    entries = cfg.memo_entries > 0 ? 1 : (1 << 16);
+    if (cfg.memo_entries > 0)
+      while (entries < (u64)cfg.memo_entries) entries <<= 1;
+    else
+      while (entries > 256 && entries * es * (size_t)maxgrid > budget) entries >>= 1;
+    memo_bytes = entries * es * (size_t)maxgrid;
+  }
+  if (dev_alloc((void**)&P->d_wave_out, (wave_words ? wave_words : 1) * sizeof(u64))) return DIST_E_NOMEM;
+  if (memo_bytes && dev_alloc((void**)&P->d_memo, memo_bytes)) return DIST_E_NOMEM;
+  for (auto& L : launches) {
+    L.prm.wave_out = P->d_wave_out;
+    L.prm.memo_base = memo_bytes ? P->d_memo : nullptr;
+    L.prm.memo_mask = memo_bytes ? entries - 1 : 0;
+  }
+  return DIST_OK;
+}
+
+int enqueue_batch(BatchPlan* P, int n, const std::vector<BatchLaunch>& launches, hipStream_t s) {
+  // fresh root tags for this run: memo entries of an earlier run never match
+  hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, P->d_epoch, P->units_total + 1);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, P->d_cursor, 64);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)P->d_abort, 16);
+  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, P->d_pair_out, (u64)3 * (n > 0 ? n : 1));
+  for (const auto& L : launches) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, P->d_wave_out, (u64)L.grid * kOutWords);
+    int rc = launch_any(L.W, L.prm, L.grid, L.lds, s);
+    if (rc) return rc;
+  }
+  DIST_CHECK(hipMemcpyAsync(P->h_pair_out, P->d_pair_out, sizeof(u64) * 3 * (n > 0 ? n : 1),
+                            hipMemcpyDeviceToHost, s));
+  return DIST_OK;
+}
+
+}  // namespace
+
+int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const dist_config& cfg, int use_graph,
+                       hipStream_t s, dist_result* out, double* ms) {
+  for (int i = 0; i < n; ++i)
+    if (!gs[i] || ks[i] < 1 || ks[i] > DIST_K_MAX) return gs[i] ? DIST_E_K : DIST_E_INVALID;
+  int dev = 0;
+  DIST_CHECK(hipGetDevice(&dev));
+  if (use_graph && s == nullptr) {
+    // the legacy default stream cannot be captured: use a library stream
+    static hipStream_t own = nullptr;
+    static int own_dev = -1;
+    if (own_dev != dev) {
+      DIST_CHECK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+      own_dev = dev;
+    }
+    DIST_CHECK(hipDeviceSynchronize());
+    int rc2 = search_count_batch(gs, ks, n, cfg, use_graph, own, out, ms);
+    DIST_CHECK(hipStreamSynchronize(own));
+    return rc2;
+  }
+  bool reuse = g_plan && g_plan->device == dev && (int)g_plan->gs.size() == n && same_cfg(g_plan->cfg, cfg) &&
+               std::equal(g_plan->gs.begin(), g_plan->gs.end(), gs) && std::equal(g_plan->ks.begin(), g_plan->ks.end(), ks);
+  if (reuse)
+    for (int i = 0; i < n && reuse; ++i) reuse = g_plan->serials[i] == gs[i]->serial;
+  hipEvent_t e0, e1;
+  DIST_CHECK(hipEventCreate(&e0));
+  DIST_CHECK(hipEventCreate(&e1));
+  int rc = DIST_OK;
+  if (!reuse) {
+    delete g_plan;
+    g_plan = new BatchPlan();
+    g_plan->gs.assign(gs, gs + n);
+    for (int i = 0; i < n; ++i) g_plan->serials.push_back(gs[i]->serial);
+    g_plan->ks.assign(ks, ks + n);
+    g_plan->cfg = cfg;
+    g_plan->device = dev;
+    std::vector<BatchLaunch> launches;
+    size_t ww = 0, mb = 0;
+    rc = plan_batch(g_plan, gs, ks, n, cfg, launches, ww, mb);
+    if (rc) {
+      delete g_plan;
+      g_plan = nullptr;
+      return rc;
+    }
+    // set LDS limits outside any capture
+    for (const auto& L : launches) {
+      const void* f = nullptr;
+      switch (L.W) {
+        case 1: f = (const void*)k_search<1, false>; break;
+        case 2: f = (const void*)k_search<2, false>; break;
+        case 4: f = (const void*)k_search<4, false>; break;
+        case 8: f = (const void*)k_search<8, false>; break;
+        default: f = (const void*)k_search<16, false>; break;
+      }
+      DIST_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
+    }
+    if (use_graph) {
+      DIST_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      int erc = enqueue_batch(g_plan, n, launches, s);
+      hipGraph_t gr = nullptr;
+      hipError_t ce = hipStreamEndCapture(s, &gr);
+      if (erc || ce != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        delete g_plan;
+        g_plan = nullptr;
+        return erc ? erc : DIST_E_DEVICE;
+      }
+      g_plan->graph = gr;
+      if (hipGraphInstantiate(&g_plan->exec, gr, nullptr, nullptr, 0) != hipSuccess) {
+        delete g_plan;
+        g_plan = nullptr;
+        return DIST_E_DEVICE;
+      }
+    } else {
+      DIST_CHECK(hipEventRecord(e0, s));
+      rc = enqueue_batch(g_plan, n, launches, s);
+      DIST_CHECK(hipEventRecord(e1, s));
+      if (rc) return rc;
+    }
+  }
+  if (g_plan->exec) {
+    DIST_CHECK(hipEventRecord(e0, s));
+    DIST_CHECK(hipGraphLaunch(g_plan->exec, s));
+    DIST_CHECK(hipEventRecord(e1, s));
+  } else if (reuse) {
+    // plan without a graph: rebuild the launch list each time
+    std::vector<BatchLaunch> launches;
+    delete g_plan;
+    g_plan = nullptr;
+    return search_count_batch(gs, ks, n, cfg, use_graph, s, out, ms);
+  }
+  DIST_CHECK(hipEventSynchronize(e1));
+  float t = 0;
+  DIST_CHECK(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ms) *ms = t;
+  int first = DIST_OK;
+  for (int i = 0; i < n; ++i) {
+    dist_result r{g_plan->h_pair_out[3 * i], g_plan->h_pair_out[3 * i + 1],
+                  cfg.fingerprint ? g_plan->h_pair_out[3 * i + 2] : 0};
+    int st = g_plan->status[i];
+    if (ks[i] == 1 && st == DIST_OK) {
+      SearchLaunch L{gs[i], 1, cfg, nullptr, s};
+      dist_stats dummy{};
+      st = search_count(L, &r, &dummy);
+    }
+    out[i] = r;
+    if (st == DIST_OK && r.count_hi) st = DIST_E_OVERFLOW;
+    if (st != DIST_OK && first == DIST_OK) first = st;
+  }
+  return first;
+}
+
+void batch_forget(const dist_graph* g) {
+  if (!g_plan) return;
+  for (const dist_graph* x : g_plan->gs)
+    if (x == g) {
+      delete g_plan;
+      g_plan = nullptr;
+      return;
+    }
 }

@@ -34,7 +34,7 @@ class Config(ctypes.Structure):
     _fields_ = [("memo", ctypes.c_int32), ("prune", ctypes.c_int32),
                 ("fingerprint", ctypes.c_int32), ("memo_entries", ctypes.c_int32),
                 ("memo_bytes", ctypes.c_int64), ("deadline_ms", ctypes.c_int64),
-                ("chunk_work", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("chunk_work", ctypes.c_int32), ("min_width", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -102,6 +102,10 @@ def _load():
     lib.dist_count_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
                                      ctypes.c_int, vp, ctypes.POINTER(Result)]
     lib.dist_count_batch.restype = ctypes.c_int
+    lib.dist_count_batch_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
+                                        ctypes.c_int, ctypes.POINTER(Config), ctypes.c_int, vp,
+                                        ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_double)]
+    lib.dist_count_batch_ex.restype = ctypes.c_int
     lib.dist_root_soft_embed.argtypes = [vp, ctypes.c_int, vp, vp]
     lib.dist_root_soft_embed.restype = ctypes.c_int
     lib.dist_graph_ranks.argtypes = [vp, vp, vp]
@@ -231,13 +235,18 @@ def count(g: Graph, k: int, cfg: Config | None = None, per_root=None, stream=Non
     return res.count, int(res.fp), rc
 
 
-def count_batch(graphs, ks, stream=None):
+def count_batch(graphs, ks, cfg: Config | None = None, use_graph=True, stream=None):
+    """dist_count_batch_ex: ([(count, fp)] per pair, status, device ms)."""
     n = len(graphs)
     arr = (ctypes.c_void_p * max(n, 1))(*[g.handle for g in graphs])
     karr = (ctypes.c_int * max(n, 1))(*[int(k) for k in ks])
     out = (Result * max(n, 1))()
-    rc = _load().dist_count_batch(arr, karr, n, _stream_ptr(stream), out)
-    return [(out[i].count, int(out[i].fp)) for i in range(n)], rc
+    ms = ctypes.c_double(0)
+    rc = _load().dist_count_batch_ex(arr, karr, n, ctypes.byref(cfg) if cfg is not None else None,
+                                     1 if use_graph else 0, _stream_ptr(stream), out, ctypes.byref(ms))
+    if rc not in (OK, E_OVERFLOW):
+        _check(rc, "dist_count_batch")
+    return [(out[i].count, int(out[i].fp)) for i in range(n)], rc, ms.value
 
 
 def list_cliques(g: Graph, k: int, sink=None, stream=None):

@@ -70,7 +70,7 @@ struct BatchSeg {
   uint32_t unit_begin;
   int32_t pair;
   int32_t a;      // first root (index into the pair's roots array)
-  int32_t pad;
+  int32_t upr;    // work units per root in this segment (>= 1)
 };
 
 struct Params {
@@ -96,7 +96,6 @@ struct Params {
   const BatchSeg* segs;
   int32_t nsegs;
   u64* pair_out;             // batch: 3 words per pair, accumulated
-  const uint32_t* unit_prefix;  // units before root i of this bucket (null: one unit per root)
   uint32_t units;            // work units in this bucket
   int chunk_work;            // children per unit = max(1, chunk_work / d) for d > 64
   u64* wave_out;
@@ -109,14 +108,6 @@ struct Params {
   int* abort_flag;
 };
 
-// Children of one root handled per work unit.  Light roots are one unit;
-// a heavy root (d > 64) is cut into ranges of its depth-1 children so that
-// many waves share it (each wave rebuilds G_u in its own LDS).
-__host__ __device__ inline int chunk_of(int d, int k, int chunk_work) {
-  if (d <= 64 || k <= 3) return d > 0 ? d : 1;
-  int c = chunk_work / d;
-  return c < 1 ? 1 : (c > d ? d : c);
-}
 
 // ---- per-wave memo table (Induced Subgraph Trie nodes, counting form) --------
 // Entry: [tag][key W words][cnt_lo][cnt_hi][fp]; tag = (root tag << 8) | l.
@@ -189,6 +180,18 @@ __device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, u
   __threadfence_block();
 }
 
+// Work units per root.  A root with more than 64 out-neighbours is cut into
+// ranges of max(1, chunk_work / d) depth-1 children so that many waves share
+// it (each wave rebuilds G_u in its own LDS); lighter roots stay one unit,
+// which keeps the memo reuse between the children of a root inside one wave.
+__host__ __device__ inline int units_per_root(int d, int k, int chunk_work) {
+  if (k <= 3 || d <= 64) return 1;
+  int c = chunk_work / d;  // depth-1 children per unit
+  if (c < 1) c = 1;
+  if (c >= d) return 1;
+  return (d + c - 1) / c;
+}
+
 // ---- listing: record slots and sorted records ----------------------------------
 
 // Wave-collective: reserve cnt record slots for every lane; returns the
@@ -252,17 +255,16 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
   u64 wops = 0, bits = 0, arcs = 0;
   bool aborted = false;
   const u64 deadline = p.deadline ? wall_clock64() + p.deadline : 0;
-  const int nbk = p.root_end - p.root_begin;
   const u64 tag0 = p.tag_base + (p.epoch ? __hip_atomic_load(p.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull);
 
   int cur_rel = -1;       // root whose G_u is in LDS
   int cur_pair = -1;
   bool cur_pruned = false;
-  const int32_t* Gdptr = p.dptr;
-  const int32_t* Gdcol = p.dcol;
-  const int32_t* Gorig = p.orig;
-  const int32_t* Groots = p.roots;
-  const u64* Ggw = p.gw;
+  const int32_t* Gdptr = nullptr;
+  const int32_t* Gdcol = nullptr;
+  const int32_t* Gorig = nullptr;
+  const int32_t* Groots = nullptr;
+  const u64* Ggw = nullptr;
   int pair = -1;
   int32_t r = 0;
   int d = 0;
@@ -272,16 +274,19 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
     if (lane == 0) u = atomicAdd(p.cursor, 1u);
     u = __shfl(u, 0);
     if (u >= p.units) break;
-    int rel = (int)u, ci = 0;
-    if (p.segs) {
-      int lo = 0, hi = p.nsegs - 1;  // largest segment with unit_begin <= u
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (p.segs[mid].unit_begin <= u) lo = mid; else hi = mid - 1;
-      }
-      const BatchSeg sg = p.segs[lo];
-      pair = sg.pair;
-      rel = sg.a + (int)(u - sg.unit_begin);
+    // segment: consecutive roots of one (graph, k) pair, upr units each
+    int lo = 0, hi = p.nsegs - 1;  // largest segment with unit_begin <= u
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (p.segs[mid].unit_begin <= u) lo = mid; else hi = mid - 1;
+    }
+    const BatchSeg sg = p.segs[lo];
+    pair = sg.pair;
+    const uint32_t off = u - sg.unit_begin;
+    const int rel = sg.a + (int)(off / (uint32_t)sg.upr);
+    const int ci = (int)(off % (uint32_t)sg.upr);
+    const int upr = sg.upr;
+    {
       const BatchGraph bgr = p.bg[pair];
       Gdptr = bgr.dptr;
       Gdcol = bgr.dcol;
@@ -289,14 +294,6 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       Groots = bgr.roots;
       Ggw = bgr.gw;
       k = bgr.k;
-    } else if (p.unit_prefix) {
-      int lo = 0, hi = nbk - 1;  // largest rel with prefix[rel] <= u
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (p.unit_prefix[mid] <= u) lo = mid; else hi = mid - 1;
-      }
-      rel = lo;
-      ci = (int)(u - p.unit_prefix[rel]);
     }
     if (__hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       aborted = true;
@@ -307,8 +304,9 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       aborted = true;
       break;
     }
-    const int ridx = p.segs ? rel : p.root_begin + rel;
-    const u64 root_tag = tag0 + (p.segs ? (u64)u : (u64)ridx);
+    const int ridx = rel;
+    // one tag per root (its first unit): chunks of a root share memo entries
+    const u64 root_tag = tag0 + (u64)sg.unit_begin + (u64)(off / (uint32_t)upr) * (u64)upr;
     ++n_units;
 
     if (rel != cur_rel || pair != cur_pair) {
@@ -343,8 +341,8 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       continue;
     }
     // children of frame 0 handled by this unit: local ids [x_lo, x_hi)
-    const int ch = p.unit_prefix ? chunk_of(d, k, p.chunk_work) : d;
-    const int x_lo = ci * ch;
+    const int ch = (d + upr - 1) / upr;
+    const int x_lo = ci * ch < d ? ci * ch : d;
     const int x_hi = x_lo + ch < d ? x_lo + ch : d;
 
     // ---- 3. depth-first search over candidate bitmaps -----------------------------
@@ -796,9 +794,9 @@ struct Workspace {
   size_t memo_bytes = 0;
   u64* host_out = nullptr;  // pinned
   size_t host_out_words = 0;
-  uint32_t* d_prefix = nullptr;
-  uint32_t* h_prefix = nullptr;  // pinned
-  size_t prefix_cap = 0;
+  char* d_plan = nullptr;   // graph descriptor + segments of a single-graph launch
+  char* h_plan = nullptr;   // pinned staging for the same
+  size_t plan_cap = 0;
 };
 
 Workspace g_ws;  // one device per process in this library
@@ -837,17 +835,56 @@ int ws_ensure(size_t wave_words, size_t memo_bytes) {
   return DIST_OK;
 }
 
-int ws_prefix(size_t n) {
-  if (n <= g_ws.prefix_cap) return DIST_OK;
-  if (g_ws.d_prefix) (void)hipFree(g_ws.d_prefix);
-  if (g_ws.h_prefix) (void)hipHostFree(g_ws.h_prefix);
-  g_ws.d_prefix = nullptr;
-  g_ws.h_prefix = nullptr;
-  g_ws.prefix_cap = 0;
-  if (dev_alloc((void**)&g_ws.d_prefix, n * sizeof(uint32_t))) return DIST_E_NOMEM;
-  if (hipHostMalloc((void**)&g_ws.h_prefix, n * sizeof(uint32_t)) != hipSuccess) return DIST_E_NOMEM;
-  g_ws.prefix_cap = n;
+int width_of(int d) {
+  if (d <= 64) return 1;
+  if (d <= 128) return 2;
+  if (d <= 256) return 4;
+  if (d <= 512) return 8;
+  return 16;
+}
+
+int ws_plan(size_t bytes) {
+  if (bytes <= g_ws.plan_cap) return DIST_OK;
+  if (g_ws.d_plan) (void)hipFree(g_ws.d_plan);
+  if (g_ws.h_plan) (void)hipHostFree(g_ws.h_plan);
+  g_ws.d_plan = nullptr;
+  g_ws.h_plan = nullptr;
+  g_ws.plan_cap = 0;
+  if (dev_alloc((void**)&g_ws.d_plan, bytes)) return DIST_E_NOMEM;
+  if (hipHostMalloc((void**)&g_ws.h_plan, bytes) != hipSuccess) return DIST_E_NOMEM;
+  g_ws.plan_cap = bytes;
   return DIST_OK;
+}
+
+int wslot_of_width(int W) { return W == 16 ? 0 : W == 8 ? 1 : W == 4 ? 2 : W == 2 ? 3 : 4; }
+const int kSlotWidth[5] = {16, 8, 4, 2, 1};
+
+// Appends the work segments of pair `pair` (roots [0, nroots) of g, clique
+// size k) to the five width classes: consecutive roots with the same width
+// and the same number of units per root form one segment.
+void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, bool whole_roots, int min_w,
+                  std::vector<BatchSeg> (&segs)[5], uint64_t (&units)[5], int (&kmax)[5]) {
+  int32_t a = 0;
+  while (a < nroots) {
+    int d = g->root_deg[a];
+    int W = width_of(d);
+    if (W < min_w) W = min_w;
+    int upr = whole_roots ? 1 : units_per_root(d, k, cw);
+    int32_t b = a + 1;
+    while (b < nroots) {
+      int db = g->root_deg[b];
+      int Wb = width_of(db);
+      if (Wb < min_w) Wb = min_w;
+      int ub = whole_roots ? 1 : units_per_root(db, k, cw);
+      if (Wb != W || ub != upr) break;
+      ++b;
+    }
+    int sl = wslot_of_width(W);
+    segs[sl].push_back(BatchSeg{(uint32_t)units[sl], pair, a, upr});
+    units[sl] += (uint64_t)(b - a) * (uint64_t)upr;
+    if (k > kmax[sl]) kmax[sl] = k;
+    a = b;
+  }
 }
 
 template <int W>
@@ -866,13 +903,6 @@ int launch_bucket(Params prm, int grid, size_t lds, hipStream_t s, bool set_attr
   return DIST_OK;
 }
 
-int width_of(int d) {
-  if (d <= 64) return 1;
-  if (d <= 128) return 2;
-  if (d <= 256) return 4;
-  if (d <= 512) return 8;
-  return 16;
-}
 
 struct Bucket {
   int W;
@@ -900,37 +930,29 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   for (int i = 0; i < kOutWords; ++i) totals[i] = 0;
   if (nroots <= 0) return DIST_OK;
   if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
-  std::vector<Bucket> buckets = make_buckets(g, nroots);
+  const int cw = base.chunk_work > 0 ? base.chunk_work : 512;
+  std::vector<BatchSeg> segs[5];
+  uint64_t units64[5] = {0, 0, 0, 0, 0};
+  int kmax[5] = {0, 0, 0, 0, 0};
+  add_segments(g, 0, nroots, base.k, cw, base.soft_only != 0, 1, segs, units64, kmax);
+  std::vector<Bucket> buckets;
+  std::vector<uint32_t> units;
+  std::vector<size_t> seg_off;
+  size_t nseg_total = 0;
+  for (int sl = 0; sl < 5; ++sl) {
+    if (units64[sl] == 0) continue;
+    if (units64[sl] >= 0xffffffffull) return DIST_E_UNSUPPORTED;
+    buckets.push_back(Bucket{kSlotWidth[sl], 0, 0});
+    units.push_back((uint32_t)units64[sl]);
+    seg_off.push_back(nseg_total);
+    nseg_total += segs[sl].size();
+  }
   {
     int dev = 0, maxlds = 0;
     DIST_CHECK(hipGetDevice(&dev));
     DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     for (auto& b : buckets)
       if (lds_bytes(b.W, base.k) > (size_t)maxlds) return DIST_E_UNSUPPORTED;
-  }
-  // work units: heavy roots are cut into ranges of depth-1 children
-  const int cw = base.chunk_work > 0 ? base.chunk_work : 512;
-  std::vector<std::vector<uint32_t>> prefixes(buckets.size());
-  std::vector<uint32_t> units(buckets.size());
-  size_t max_prefix = 0;
-  for (size_t b = 0; b < buckets.size(); ++b) {
-    int32_t nb = buckets[b].end - buckets[b].begin;
-    uint64_t U = 0;
-    std::vector<uint32_t> pre(nb);
-    for (int32_t i = 0; i < nb; ++i) {
-      int dd = g->root_deg[buckets[b].begin + i];
-      pre[i] = (uint32_t)U;
-      int c = base.soft_only ? dd : chunk_of(dd, base.k, cw);
-      U += (dd <= 0 || c <= 0) ? 1ull : (uint64_t)((dd + c - 1) / c);
-    }
-    if (U >= 0xffffffffull) return DIST_E_UNSUPPORTED;
-    units[b] = (uint32_t)U;
-    if (U > (uint64_t)nb) {
-      prefixes[b].swap(pre);
-      if ((size_t)nb > max_prefix) max_prefix = nb;
-    } else {
-      units[b] = (uint32_t)nb;
-    }
   }
   // grids and memo sizing
   int maxgrid = 0;
@@ -973,8 +995,21 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   }
   int rc = ws_ensure((size_t)maxgrid * kOutWords, memo_total);
   if (rc) return rc;
-  rc = ws_prefix(max_prefix);
+  // device plan: the graph descriptor, then the segments of every class
+  const size_t plan_bytes = sizeof(BatchGraph) + sizeof(BatchSeg) * (nseg_total + 1);
+  rc = ws_plan(plan_bytes);
   if (rc) return rc;
+  {
+    BatchGraph bgh{g->dptr, g->dcol, g->orig, g->roots, g->gw, base.k, 0};
+    memcpy(g_ws.h_plan, &bgh, sizeof(bgh));
+    BatchSeg* hs = (BatchSeg*)(g_ws.h_plan + sizeof(BatchGraph));
+    size_t o = 0;
+    for (int sl = 0; sl < 5; ++sl)
+      for (const BatchSeg& x : segs[sl]) hs[o++] = x;
+    DIST_CHECK(hipMemcpyAsync(g_ws.d_plan, g_ws.h_plan, plan_bytes, hipMemcpyHostToDevice, s));
+  }
+  const BatchGraph* d_bg = (const BatchGraph*)g_ws.d_plan;
+  const BatchSeg* d_segs = (const BatchSeg*)(g_ws.d_plan + sizeof(BatchGraph));
 
   hipEvent_t e0, e1, kb0, kb1;
   DIST_CHECK(hipEventCreate(&e0));
@@ -994,27 +1029,23 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   DIST_CHECK(hipEventRecord(e0, s));
   for (size_t b = 0; b < buckets.size(); ++b) {
     Params prm = base;
-    prm.root_begin = buckets[b].begin;
-    prm.root_end = buckets[b].end;
     prm.root_deg = g->d_root_deg;
     prm.chunk_work = cw;
     prm.units = units[b];
-    prm.unit_prefix = nullptr;
-    if (!prefixes[b].empty()) {
-      size_t nbytes = prefixes[b].size() * sizeof(uint32_t);
-      memcpy(g_ws.h_prefix, prefixes[b].data(), nbytes);
-      DIST_CHECK(hipMemcpyAsync(g_ws.d_prefix, g_ws.h_prefix, nbytes, hipMemcpyHostToDevice, s));
-      prm.unit_prefix = g_ws.d_prefix;
-    }
+    prm.bg = d_bg;
+    prm.segs = d_segs + seg_off[b];
+    prm.nsegs = (int32_t)segs[wslot_of_width(buckets[b].W)].size();
+    prm.pair_out = nullptr;
     prm.cursor = g_ws.cursor + b;  // one counter per bucket (zeroed above; <= 6 buckets)
     prm.wave_out = g_ws.wave_out;
     prm.abort_flag = g_ws.abort_flag;
     prm.memo_base = want_memo ? g_ws.memo : nullptr;
     prm.memo_mask = want_memo ? entries - 1 : 0;
+    // root tags are unit indices of this launch: reserve the whole range
     prm.tag_base = g_tag_next;
     prm.epoch = nullptr;
     prm.deadline = deadline;
-    g_tag_next += (u64)nroots + 1;
+    g_tag_next += (u64)units[b] + 1;
     size_t lds = lds_bytes(buckets[b].W, base.k);
     hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grids[b] * kOutWords);
     DIST_CHECK(hipEventRecord(kb0, s));
@@ -1326,14 +1357,21 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
       if (grid < 1) grid = 1;
       rc = ws_ensure((size_t)grid * kOutWords, 0);
       if (rc) return rc;
+      rc = ws_plan(sizeof(BatchGraph) + 2 * sizeof(BatchSeg));
+      if (rc) return rc;
+      {
+        BatchGraph bgh{g->dptr, g->dcol, g->orig, g->roots, g->gw, k, 0};
+        BatchSeg sg{0u, 0, b0, 1};
+        memcpy(g_ws.h_plan, &bgh, sizeof(bgh));
+        memcpy(g_ws.h_plan + sizeof(BatchGraph), &sg, sizeof(sg));
+        DIST_CHECK(hipMemcpyAsync(g_ws.d_plan, g_ws.h_plan, sizeof(BatchGraph) + sizeof(BatchSeg),
+                                  hipMemcpyHostToDevice, s));
+      }
       Params prm{};
-      prm.dptr = g->dptr;
-      prm.dcol = g->dcol;
-      prm.gw = g->gw;
-      prm.orig = g->orig;
-      prm.roots = g->roots;
-      prm.root_begin = b0;
-      prm.root_end = b1;
+      prm.bg = (const BatchGraph*)g_ws.d_plan;
+      prm.segs = (const BatchSeg*)(g_ws.d_plan + sizeof(BatchGraph));
+      prm.nsegs = 1;
+      prm.pair_out = nullptr;
       prm.k = k;
       prm.prune = cfg.prune;
       prm.memo = 0;
@@ -1341,7 +1379,6 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
       prm.soft_only = 0;
       prm.cursor = g_ws.cursor;
       prm.root_deg = g->d_root_deg;
-      prm.unit_prefix = nullptr;
       prm.units = (uint32_t)(b1 - b0);
       prm.chunk_work = 1 << 30;
       prm.wave_out = g_ws.wave_out;
@@ -1495,10 +1532,11 @@ int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, 
   const int widths[5] = {16, 8, 4, 2, 1};
   P->status.assign(n, DIST_OK);
   std::vector<BatchGraph> bg(n);
-  std::vector<std::vector<BatchSeg>> segs(5);
-  std::vector<uint32_t> units(5, 0);
-  std::vector<int> kmax(5, 0);
+  std::vector<BatchSeg> segs[5];
+  uint64_t units64[5] = {0, 0, 0, 0, 0};
+  int kmax[5] = {0, 0, 0, 0, 0};
   const int min_w = cfg.min_width > 1 ? cfg.min_width : 1;
+  const int cw = cfg.chunk_work > 0 ? cfg.chunk_work : 512;
   for (int i = 0; i < n; ++i) {
     const dist_graph* g = gs[i];
     const int k = ks[i];
@@ -1514,23 +1552,12 @@ int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, 
       P->status[i] = DIST_E_UNSUPPORTED;
       continue;
     }
-    int32_t a = 0;
-    while (a < nroots) {
-      int W = width_of(g->root_deg[a]);
-      if (W < min_w) W = min_w;
-      int32_t b = a;
-      while (b < nroots) {
-        int Wb = width_of(g->root_deg[b]);
-        if (Wb < min_w) Wb = min_w;
-        if (Wb != W) break;
-        ++b;
-      }
-      int slot = W == 16 ? 0 : W == 8 ? 1 : W == 4 ? 2 : W == 2 ? 3 : 4;
-      segs[slot].push_back(BatchSeg{units[slot], i, a, 0});
-      units[slot] += (uint32_t)(b - a);
-      if (k > kmax[slot]) kmax[slot] = k;
-      a = b;
-    }
+    add_segments(g, i, nroots, k, cw, false, min_w, segs, units64, kmax);
+  }
+  std::vector<uint32_t> units(5, 0);
+  for (int b = 0; b < 5; ++b) {
+    if (units64[b] >= 0xffffffffull) return DIST_E_UNSUPPORTED;
+    units[b] = (uint32_t)units64[b];
   }
   // device arrays
   std::vector<BatchSeg> all;
@@ -1542,7 +1569,7 @@ int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, 
   if (dev_alloc((void**)&P->d_bg, sizeof(BatchGraph) * (n > 0 ? n : 1))) return DIST_E_NOMEM;
   if (dev_alloc((void**)&P->d_segs, sizeof(BatchSeg) * (all.size() + 1))) return DIST_E_NOMEM;
   if (dev_alloc((void**)&P->d_pair_out, sizeof(u64) * 3 * ((size_t)n + 1))) return DIST_E_NOMEM;
-  if (hipHostMalloc((void**)&P->h_pair_out, sizeof(u64) * 3 * ((size_t)n + 1)) != hipSuccess) return DIST_E_NOMEM;
+  if (hipHostMalloc((void**)&P->h_pair_out, sizeof(u64) * (3 * ((size_t)n + 1) + 1)) != hipSuccess) return DIST_E_NOMEM;
   if (dev_alloc((void**)&P->d_cursor, 64 * sizeof(unsigned))) return DIST_E_NOMEM;
   if (dev_alloc((void**)&P->d_abort, 64)) return DIST_E_NOMEM;
   if (dev_alloc((void**)&P->d_epoch, 64)) return DIST_E_NOMEM;
@@ -1581,14 +1608,18 @@ int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, 
     prm.fingerprint = cfg.fingerprint;
     prm.cursor = P->d_cursor + b;
     prm.units = units[b];
-    prm.unit_prefix = nullptr;
-    prm.chunk_work = 1 << 30;
+    prm.chunk_work = cw;
     prm.bg = P->d_bg;
     prm.segs = P->d_segs + seg_off[b];
     prm.nsegs = (int32_t)segs[b].size();
     prm.pair_out = P->d_pair_out;
     prm.abort_flag = P->d_abort;
     prm.epoch = P->d_epoch;
+    if (cfg.deadline_ms > 0) {
+      int rate_khz = 0;
+      DIST_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+      prm.deadline = (u64)cfg.deadline_ms * (u64)rate_khz;
+    }
     prm.tag_base = P->units_total;  // units of earlier width classes come first
     P->units_total += units[b];
     launches.push_back(L);
@@ -1630,6 +1661,8 @@ int enqueue_batch(BatchPlan* P, int n, const std::vector<BatchLaunch>& launches,
     if (rc) return rc;
   }
   DIST_CHECK(hipMemcpyAsync(P->h_pair_out, P->d_pair_out, sizeof(u64) * 3 * (n > 0 ? n : 1),
+                            hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipMemcpyAsync(P->h_pair_out + 3 * (size_t)(n > 0 ? n : 1), P->d_abort, sizeof(int),
                             hipMemcpyDeviceToHost, s));
   return DIST_OK;
 }
@@ -1732,7 +1765,8 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (ms) *ms = t;
-  int first = DIST_OK;
+  const bool aborted = (g_plan->h_pair_out[3 * (size_t)(n > 0 ? n : 1)] & 0xffffffffull) != 0;
+  int first = aborted ? DIST_E_CANCELLED : DIST_OK;
   for (int i = 0; i < n; ++i) {
     dist_result r{g_plan->h_pair_out[3 * i], g_plan->h_pair_out[3 * i + 1],
                   cfg.fingerprint ? g_plan->h_pair_out[3 * i + 2] : 0};

@@ -339,6 +339,26 @@ def batch_graph(spec) -> Graph:
                     name="batch#%d" % spec["i"])
 
 
+def _batch_graph_arrays(spec):
+    g = batch_graph(spec)
+    return g.row_ptr, g.col
+
+
+def batch_graphs(specs, workers: int = 0):
+    """batch_graph for every spec, in worker processes (spawned, so the
+    caller may hold a GPU context).  Each graph depends only on its spec."""
+    import multiprocessing as mp
+    import os
+    if workers <= 0:
+        workers = min(16, os.cpu_count() or 1)
+    if workers == 1 or len(specs) < 8:
+        return [batch_graph(s) for s in specs]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        arrays = pool.map(_batch_graph_arrays, specs, chunksize=8)
+    return [Graph(rp, col, name="batch#%d" % s["i"]) for (rp, col), s in zip(arrays, specs)]
+
+
 def serving_pool_specs(seed: int = 5, count: int = 64, n_lo: float = 1e4,
                        n_hi: float = 2e6):
     """Resident pool: n log-uniform in [n_lo, n_hi], exponent U[2.2, 2.8],

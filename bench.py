@@ -5,8 +5,8 @@ Workload: Chung-Lu graph, n = 1,000,000, power-law exponent 2.2, mean
 degree 20, degrees capped at 5,000, plus 200 planted 30-cliques (seed 2;
 synthetic stand-in for the paper's real networks).  One step = the whole
 hot path on the resident CSR: dist_orient (degree order) followed by
-dist_count for every k of --ks (default 5 and 7).  k = 9 is attempted once,
-outside the timed region, under a deadline and reported as finished or not.
+dist_count for every k of --ks (default 5, 7 and 9; the fingerprint is
+computed at k = 5, the other ks are exact counts).
 
 Prints one JSON line with the metric, the roofline of the dominant search
 kernel (integer ALU bound) and the CPU oracle timed on a bounded sample of
@@ -34,29 +34,54 @@ BUCKET_W = [1, 2, 4, 8, 16]
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--ks", default="5,7")
+    ap.add_argument("--ks", default="5,7,9")
     ap.add_argument("--fp-ks", default="5", help="ks whose fingerprint is computed (the rest: exact count only)")
-    ap.add_argument("--k-dnf", type=int, default=9, help="k attempted once under a deadline")
+    ap.add_argument("--k-dnf", type=int, default=0, help="a further k attempted once under a deadline")
     ap.add_argument("--dnf-deadline-ms", type=int, default=20000)
     ap.add_argument("--order", default="degree", choices=["degree", "degeneracy"])
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--cpu-stride", type=int, default=8, help="oracle sample: every s-th vertex as root")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched (4,096 graph) section")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     ap.add_argument("--out", default="")
     return ap.parse_args()
 
 
 def main():
     a = parse()
+    if a.calib_copy:
+        import torch
+        n = a.calib_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": n}))
+        return
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus 1); the per-root work "
               "would shard across GPUs as described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
     import numpy as np
+    from paper_2502_00317_amd import graphgen as gg
+
+    # inputs of the batched section are generated in worker processes before
+    # this process touches the GPU
+    batch_specs = batch_graphs = None
+    if not a.no_batched:
+        t0 = time.time()
+        batch_specs = gg.batch_specs(count=a.batch_count)
+        batch_graphs = gg.batch_graphs(batch_specs)
+        print("[bench] batched inputs: %d graphs, %d edges, %.1f s" % (
+            len(batch_graphs), sum(g.m for g in batch_graphs), time.time() - t0), file=sys.stderr, flush=True)
+
     import torch
-    from paper_2502_00317_amd import dist, graphgen as gg
+    from paper_2502_00317_amd import dist
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.init()
@@ -185,6 +210,10 @@ def main():
                "sample": "k=%d, every %d-th vertex id as root (%d roots, %d cliques, %.1f s)" % (
                    kc, a.cpu_stride, len(sample), sample_cliques, cpu_s)}
 
+    batched = None
+    if batch_graphs is not None:
+        batched = run_batched(a, dist, torch, batch_specs, batch_graphs, log)
+
     line = {
         "metric": "k-cliques/sec at k=5..9 (plain vs batched); p50/p99 query latency in serving",
         "value": value,
@@ -211,6 +240,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sampled_roots": parity,
+        "batched": batched,
         "gen_s": gen_s,
     }
     s = json.dumps(line)
@@ -218,6 +248,57 @@ def main():
     if a.out:
         with open(a.out, "w") as f:
             f.write(s + "\n")
+
+
+def run_batched(a, dist, torch, specs, graphs, log):
+    """4,096 Chung-Lu graphs (n ~ U{50..5000}, exponent ~ U[2.1, 3.0], mean
+    degree ~ U[4, 40], 0-3 planted cliques of 8..25 vertices), each with its
+    own k ~ U{3..12}: the plain path (one dist_count per pair) against the
+    batched path (dist_count_batch: one persistent launch per width class,
+    replayed from a captured HIP graph), both with fingerprints."""
+    import numpy as np
+    from paper_2502_00317_amd import autotune
+
+    ks = [s["k"] for s in specs]
+    t = time.perf_counter()
+    G = [dist.orient(g.row_ptr, g.col) for g in graphs]
+    torch.cuda.synchronize()
+    orient_s = time.perf_counter() - t
+    log("batched: oriented %d graphs in %.2f s" % (len(G), orient_s))
+    cfg = dist.config()
+    # plain: one call per pair
+    t = time.perf_counter()
+    plain = [dist.count(Gi, k, cfg=cfg)[:2] for Gi, k in zip(G, ks)]
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t
+    total = sum(c for c, _ in plain)
+    log("batched: plain loop %.2f s, %d cliques" % (plain_s, total))
+    m_total = sum(g.m for g in graphs)
+    db = autotune.TuningDB(os.path.join(ROOT, "gpurun_out", "autotune_db.json")
+                           if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    best, report = autotune.tune_batch(dist, G, ks, m_total, db=db, log=log)
+    bcfg = dist.config(**best)
+    res, rc, _ = dist.count_batch(G, ks, cfg=bcfg, use_graph=True)
+    times = []
+    for _ in range(a.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r2, rc, dev_ms = dist.count_batch(G, ks, cfg=bcfg, use_graph=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        assert r2 == res
+    batch_s = float(np.median(times))
+    same = res == plain
+    log("batched: %.3f s per batch (best %s), same as plain: %s" % (batch_s, best, same))
+    for Gi in G:
+        Gi.free()
+    return {"workload": "batched: 4,096 Chung-Lu graphs n~U{50..5000}, exponent~U[2.1,3.0], "
+                        "mean degree~U[4,40], 0-3 planted cliques of 8..25, k~U{3..12}, seed 4",
+            "pairs": len(ks), "edges": m_total, "cliques": total,
+            "value": total / batch_s, "unit": "k-cliques/s", "ms_per_batch": batch_s * 1e3,
+            "plain_ms": plain_s * 1e3, "plain_value": total / plain_s,
+            "speedup_vs_plain": plain_s / batch_s, "orient_ms": orient_s * 1e3,
+            "switches": best, "autotune": report, "same_as_plain": same, "fingerprint": True}
 
 
 if __name__ == "__main__":

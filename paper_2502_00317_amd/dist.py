@@ -244,7 +244,7 @@ def count_batch(graphs, ks, cfg: Config | None = None, use_graph=True, stream=No
     ms = ctypes.c_double(0)
     rc = _load().dist_count_batch_ex(arr, karr, n, ctypes.byref(cfg) if cfg is not None else None,
                                      1 if use_graph else 0, _stream_ptr(stream), out, ctypes.byref(ms))
-    if rc not in (OK, E_OVERFLOW):
+    if rc not in (OK, E_OVERFLOW, E_CANCELLED):
         _check(rc, "dist_count_batch")
     return [(out[i].count, int(out[i].fp)) for i in range(n)], rc, ms.value
 

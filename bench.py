@@ -46,14 +46,102 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (4,096 graph) section")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--summarize-profiles", default="", metavar="DIR",
+                    help="turn rocprofv3 CSVs under DIR into the summaries under profiles/")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     ap.add_argument("--out", default="")
     return ap.parse_args()
 
 
+KERNEL_SOURCES = ["paper_2502_00317_amd/csrc/search.hip", "paper_2502_00317_amd/csrc/device_common.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_search_cfg2_traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def summarize_profiles(d):
+    """Per-launch HBM traffic of the search kernels from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the
+    same counter reads for a 1 GiB device-to-device copy."""
+    import csv
+    import glob
+
+    def rows(sub):
+        f = glob.glob(os.path.join(d, sub, "*counter_collection.csv"))
+        return list(csv.DictReader(open(f[0])))
+
+    out = {"source_hash": kernel_source_hash(), "kernels": {}, "calibration": {}}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        cal = [float(r["Counter_Value"]) for r in rows("pmccal_" + c) if "copyBuffer" in r["Kernel_Name"]]
+        factor = (1 << 20) / cal[0]  # KiB of a 1 GiB copy / counter reading
+        out["calibration"][c] = {"copy_KiB": 1 << 20, "counter_KiB": cal[0], "factor": factor}
+        for r in rows("pmc_" + c):
+            name = r["Kernel_Name"]
+            if "k_search<" not in name:
+                continue
+            kname = "k_search<%s>" % name.split("k_search<")[1].split(",")[0]
+            e = out["kernels"].setdefault(kname, {"FETCH_SIZE": [], "WRITE_SIZE": []})
+            e[c].append(float(r["Counter_Value"]) * 1024.0 * factor)
+    for kname, e in out["kernels"].items():
+        n = max(len(e["FETCH_SIZE"]), 1)
+        e["launches"] = n
+        e["bytes_per_launch"] = (sum(e["FETCH_SIZE"]) + sum(e["WRITE_SIZE"])) / n
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    lines = ["# HBM traffic of the search kernels (rocprofv3 --pmc), plain count on the",
+             "# Chung-Lu n=1e6 workload, k = 5 (fingerprint), 7 and 9, one launch each",
+             "",
+             "Commands (repository root, one MI355X; TMPDIR=/tmp):",
+             "",
+             "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $PWD/gpurun_out/pmc_FETCH_SIZE -o run -- \\",
+             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched",
+             "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $PWD/gpurun_out/pmc_WRITE_SIZE -o run -- \\",
+             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched",
+             "    rocprofv3 --pmc FETCH_SIZE (and WRITE_SIZE) ... -- python3 $PWD/bench.py --calib-copy 1024",
+             "    python3 bench.py --summarize-profiles gpurun_out",
+             "",
+             "Calibration (1 GiB device copy): FETCH_SIZE factor %.3f, WRITE_SIZE factor %.3f." % (
+                 out["calibration"]["FETCH_SIZE"]["factor"], out["calibration"]["WRITE_SIZE"]["factor"]),
+             "Kernel source hash: %s" % out["source_hash"],
+             "",
+             "| kernel | launches (k = 5, 7, 9) | fetched GB per launch | written GB per launch |",
+             "|---|---|---|---|"]
+    for kname, e in sorted(out["kernels"].items()):
+        lines.append("| %s | %d | %s | %s |" % (kname, e["launches"],
+                     " / ".join("%.2f" % (x / 1e9) for x in e["FETCH_SIZE"]),
+                     " / ".join("%.2f" % (x / 1e9) for x in e["WRITE_SIZE"])))
+    with open(os.path.join(ROOT, "profiles", "k_search_cfg2_traffic.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps(out)[:400])
+
+
+def measured_traffic(kernel):
+    """Calibrated bytes per launch of `kernel` from the committed counter
+    summary, or None if the search kernel has changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    e = t["kernels"].get(kernel)
+    return e["bytes_per_launch"] if e else None
+
+
 def main():
     a = parse()
+    if a.summarize_profiles:
+        summarize_profiles(a.summarize_profiles)
+        return
     if a.calib_copy:
         import torch
         n = a.calib_copy << 20
@@ -166,7 +254,7 @@ def main():
     peak = PEAK_INT_LANE_OPS / 1e12
     roofline = {"bound": "alu", "kernel": "k_search<%d>" % wdom, "achieved": round(achieved, 4),
                 "peak": round(peak, 2), "unit": "Tlane-op/s", "frac": round(achieved / peak, 5),
-                "traffic": None, "avg_launch_ms": round(avg_launch_ms, 3),
+                "traffic": measured_traffic("k_search<%d>" % wdom), "avg_launch_ms": round(avg_launch_ms, 3),
                 "ops_per_launch": ops_per_launch}
 
     # ---- k attempted under a deadline (not timed) ----

@@ -186,12 +186,19 @@ int dist_count_batch(const dist_graph* const* gs, const int* ks, int n,
                      void* hip_stream, dist_result* out);
 
 /* dist_count_batch with switches (cfg NULL = defaults; memo, prune,
- * fingerprint, memo sizes and min_width apply to every pair) and
- * use_graph = 0 to launch without graph capture.  *ms (may be NULL)
- * receives the device time of the batch. */
+ * fingerprint, memo sizes, chunk_work and min_width apply to every pair),
+ * use_graph = 0 to launch without graph capture, and per-pair time budgets:
+ * pair_deadline_ms[i] > 0 (array may be NULL) stops pair i once that many
+ * milliseconds of kernel time have passed, without stopping the other
+ * pairs; pair_status[i] (array may be NULL) receives DIST_OK,
+ * DIST_E_OVERFLOW, DIST_E_CANCELLED (budget spent; out[i] is partial) or
+ * DIST_E_UNSUPPORTED.  *ms (may be NULL) receives the device time of the
+ * batch.  Batches on different streams may be issued concurrently from
+ * different host threads; each stream keeps its own workspace. */
 int dist_count_batch_ex(const dist_graph* const* gs, const int* ks, int n,
-                        const dist_config* cfg, int use_graph, void* hip_stream,
-                        dist_result* out, double* ms);
+                        const dist_config* cfg, int use_graph,
+                        const int64_t* pair_deadline_ms, void* hip_stream,
+                        dist_result* out, int* pair_status, double* ms);
 
 /* r_{G'}(u) of Algorithm 5 on G' = G[N+(u) u {u}] for every vertex u, the
  * value the top-level pruning test compares with k (Section V).  Values

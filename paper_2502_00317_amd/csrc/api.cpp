@@ -154,17 +154,19 @@ int dist_list(const dist_graph* g, int k, dist_sink sink, void* user, void* hip_
 }
 
 int dist_count_batch_ex(const dist_graph* const* gs, const int* ks, int n, const dist_config* cfg, int use_graph,
-                        void* hip_stream, dist_result* out, double* ms) {
+                        const int64_t* pair_deadline_ms, void* hip_stream, dist_result* out, int* pair_status,
+                        double* ms) {
   if (n < 0 || (n > 0 && (!gs || !ks || !out))) return DIST_E_INVALID;
   if (n == 0) return DIST_OK;
   dist_config c;
   if (cfg) c = *cfg;
   else dist_config_init(&c);
-  return search_count_batch(gs, ks, n, c, use_graph, (hipStream_t)hip_stream, out, ms);
+  return search_count_batch(gs, ks, n, c, use_graph, pair_deadline_ms, (hipStream_t)hip_stream, out, pair_status,
+                            ms);
 }
 
 int dist_count_batch(const dist_graph* const* gs, const int* ks, int n, void* hip_stream, dist_result* out) {
-  return dist_count_batch_ex(gs, ks, n, nullptr, 1, hip_stream, out, nullptr);
+  return dist_count_batch_ex(gs, ks, n, nullptr, 1, nullptr, hip_stream, out, nullptr, nullptr);
 }
 
 int dist_root_soft_embed(const dist_graph* g, int cap, int32_t* r_out, void* hip_stream) {

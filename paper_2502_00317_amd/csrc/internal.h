@@ -52,7 +52,8 @@ int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out,
                            hipStream_t s);
 
 int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const dist_config& cfg, int use_graph,
-                       hipStream_t s, dist_result* out, double* ms);
+                       const int64_t* pair_deadline_ms, hipStream_t s, dist_result* out, int* pair_status,
+                       double* ms);
 
 void batch_forget(const dist_graph* g);  // drop a cached batch plan that uses g
 

@@ -42,6 +42,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 namespace {
 
@@ -64,6 +66,7 @@ struct BatchGraph {
   const u64* gw;
   int32_t k;
   int32_t pad;
+  u64 budget;  // wall-clock ticks this pair may use from the kernel start; 0 = no limit
 };
 
 struct BatchSeg {
@@ -96,6 +99,7 @@ struct Params {
   const BatchSeg* segs;
   int32_t nsegs;
   u64* pair_out;             // batch: 3 words per pair, accumulated
+  int* pair_abort;           // batch: set for a pair that ran out of its budget
   uint32_t units;            // work units in this bucket
   int chunk_work;            // children per unit = max(1, chunk_work / d) for d > 64
   u64* wave_out;
@@ -254,7 +258,9 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
   u64 n_units = 0, n_builds = 0, n_pruned = 0, n_frames = 0, n_look = 0, n_hit = 0, n_ins = 0;
   u64 wops = 0, bits = 0, arcs = 0;
   bool aborted = false;
-  const u64 deadline = p.deadline ? wall_clock64() + p.deadline : 0;
+  const u64 t_start = wall_clock64();
+  const u64 deadline = p.deadline ? t_start + p.deadline : 0;
+  u64 pair_deadline = 0;
   const u64 tag0 = p.tag_base + (p.epoch ? __hip_atomic_load(p.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull);
 
   int cur_rel = -1;       // root whose G_u is in LDS
@@ -294,6 +300,16 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       Groots = bgr.roots;
       Ggw = bgr.gw;
       k = bgr.k;
+      pair_deadline = bgr.budget ? t_start + bgr.budget : 0;
+    }
+    if (p.pair_abort) {
+      // a pair out of budget: its remaining units are skipped
+      int ab = __hip_atomic_load(p.pair_abort + pair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!ab && pair_deadline && wall_clock64() > pair_deadline) {
+        if (lane == 0) atomicOr(p.pair_abort + pair, 1);
+        ab = 1;
+      }
+      if (ab) continue;
     }
     if (__hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       aborted = true;
@@ -362,14 +378,22 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
     u64 r_look = 0, r_hit = 0;  // this root's memo lookups and hits
     bool memo_live = table != nullptr;
     u64 res_lo = 0, res_hi = 0, res_fp = 0;
-    bool stop = false;
+    bool stop = false, unit_cancel = false;
     while (true) {
       if (mode == ENTER) {
         ++n_frames;
-        if (deadline && (n_frames & 255) == 0 && wall_clock64() > deadline) {
-          if (lane == 0) atomicOr(p.abort_flag, 1);
-          stop = true;
-          break;
+        if ((deadline || pair_deadline) && (n_frames & 255) == 0) {
+          const u64 now = wall_clock64();
+          if (deadline && now > deadline) {
+            if (lane == 0) atomicOr(p.abort_flag, 1);
+            stop = true;
+            break;
+          }
+          if (pair_deadline && now > pair_deadline && p.pair_abort) {
+            if (lane == 0) atomicOr(p.pair_abort + pair, 1);
+            unit_cancel = true;
+            break;
+          }
         }
         const int l = k - 1 - j;
         const u64* P = s.stP + j * W;
@@ -701,6 +725,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       aborted = true;
       break;
     }
+    if (unit_cancel) continue;  // the pair is reported as cancelled
     // root result: cnt, fp * g(root)
     u64 rfp = p.fingerprint ? mulp(Ggw[r], res_fp) : 0;
     if (p.pair_out && lane == 0) {
@@ -800,6 +825,7 @@ struct Workspace {
 };
 
 Workspace g_ws;  // one device per process in this library
+std::recursive_mutex g_ws_mu;  // serialises the calls that use g_ws
 
 // Memo keys carry a root tag that is unique over the life of the process,
 // so entries left in a table by an earlier launch can never match.
@@ -1110,6 +1136,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
 }  // namespace
 
 int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st) {
+  std::lock_guard<std::recursive_mutex> lock(g_ws_mu);
   const dist_graph* g = L.g;
   const int k = L.k;
   dist_result res{0, 0, 0};
@@ -1188,6 +1215,7 @@ int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st) {
 }
 
 int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out, hipStream_t s) {
+  std::lock_guard<std::recursive_mutex> lock(g_ws_mu);
   // every vertex is a root here; vertices with no out-neighbour get r = 1
   std::vector<int32_t> ones;
   Params prm{};
@@ -1257,6 +1285,7 @@ struct HostBuf {
 
 int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink sink, void* user, hipStream_t s,
                 dist_result* out) {
+  std::lock_guard<std::recursive_mutex> lock(g_ws_mu);
   dist_result res{0, 0, 0};
   dist_config cfg = cfg_in;
   *out = res;
@@ -1452,49 +1481,94 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
 // ---- batched counting ----------------------------------------------------------
 // Many (graph, k) pairs in one persistent launch per bitmap width: the work
 // units of all pairs are laid end to end as segments of consecutive roots;
-// every unit adds its root's result into its pair's slot.  The launch
-// sequence of a batch is captured once as a hipGraph and replayed while the
-// same batch (same graphs, ks and switches) is submitted again.
+// every unit adds its root's result into its pair's slot.  Each HIP stream
+// has its own batch workspace, so batches on different streams (issued from
+// different host threads) run concurrently on the device.  With use_graph
+// the launch sequence is captured as a hipGraph and replayed while the same
+// batch is submitted again on that stream; every run starts a fresh range of
+// memo root tags, so no run reuses what an earlier one stored.
 namespace {
-
-struct BatchPlan {
-  std::vector<const dist_graph*> gs;
-  std::vector<u64> serials;
-  u64* d_epoch = nullptr;     // bumped at the start of every run
-  u64 units_total = 0;
-  std::vector<int> ks;
-  dist_config cfg{};
-  int device = -1;
-  BatchGraph* d_bg = nullptr;
-  BatchSeg* d_segs = nullptr;
-  u64* d_pair_out = nullptr;
-  u64* h_pair_out = nullptr;  // pinned
-  unsigned* d_cursor = nullptr;
-  int* d_abort = nullptr;
-  u64* d_wave_out = nullptr;
-  u64* d_memo = nullptr;
-  std::vector<int> status;    // per pair: OK or an error found while planning
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  double last_ms = 0;
-  ~BatchPlan() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipFree(d_bg);
-    (void)hipFree(d_segs);
-    (void)hipFree(d_pair_out);
-    (void)hipFree(d_cursor);
-    (void)hipFree(d_abort);
-    (void)hipFree(d_wave_out);
-    (void)hipFree(d_memo);
-    (void)hipFree(d_epoch);
-    if (h_pair_out) (void)hipHostFree(h_pair_out);
-  }
-};
 
 __global__ void k_bump_epoch(u64* e, u64 by) { *e += by; }
 
-BatchPlan* g_plan = nullptr;
+__global__ void k_zero_i32(int* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+struct BatchLaunch {
+  int W;
+  int grid;
+  size_t lds;
+  Params prm;
+};
+
+template <class T>
+int grow_dev(T** p, size_t& cap, size_t need) {
+  if (need <= cap && *p) return DIST_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  cap = 0;
+  if (dev_alloc((void**)p, need * sizeof(T))) return DIST_E_NOMEM;
+  cap = need;
+  return DIST_OK;
+}
+
+struct BatchWs {
+  int device = -1;
+  BatchGraph* d_bg = nullptr;
+  size_t cap_bg = 0;
+  BatchSeg* d_segs = nullptr;
+  size_t cap_segs = 0;
+  u64* d_pair_out = nullptr;  // 3 per pair, then one word: the launch abort flag
+  size_t cap_out = 0;
+  int* d_pair_abort = nullptr;
+  size_t cap_pab = 0;
+  u64* h_out = nullptr;       // pinned: pair_out, abort word, pair abort flags
+  size_t cap_h = 0;
+  unsigned* d_cursor = nullptr;
+  int* d_abort = nullptr;
+  u64* d_epoch = nullptr;
+  u64* d_wave_out = nullptr;
+  size_t cap_wave = 0;
+  u64* d_memo = nullptr;
+  size_t cap_memo = 0;
+  // the batch held by this workspace
+  int n = 0;
+  std::vector<u64> serials;
+  std::vector<int> ks;
+  std::vector<int64_t> dls;
+  dist_config cfg{};
+  std::vector<int> status;
+  std::vector<BatchLaunch> launches;
+  u64 units_total = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    serials.clear();
+  }
+  ~BatchWs() {
+    drop_graph();
+    (void)hipFree(d_bg);
+    (void)hipFree(d_segs);
+    (void)hipFree(d_pair_out);
+    (void)hipFree(d_pair_abort);
+    (void)hipFree(d_cursor);
+    (void)hipFree(d_abort);
+    (void)hipFree(d_epoch);
+    (void)hipFree(d_wave_out);
+    (void)hipFree(d_memo);
+    if (h_out) (void)hipHostFree(h_out);
+  }
+};
+
+std::mutex g_batch_mu;
+std::map<hipStream_t, BatchWs*> g_batch;
 
 bool same_cfg(const dist_config& a, const dist_config& b) { return memcmp(&a, &b, sizeof(a)) == 0; }
 
@@ -1505,6 +1579,16 @@ int occupancy_any(int W, size_t lds) {
     case 4: return occupancy_blocks<4>(lds);
     case 8: return occupancy_blocks<8>(lds);
     default: return occupancy_blocks<16>(lds);
+  }
+}
+
+const void* kernel_of(int W) {
+  switch (W) {
+    case 1: return (const void*)k_search<1, false>;
+    case 2: return (const void*)k_search<2, false>;
+    case 4: return (const void*)k_search<4, false>;
+    case 8: return (const void*)k_search<8, false>;
+    default: return (const void*)k_search<16, false>;
   }
 }
 
@@ -1519,18 +1603,18 @@ int launch_any(int W, const Params& prm, int grid, size_t lds, hipStream_t s) {
   }
 }
 
-// Builds the device-side plan and enqueues its launches on s (captured or not).
-struct BatchLaunch {
-  int W;
-  int grid;
-  size_t lds;
-  Params prm;
-};
-
-int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, const dist_config& cfg,
-               std::vector<BatchLaunch>& launches, size_t& wave_words, size_t& memo_bytes) {
-  const int widths[5] = {16, 8, 4, 2, 1};
+// Lays out the batch in ws and uploads its descriptors (synchronous on s).
+int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int64_t* dls, int n,
+               const dist_config& cfg, hipStream_t s) {
+  P->drop_graph();
+  P->launches.clear();
   P->status.assign(n, DIST_OK);
+  P->units_total = 0;
+  int dev = 0, maxlds = 0, cus = 0, rate_khz = 0;
+  DIST_CHECK(hipGetDevice(&dev));
+  DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  DIST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  DIST_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
   std::vector<BatchGraph> bg(n);
   std::vector<BatchSeg> segs[5];
   uint64_t units64[5] = {0, 0, 0, 0, 0};
@@ -1540,7 +1624,8 @@ int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, 
   for (int i = 0; i < n; ++i) {
     const dist_graph* g = gs[i];
     const int k = ks[i];
-    bg[i] = BatchGraph{g->dptr, g->dcol, g->orig, g->roots, g->gw, k, 0};
+    u64 budget = (dls && dls[i] > 0) ? (u64)dls[i] * (u64)rate_khz : 0;
+    bg[i] = BatchGraph{g->dptr, g->dcol, g->orig, g->roots, g->gw, k, 0, budget};
     if (k < 2) continue;  // k = 1 is answered on the host side
     int32_t lo = 0, hi = g->n;
     while (lo < hi) {
@@ -1554,43 +1639,49 @@ int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, 
     }
     add_segments(g, i, nroots, k, cw, false, min_w, segs, units64, kmax);
   }
-  std::vector<uint32_t> units(5, 0);
+  std::vector<BatchSeg> all;
+  size_t seg_off[5];
   for (int b = 0; b < 5; ++b) {
     if (units64[b] >= 0xffffffffull) return DIST_E_UNSUPPORTED;
-    units[b] = (uint32_t)units64[b];
-  }
-  // device arrays
-  std::vector<BatchSeg> all;
-  std::vector<size_t> seg_off(5);
-  for (int b = 0; b < 5; ++b) {
     seg_off[b] = all.size();
     all.insert(all.end(), segs[b].begin(), segs[b].end());
   }
-  if (dev_alloc((void**)&P->d_bg, sizeof(BatchGraph) * (n > 0 ? n : 1))) return DIST_E_NOMEM;
-  if (dev_alloc((void**)&P->d_segs, sizeof(BatchSeg) * (all.size() + 1))) return DIST_E_NOMEM;
-  if (dev_alloc((void**)&P->d_pair_out, sizeof(u64) * 3 * ((size_t)n + 1))) return DIST_E_NOMEM;
-  if (hipHostMalloc((void**)&P->h_pair_out, sizeof(u64) * (3 * ((size_t)n + 1) + 1)) != hipSuccess) return DIST_E_NOMEM;
-  if (dev_alloc((void**)&P->d_cursor, 64 * sizeof(unsigned))) return DIST_E_NOMEM;
-  if (dev_alloc((void**)&P->d_abort, 64)) return DIST_E_NOMEM;
-  if (dev_alloc((void**)&P->d_epoch, 64)) return DIST_E_NOMEM;
-  {
-    // a private tag range for this plan; every run advances by units_total + 1
-    u64 base = g_tag_next;
-    g_tag_next += (u64)1 << 40;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  int rc = DIST_OK;
+  if ((rc = grow_dev(&P->d_bg, P->cap_bg, nn))) return rc;
+  if ((rc = grow_dev(&P->d_segs, P->cap_segs, all.size() + 1))) return rc;
+  if ((rc = grow_dev(&P->d_pair_out, P->cap_out, 3 * nn + 1))) return rc;
+  if ((rc = grow_dev(&P->d_pair_abort, P->cap_pab, nn))) return rc;
+  if (!P->d_cursor && dev_alloc((void**)&P->d_cursor, 64 * sizeof(unsigned))) return DIST_E_NOMEM;
+  if (!P->d_abort && dev_alloc((void**)&P->d_abort, 64)) return DIST_E_NOMEM;
+  if (!P->d_epoch) {
+    if (dev_alloc((void**)&P->d_epoch, 64)) return DIST_E_NOMEM;
+    // a private range of root tags for this workspace
+    u64 base;
+    {
+      std::lock_guard<std::recursive_mutex> lock(g_ws_mu);
+      base = g_tag_next;
+      g_tag_next += (u64)1 << 44;
+    }
     DIST_CHECK(hipMemcpy(P->d_epoch, &base, sizeof(u64), hipMemcpyHostToDevice));
   }
-  if (n) DIST_CHECK(hipMemcpy(P->d_bg, bg.data(), sizeof(BatchGraph) * n, hipMemcpyHostToDevice));
-  if (!all.empty()) DIST_CHECK(hipMemcpy(P->d_segs, all.data(), sizeof(BatchSeg) * all.size(), hipMemcpyHostToDevice));
-  int maxlds = 0, cus = 0, dev = 0;
-  DIST_CHECK(hipGetDevice(&dev));
-  DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  DIST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  wave_words = 0;
+  const size_t hneed = 3 * nn + 1 + nn;  // pair_out, abort word, pair aborts (as u64 slots)
+  if (hneed > P->cap_h) {
+    if (P->h_out) (void)hipHostFree(P->h_out);
+    P->h_out = nullptr;
+    P->cap_h = 0;
+    if (hipHostMalloc((void**)&P->h_out, hneed * sizeof(u64)) != hipSuccess) return DIST_E_NOMEM;
+    P->cap_h = hneed;
+  }
+  if (n) DIST_CHECK(hipMemcpyAsync(P->d_bg, bg.data(), sizeof(BatchGraph) * n, hipMemcpyHostToDevice, s));
+  if (!all.empty())
+    DIST_CHECK(hipMemcpyAsync(P->d_segs, all.data(), sizeof(BatchSeg) * all.size(), hipMemcpyHostToDevice, s));
+  DIST_CHECK(hipStreamSynchronize(s));  // bg and all are host locals
   int maxgrid = 0, maxW = 1;
   for (int b = 0; b < 5; ++b) {
-    if (units[b] == 0) continue;
+    if (units64[b] == 0) continue;
     BatchLaunch L{};
-    L.W = widths[b];
+    L.W = kSlotWidth[b];
     L.lds = lds_bytes(L.W, kmax[b]);
     if (L.lds > (size_t)maxlds) {
       for (auto& sg : segs[b]) P->status[sg.pair] = DIST_E_UNSUPPORTED;
@@ -1598,7 +1689,7 @@ int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, 
     }
     int occ = occupancy_any(L.W, L.lds);
     int64_t grid = (int64_t)occ * (cus > 0 ? cus : 256);
-    if (grid > units[b]) grid = units[b];
+    if (grid > (int64_t)units64[b]) grid = (int64_t)units64[b];
     L.grid = (int)(grid < 1 ? 1 : grid);
     Params& prm = L.prm;
     prm = Params{};
@@ -1607,28 +1698,25 @@ int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, 
     prm.memo = cfg.memo;
     prm.fingerprint = cfg.fingerprint;
     prm.cursor = P->d_cursor + b;
-    prm.units = units[b];
+    prm.units = (uint32_t)units64[b];
     prm.chunk_work = cw;
     prm.bg = P->d_bg;
     prm.segs = P->d_segs + seg_off[b];
     prm.nsegs = (int32_t)segs[b].size();
     prm.pair_out = P->d_pair_out;
+    prm.pair_abort = P->d_pair_abort;
     prm.abort_flag = P->d_abort;
     prm.epoch = P->d_epoch;
-    if (cfg.deadline_ms > 0) {
-      int rate_khz = 0;
-      DIST_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
-      prm.deadline = (u64)cfg.deadline_ms * (u64)rate_khz;
-    }
     prm.tag_base = P->units_total;  // units of earlier width classes come first
-    P->units_total += units[b];
-    launches.push_back(L);
+    if (cfg.deadline_ms > 0) prm.deadline = (u64)cfg.deadline_ms * (u64)rate_khz;
+    P->units_total += units64[b];
+    P->launches.push_back(L);
     if (L.grid > maxgrid) maxgrid = L.grid;
     if (L.W > maxW) maxW = L.W;
   }
-  wave_words = (size_t)maxgrid * kOutWords;
-  memo_bytes = 0;
+  if ((rc = grow_dev(&P->d_wave_out, P->cap_wave, (size_t)(maxgrid > 0 ? maxgrid : 1) * kOutWords))) return rc;
   u64 entries = 0;
+  size_t memo_bytes = 0;
   if (cfg.memo != 0 && maxgrid > 0) {
     size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)4 << 30);
     size_t es = (size_t)(maxW + 4) * 8;
@@ -1638,39 +1726,48 @@ int plan_batch(BatchPlan* P, const dist_graph* const* gs, const int* ks, int n, 
     else
       while (entries > 256 && entries * es * (size_t)maxgrid > budget) entries >>= 1;
     memo_bytes = entries * es * (size_t)maxgrid;
+    if ((rc = grow_dev((char**)&P->d_memo, P->cap_memo, memo_bytes))) return rc;
   }
-  if (dev_alloc((void**)&P->d_wave_out, (wave_words ? wave_words : 1) * sizeof(u64))) return DIST_E_NOMEM;
-  if (memo_bytes && dev_alloc((void**)&P->d_memo, memo_bytes)) return DIST_E_NOMEM;
-  for (auto& L : launches) {
+  for (auto& L : P->launches) {
     L.prm.wave_out = P->d_wave_out;
     L.prm.memo_base = memo_bytes ? P->d_memo : nullptr;
     L.prm.memo_mask = memo_bytes ? entries - 1 : 0;
+    DIST_CHECK(hipFuncSetAttribute(kernel_of(L.W), hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
   }
+  P->n = n;
+  P->ks.assign(ks, ks + n);
+  P->dls.assign(n, 0);
+  if (dls) P->dls.assign(dls, dls + n);
+  P->cfg = cfg;
+  P->serials.clear();
+  for (int i = 0; i < n; ++i) P->serials.push_back(gs[i]->serial);
   return DIST_OK;
 }
 
-int enqueue_batch(BatchPlan* P, int n, const std::vector<BatchLaunch>& launches, hipStream_t s) {
+int enqueue_batch(BatchWs* P, hipStream_t s) {
+  const int n = P->n;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
   // fresh root tags for this run: memo entries of an earlier run never match
   hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, P->d_epoch, P->units_total + 1);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, P->d_cursor, 64);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)P->d_abort, 16);
-  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, P->d_pair_out, (u64)3 * (n > 0 ? n : 1));
-  for (const auto& L : launches) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, P->d_pair_out, (u64)(3 * nn));
+  hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, P->d_pair_abort, (int)nn);
+  for (const auto& L : P->launches) {
     hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, P->d_wave_out, (u64)L.grid * kOutWords);
     int rc = launch_any(L.W, L.prm, L.grid, L.lds, s);
     if (rc) return rc;
   }
-  DIST_CHECK(hipMemcpyAsync(P->h_pair_out, P->d_pair_out, sizeof(u64) * 3 * (n > 0 ? n : 1),
-                            hipMemcpyDeviceToHost, s));
-  DIST_CHECK(hipMemcpyAsync(P->h_pair_out + 3 * (size_t)(n > 0 ? n : 1), P->d_abort, sizeof(int),
-                            hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipMemcpyAsync(P->h_out, P->d_pair_out, sizeof(u64) * 3 * nn, hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipMemcpyAsync(P->h_out + 3 * nn, P->d_abort, sizeof(int), hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipMemcpyAsync(P->h_out + 3 * nn + 1, P->d_pair_abort, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
   return DIST_OK;
 }
 
 }  // namespace
 
 int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const dist_config& cfg, int use_graph,
-                       hipStream_t s, dist_result* out, double* ms) {
+                       const int64_t* dls, hipStream_t s, dist_result* out, int* pair_status, double* ms) {
   for (int i = 0; i < n; ++i)
     if (!gs[i] || ks[i] < 1 || ks[i] > DIST_K_MAX) return gs[i] ? DIST_E_K : DIST_E_INVALID;
   int dev = 0;
@@ -1679,116 +1776,106 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
     // the legacy default stream cannot be captured: use a library stream
     static hipStream_t own = nullptr;
     static int own_dev = -1;
-    if (own_dev != dev) {
-      DIST_CHECK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
-      own_dev = dev;
+    {
+      std::lock_guard<std::mutex> lock(g_batch_mu);
+      if (own_dev != dev) {
+        DIST_CHECK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        own_dev = dev;
+      }
     }
     DIST_CHECK(hipDeviceSynchronize());
-    int rc2 = search_count_batch(gs, ks, n, cfg, use_graph, own, out, ms);
+    int rc2 = search_count_batch(gs, ks, n, cfg, use_graph, dls, own, out, pair_status, ms);
     DIST_CHECK(hipStreamSynchronize(own));
     return rc2;
   }
-  bool reuse = g_plan && g_plan->device == dev && (int)g_plan->gs.size() == n && same_cfg(g_plan->cfg, cfg) &&
-               std::equal(g_plan->gs.begin(), g_plan->gs.end(), gs) && std::equal(g_plan->ks.begin(), g_plan->ks.end(), ks);
-  if (reuse)
-    for (int i = 0; i < n && reuse; ++i) reuse = g_plan->serials[i] == gs[i]->serial;
+  BatchWs* P = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    BatchWs*& slot = g_batch[s];
+    if (slot && slot->device != dev) {
+      delete slot;
+      slot = nullptr;
+    }
+    if (!slot) {
+      slot = new BatchWs();
+      slot->device = dev;
+    }
+    P = slot;
+  }
+  bool reuse = use_graph && P->exec && P->n == n && same_cfg(P->cfg, cfg) &&
+               std::equal(P->ks.begin(), P->ks.end(), ks) && (int)P->serials.size() == n;
+  for (int i = 0; i < n && reuse; ++i) reuse = P->serials[i] == gs[i]->serial && P->dls[i] == (dls ? dls[i] : 0);
   hipEvent_t e0, e1;
   DIST_CHECK(hipEventCreate(&e0));
   DIST_CHECK(hipEventCreate(&e1));
   int rc = DIST_OK;
   if (!reuse) {
-    delete g_plan;
-    g_plan = new BatchPlan();
-    g_plan->gs.assign(gs, gs + n);
-    for (int i = 0; i < n; ++i) g_plan->serials.push_back(gs[i]->serial);
-    g_plan->ks.assign(ks, ks + n);
-    g_plan->cfg = cfg;
-    g_plan->device = dev;
-    std::vector<BatchLaunch> launches;
-    size_t ww = 0, mb = 0;
-    rc = plan_batch(g_plan, gs, ks, n, cfg, launches, ww, mb);
+    rc = plan_batch(P, gs, ks, dls, n, cfg, s);
     if (rc) {
-      delete g_plan;
-      g_plan = nullptr;
+      P->drop_graph();
       return rc;
-    }
-    // set LDS limits outside any capture
-    for (const auto& L : launches) {
-      const void* f = nullptr;
-      switch (L.W) {
-        case 1: f = (const void*)k_search<1, false>; break;
-        case 2: f = (const void*)k_search<2, false>; break;
-        case 4: f = (const void*)k_search<4, false>; break;
-        case 8: f = (const void*)k_search<8, false>; break;
-        default: f = (const void*)k_search<16, false>; break;
-      }
-      DIST_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
     }
     if (use_graph) {
       DIST_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      int erc = enqueue_batch(g_plan, n, launches, s);
+      int erc = enqueue_batch(P, s);
       hipGraph_t gr = nullptr;
       hipError_t ce = hipStreamEndCapture(s, &gr);
       if (erc || ce != hipSuccess) {
         if (gr) (void)hipGraphDestroy(gr);
-        delete g_plan;
-        g_plan = nullptr;
+        P->drop_graph();
         return erc ? erc : DIST_E_DEVICE;
       }
-      g_plan->graph = gr;
-      if (hipGraphInstantiate(&g_plan->exec, gr, nullptr, nullptr, 0) != hipSuccess) {
-        delete g_plan;
-        g_plan = nullptr;
+      P->graph = gr;
+      if (hipGraphInstantiate(&P->exec, gr, nullptr, nullptr, 0) != hipSuccess) {
+        P->drop_graph();
         return DIST_E_DEVICE;
       }
-    } else {
-      DIST_CHECK(hipEventRecord(e0, s));
-      rc = enqueue_batch(g_plan, n, launches, s);
-      DIST_CHECK(hipEventRecord(e1, s));
-      if (rc) return rc;
     }
   }
-  if (g_plan->exec) {
-    DIST_CHECK(hipEventRecord(e0, s));
-    DIST_CHECK(hipGraphLaunch(g_plan->exec, s));
-    DIST_CHECK(hipEventRecord(e1, s));
-  } else if (reuse) {
-    // plan without a graph: rebuild the launch list each time
-    std::vector<BatchLaunch> launches;
-    delete g_plan;
-    g_plan = nullptr;
-    return search_count_batch(gs, ks, n, cfg, use_graph, s, out, ms);
+  DIST_CHECK(hipEventRecord(e0, s));
+  if (P->exec) {
+    DIST_CHECK(hipGraphLaunch(P->exec, s));
+  } else {
+    rc = enqueue_batch(P, s);
+    if (rc) return rc;
   }
+  DIST_CHECK(hipEventRecord(e1, s));
   DIST_CHECK(hipEventSynchronize(e1));
   float t = 0;
   DIST_CHECK(hipEventElapsedTime(&t, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (ms) *ms = t;
-  const bool aborted = (g_plan->h_pair_out[3 * (size_t)(n > 0 ? n : 1)] & 0xffffffffull) != 0;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  const bool aborted = (P->h_out[3 * nn] & 0xffffffffull) != 0;
+  const int* pab = (const int*)(P->h_out + 3 * nn + 1);
   int first = aborted ? DIST_E_CANCELLED : DIST_OK;
   for (int i = 0; i < n; ++i) {
-    dist_result r{g_plan->h_pair_out[3 * i], g_plan->h_pair_out[3 * i + 1],
-                  cfg.fingerprint ? g_plan->h_pair_out[3 * i + 2] : 0};
-    int st = g_plan->status[i];
+    dist_result r{P->h_out[3 * i], P->h_out[3 * i + 1], cfg.fingerprint ? P->h_out[3 * i + 2] : 0};
+    int st = P->status[i];
+    if (st == DIST_OK && (aborted || pab[i])) st = DIST_E_CANCELLED;
     if (ks[i] == 1 && st == DIST_OK) {
       SearchLaunch L{gs[i], 1, cfg, nullptr, s};
       dist_stats dummy{};
       st = search_count(L, &r, &dummy);
     }
-    out[i] = r;
     if (st == DIST_OK && r.count_hi) st = DIST_E_OVERFLOW;
+    out[i] = r;
+    if (pair_status) pair_status[i] = st;
     if (st != DIST_OK && first == DIST_OK) first = st;
   }
+  if (!use_graph) P->serials.clear();  // nothing captured to replay
   return first;
 }
 
 void batch_forget(const dist_graph* g) {
-  if (!g_plan) return;
-  for (const dist_graph* x : g_plan->gs)
-    if (x == g) {
-      delete g_plan;
-      g_plan = nullptr;
-      return;
-    }
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  for (auto& kv : g_batch) {
+    BatchWs* P = kv.second;
+    for (u64 sr : P->serials)
+      if (sr == g->serial) {
+        P->drop_graph();
+        break;
+      }
+  }
 }

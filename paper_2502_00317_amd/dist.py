@@ -103,8 +103,10 @@ def _load():
                                      ctypes.c_int, vp, ctypes.POINTER(Result)]
     lib.dist_count_batch.restype = ctypes.c_int
     lib.dist_count_batch_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
-                                        ctypes.c_int, ctypes.POINTER(Config), ctypes.c_int, vp,
-                                        ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_double)]
+                                        ctypes.c_int, ctypes.POINTER(Config), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int64), vp,
+                                        ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_double)]
     lib.dist_count_batch_ex.restype = ctypes.c_int
     lib.dist_root_soft_embed.argtypes = [vp, ctypes.c_int, vp, vp]
     lib.dist_root_soft_embed.restype = ctypes.c_int
@@ -235,18 +237,28 @@ def count(g: Graph, k: int, cfg: Config | None = None, per_root=None, stream=Non
     return res.count, int(res.fp), rc
 
 
-def count_batch(graphs, ks, cfg: Config | None = None, use_graph=True, stream=None):
-    """dist_count_batch_ex: ([(count, fp)] per pair, status, device ms)."""
+def count_batch(graphs, ks, cfg: Config | None = None, use_graph=True, stream=None,
+                deadlines_ms=None, with_status=False):
+    """dist_count_batch_ex: ([(count, fp)] per pair, status, device ms), plus
+    the per-pair statuses when with_status is set."""
     n = len(graphs)
     arr = (ctypes.c_void_p * max(n, 1))(*[g.handle for g in graphs])
     karr = (ctypes.c_int * max(n, 1))(*[int(k) for k in ks])
     out = (Result * max(n, 1))()
+    st = (ctypes.c_int * max(n, 1))()
+    dl = None
+    if deadlines_ms is not None:
+        dl = (ctypes.c_int64 * max(n, 1))(*[int(x) for x in deadlines_ms])
     ms = ctypes.c_double(0)
     rc = _load().dist_count_batch_ex(arr, karr, n, ctypes.byref(cfg) if cfg is not None else None,
-                                     1 if use_graph else 0, _stream_ptr(stream), out, ctypes.byref(ms))
+                                     1 if use_graph else 0, dl, _stream_ptr(stream), out, st,
+                                     ctypes.byref(ms))
     if rc not in (OK, E_OVERFLOW, E_CANCELLED):
         _check(rc, "dist_count_batch")
-    return [(out[i].count, int(out[i].fp)) for i in range(n)], rc, ms.value
+    res = [(out[i].count, int(out[i].fp)) for i in range(n)]
+    if with_status:
+        return res, rc, ms.value, [int(st[i]) for i in range(n)]
+    return res, rc, ms.value
 
 
 def list_cliques(g: Graph, k: int, sink=None, stream=None):

@@ -344,6 +344,32 @@ def _batch_graph_arrays(spec):
     return g.row_ptr, g.col
 
 
+def spec_graph(spec) -> Graph:
+    """Chung-Lu graph of a pool / ad-hoc spec (no degree cap beyond n - 1)."""
+    return chung_lu(spec["n"], spec["gamma"], spec["dbar"], None,
+                    np.random.SeedSequence(spec["seed"]), plants=spec.get("plants", []),
+                    name="spec#%d" % spec["i"])
+
+
+def _spec_graph_arrays(spec):
+    g = spec_graph(spec)
+    return g.row_ptr, g.col
+
+
+def spec_graphs(specs, workers: int = 0):
+    """spec_graph for every spec, in spawned worker processes."""
+    import multiprocessing as mp
+    import os
+    if workers <= 0:
+        workers = min(16, os.cpu_count() or 1)
+    if workers == 1 or len(specs) < 4:
+        return [spec_graph(s) for s in specs]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        arrays = pool.map(_spec_graph_arrays, specs, chunksize=1)
+    return [Graph(rp, col, name="spec#%d" % s["i"]) for (rp, col), s in zip(arrays, specs)]
+
+
 def batch_graphs(specs, workers: int = 0):
     """batch_graph for every spec, in worker processes (spawned, so the
     caller may hold a GPU context).  Each graph depends only on its spec."""

@@ -1,0 +1,68 @@
+"""A simulated device for testing the serving logic on the CPU.
+
+Counts come from the CPU oracle (so results are exact); the time a batch
+takes is simulated as the sum of per-query costs (cost_fn) scaled to
+seconds, and a query whose cost exceeds its deadline is reported as DNF.
+Live device memory is tracked so tests can check that admission never
+over-commits it."""
+import threading
+import time
+
+
+class FakeGraph:
+    def __init__(self, row_ptr, col, nbytes):
+        self.row_ptr = row_ptr
+        self.col = col
+        self.n = len(row_ptr) - 1
+        self.nbytes = nbytes
+
+
+class FakeBackend:
+    def __init__(self, oracle, cost_fn, seconds_per_cost=1e-3, pool_bytes=0, mem_limit=None):
+        self.oracle = oracle
+        self.cost_fn = cost_fn
+        self.scale = seconds_per_cost
+        self.lock = threading.Lock()
+        self.live = pool_bytes
+        self.peak = pool_bytes
+        self.mem_limit = mem_limit
+        self.active = 0
+        self.max_active = 0
+        self.calls = []
+
+    def orient(self, row_ptr, col, slot):
+        from paper_2502_00317_amd.serve import oriented_bytes
+        b = oriented_bytes(len(row_ptr) - 1, len(col) // 2)
+        with self.lock:
+            self.live += b
+            self.peak = max(self.peak, self.live)
+            if self.mem_limit is not None:
+                assert self.live <= self.mem_limit, "device memory over-committed"
+        return FakeGraph(row_ptr, col, b)
+
+    def free(self, g):
+        with self.lock:
+            self.live -= g.nbytes
+
+    def count_batch(self, slot, graphs, ks, deadlines_ms):
+        with self.lock:
+            self.active += 1
+            self.max_active = max(self.max_active, self.active)
+            self.calls.append((slot, len(graphs), time.perf_counter()))
+        res, st = [], []
+        total = 0.0
+        for g, k, dl in zip(graphs, ks, deadlines_ms):
+            c = self.cost_fn(g, k)
+            if dl and c * self.scale * 1e3 > dl:
+                res.append((0, 0))
+                st.append("dnf")
+                total += dl / 1e3
+                continue
+            total += c * self.scale
+            cnt, fp = self.oracle.count(g.row_ptr, g.col, k, nthreads=1)
+            res.append((cnt, fp))
+            st.append("overflow" if cnt >= 1 << 64 else "ok")
+        time.sleep(total)
+        with self.lock:
+            self.active -= 1
+        return res, st, total * 1e3

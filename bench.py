@@ -46,6 +46,16 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (4,096 graph) section")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-queries", type=int, default=2000)
+    ap.add_argument("--serve-deadline-ms", type=int, default=2000)
+    ap.add_argument("--serve-express-ms", type=int, default=40,
+                    help="device budget of the express lane (0: no express lane)")
+    ap.add_argument("--serve-trace", default="", help="write per-query and per-batch serving records here")
+    ap.add_argument("--serve-bulk-slots", type=int, default=1)
+    ap.add_argument("--serve-modes", default="served,plain")
+    ap.add_argument("--serve-express-pct", type=int, default=40,
+                    help="share of the device's wavefront slots for the express lane")
     ap.add_argument("--summarize-profiles", default="", metavar="DIR",
                     help="turn rocprofv3 CSVs under DIR into the summaries under profiles/")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -167,6 +177,17 @@ def main():
         batch_graphs = gg.batch_graphs(batch_specs)
         print("[bench] batched inputs: %d graphs, %d edges, %.1f s" % (
             len(batch_graphs), sum(g.m for g in batch_graphs), time.time() - t0), file=sys.stderr, flush=True)
+    serve_inputs = None
+    if not a.no_serving:
+        t0 = time.time()
+        pool_specs = gg.serving_pool_specs()
+        queries = gg.serving_queries(count=a.serve_queries)
+        adhoc_specs = [q["adhoc"] for q in queries if "adhoc" in q]
+        graphs = gg.spec_graphs(pool_specs + adhoc_specs)
+        serve_inputs = (pool_specs, queries, graphs[:len(pool_specs)], graphs[len(pool_specs):])
+        print("[bench] serving inputs: pool %d graphs (%d edges), %d ad-hoc graphs, %.1f s" % (
+            len(pool_specs), sum(g.m for g in graphs[:len(pool_specs)]), len(adhoc_specs), time.time() - t0),
+            file=sys.stderr, flush=True)
 
     import torch
     from paper_2502_00317_amd import dist
@@ -301,6 +322,9 @@ def main():
     batched = None
     if batch_graphs is not None:
         batched = run_batched(a, dist, torch, batch_specs, batch_graphs, log)
+    serving = None
+    if serve_inputs is not None:
+        serving = run_serving(a, dist, torch, serve_inputs, log)
 
     line = {
         "metric": "k-cliques/sec at k=5..9 (plain vs batched); p50/p99 query latency in serving",
@@ -329,6 +353,7 @@ def main():
         "cpu_baseline": cpu,
         "parity_sampled_roots": parity,
         "batched": batched,
+        "serving": serving,
         "gen_s": gen_s,
     }
     s = json.dumps(line)
@@ -387,6 +412,89 @@ def run_batched(a, dist, torch, specs, graphs, log):
             "plain_ms": plain_s * 1e3, "plain_value": total / plain_s,
             "speedup_vs_plain": plain_s / batch_s, "orient_ms": orient_s * 1e3,
             "switches": best, "autotune": report, "same_as_plain": same, "fingerprint": True}
+
+
+def run_serving(a, dist, torch, inputs, log):
+    """Resident pool of 64 Chung-Lu graphs (n log-uniform in [1e4, 2e6],
+    exponent U[2.2, 2.8], mean degree U[10, 30]) plus ad-hoc uploads (10% of
+    queries, n log-uniform in [1e3, 5e4]); 2,000 (graph, k ~ U{3..12})
+    queries arriving as a Poisson stream at 200 per second, each with a
+    latency budget.  Served: continuous batching on two slots (an express
+    lane with a short device budget and a bulk lane), memory-gated admission,
+    per-query completion.  Plain: the same stream, one query at a time
+    through the per-graph call with the whole device."""
+    import numpy as np
+    from paper_2502_00317_amd.serve import DeviceBackend, Query, Server, oriented_bytes, replay, summarize
+
+    pool_specs, qspecs, pool_graphs, adhoc_graphs = inputs
+    t = time.perf_counter()
+    handles = {i: dist.orient(g.row_ptr, g.col) for i, g in enumerate(pool_graphs)}
+    torch.cuda.synchronize()
+    orient_s = time.perf_counter() - t
+    pool_bytes = sum(oriented_bytes(g.n, g.m) for g in pool_graphs)
+    mem_limit = pool_bytes + (1 << 30)
+    log("serving: pool oriented in %.2f s, %.2f GB resident" % (orient_s, pool_bytes / 1e9))
+
+    def queries():
+        qs = []
+        ai = 0
+        for i, q in enumerate(qspecs):
+            if "adhoc" in q:
+                g = adhoc_graphs[ai]
+                ai += 1
+                qs.append(Query(qid=i, k=q["k"], t_arrival=q["t"], adhoc=(g.row_ptr, g.col),
+                                deadline_ms=a.serve_deadline_ms))
+            else:
+                qs.append(Query(qid=i, k=q["k"], t_arrival=q["t"], graph=q["graph"],
+                                deadline_ms=a.serve_deadline_ms))
+        return qs
+
+    out = {"workload": "serving: pool of 64 Chung-Lu graphs n log-U[1e4,2e6], exponent U[2.2,2.8], mean degree "
+                       "U[10,30] + 10%% ad-hoc uploads n log-U[1e3,5e4]; 2,000 Poisson queries at 200/s, "
+                       "k~U{3..12}, seed 5, latency budget %d ms per query" % a.serve_deadline_ms,
+           "pool_edges": sum(g.m for g in pool_graphs), "pool_gb": pool_bytes / 1e9,
+           "mem_limit_gb": mem_limit / 1e9, "orient_pool_s": orient_s}
+    nb = max(1, a.serve_bulk_slots)
+    bulk_pct = max(1, (100 - a.serve_express_pct) // nb)
+    modes = [("served", dict(slots=1 + nb, express_ms=a.serve_express_ms), [a.serve_express_pct] + [bulk_pct] * nb,
+              [{"budget_from_pair_start": 1}] + [{}] * nb),
+             ("plain", dict(slots=1, plain=True), [100], [{}])]
+    modes = [m for m in modes if m[0] in a.serve_modes.split(",")]
+    ans = {}
+    for name, kw, pcts, scfg in modes:
+        be = DeviceBackend(slots=kw["slots"], grid_pcts=pcts, slot_cfgs=scfg)
+        srv = Server(be, handles, mem_limit=mem_limit, pool_bytes=pool_bytes, **kw)
+        qs = queries()
+        srv.start()
+        replay(srv, qs, log=log)
+        wall = srv.now()
+        srv.stop()
+        summ = summarize(qs, wall)
+        sizes = [b[1] for b in srv.batches]
+        summ.update({"slots": kw["slots"], "grid_pcts": pcts, "batches": len(srv.batches),
+                     "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
+                     "max_batch": max(sizes) if sizes else 0, "peak_mem_gb": srv.peak_mem / 1e9,
+                     "error_msgs": srv.errors[:3]})
+        if name == "served":
+            summ.update({"express_ms": srv.express_ms, "moved_to_bulk": srv.demoted,
+                         "routed_to_bulk": srv.routed_bulk, "heavy_keys": len(srv.heavy)})
+        ans[name] = {(q.qid): (q.count, q.fp) for q in qs if q.status in ("ok", "overflow")}
+        if a.serve_trace:
+            with open(a.serve_trace + "." + name + ".json", "w") as f:
+                json.dump({"batches": srv.batches,
+                           "queries": [[q.qid, q.graph, q.k, q.lane, q.moves, q.status, q.t_arrival, q.t_start,
+                                        q.t_done, q.slot, q.batch_size] for q in qs]}, f)
+        log("serving[%s]: p50 %.1f ms p99 %.1f ms, %d/%d completed, %d DNF, %.3g cliques/s" % (
+            name, summ["p50_ms"], summ["p99_ms"], summ["completed"], summ["queries"], summ["dnf"],
+            summ["cliques_per_s"]))
+        out[name] = summ
+    if "served" in ans and "plain" in ans:
+        both = set(ans["served"]) & set(ans["plain"])
+        out["same_results_where_both_completed"] = all(ans["served"][i] == ans["plain"][i] for i in both)
+        out["compared"] = len(both)
+    for h in handles.values():
+        h.free()
+    return out
 
 
 if __name__ == "__main__":

@@ -89,6 +89,12 @@ typedef struct {
                             out-neighbours: such a root is split into ranges of
                             max(1, chunk_work / d) depth-1 children that
                             different wavefronts take; 0 = auto (512) */
+  int32_t grid_pct;      /* batches: percent of the full persistent grid a
+                            launch may use (so that batches of several streams
+                            share the device); 0 = 100 */
+  int32_t budget_from_pair_start; /* batches: 1 = a pair's deadline runs from
+                            the moment its first work unit starts on the
+                            device; 0 (default) = from the batch start */
   int32_t min_width;     /* smallest bitmap width in words (1, 2, 4, 8, 16)
                             used for a root; a larger value merges the small
                             width classes of a batch into fewer launches;
@@ -189,8 +195,8 @@ int dist_count_batch(const dist_graph* const* gs, const int* ks, int n,
  * fingerprint, memo sizes, chunk_work and min_width apply to every pair),
  * use_graph = 0 to launch without graph capture, and per-pair time budgets:
  * pair_deadline_ms[i] > 0 (array may be NULL) stops pair i once that many
- * milliseconds of kernel time have passed, without stopping the other
- * pairs; pair_status[i] (array may be NULL) receives DIST_OK,
+ * milliseconds have passed since the batch started on the device, without
+ * stopping the other pairs; pair_status[i] (array may be NULL) receives DIST_OK,
  * DIST_E_OVERFLOW, DIST_E_CANCELLED (budget spent; out[i] is partial) or
  * DIST_E_UNSUPPORTED.  *ms (may be NULL) receives the device time of the
  * batch.  Batches on different streams may be issued concurrently from
@@ -199,6 +205,35 @@ int dist_count_batch_ex(const dist_graph* const* gs, const int* ks, int n,
                         const dist_config* cfg, int use_graph,
                         const int64_t* pair_deadline_ms, void* hip_stream,
                         dist_result* out, int* pair_status, double* ms);
+
+/* Called from the thread of dist_count_batch_stream as soon as pair `pair`
+ * is finished on the device (or cut off by its budget), while the rest of
+ * the batch may still run.  res and status as in dist_count_batch_ex;
+ * device_ms: time from the pair's first work unit starting to its last one
+ * ending (the pair's service time), or -1 when the pair is reported only at
+ * the end of the batch. */
+typedef void (*dist_pair_done)(int pair, const dist_result* res, int status,
+                               double device_ms, void* user);
+
+/* dist_count_batch_ex without graph capture that reports every pair through
+ * on_done as it completes.  Pairs are scheduled in ascending order of
+ * pair_cost[i] (array may be NULL: dist_estimate_cost is used), so light
+ * queries of a mixed batch finish early; with budgets from the batch start
+ * (cfg->budget_from_pair_start = 0), pairs whose costs differ by more than
+ * two decades go to separate launches, cheapest first.  Returns when the
+ * whole batch is done; out and pair_status are filled as in
+ * dist_count_batch_ex. */
+int dist_count_batch_stream(const dist_graph* const* gs, const int* ks, int n,
+                            const dist_config* cfg,
+                            const int64_t* pair_deadline_ms,
+                            const double* pair_cost, void* hip_stream,
+                            dist_result* out, int* pair_status,
+                            dist_pair_done on_done, void* user);
+
+/* Upper bound on the search of (g, k): the sum over roots u of C(d+(u), k-1),
+ * the number of (k-1)-subsets of each out-neighbourhood.  Used to order and
+ * route queries; never changes a result. */
+int dist_estimate_cost(const dist_graph* g, int k, double* out);
 
 /* r_{G'}(u) of Algorithm 5 on G' = G[N+(u) u {u}] for every vertex u, the
  * value the top-level pruning test compares with k (Section V).  Values
@@ -214,9 +249,19 @@ int dist_graph_ranks(const dist_graph* g, int32_t* r_out, void* hip_stream);
 int dist_graph_info_get(const dist_graph* g, dist_graph_info* out);
 int dist_stats_get(const dist_graph* g, dist_stats* out);
 
+/* Releases g (NULL is ignored).  No call using g may still be running on
+ * any stream: its memory is reused at once by later allocations. */
 void dist_graph_free(dist_graph* g);
 
 const char* dist_strerror(int status);
+
+/* Memory.  The library keeps the device and pinned host blocks it frees
+ * (graphs, workspaces, staging) in a per-device cache and reuses them, so
+ * that no free waits for work that other streams have in flight.
+ * dist_mem_cached reports the bytes held in the cache; dist_mem_trim returns
+ * them to the runtime (this waits for the device). */
+int dist_mem_cached(int64_t* device_bytes, int64_t* host_bytes);
+int dist_mem_trim(void);
 
 #ifdef __cplusplus
 }

@@ -19,13 +19,13 @@ bool is_device_ptr(const void* p) {
 }
 
 void free_graph_arrays(dist_graph* g) {
-  (void)hipFree(g->rank);
-  (void)hipFree(g->orig);
-  (void)hipFree(g->dptr);
-  (void)hipFree(g->dcol);
-  (void)hipFree(g->gw);
-  (void)hipFree(g->roots);
-  (void)hipFree(g->d_root_deg);
+  dev_free(g->rank);
+  dev_free(g->orig);
+  dev_free(g->dptr);
+  dev_free(g->dcol);
+  dev_free(g->gw);
+  dev_free(g->roots);
+  dev_free(g->d_root_deg);
   g->rank = g->orig = g->dptr = g->dcol = g->roots = g->d_root_deg = nullptr;
   g->gw = nullptr;
 }
@@ -98,8 +98,8 @@ int dist_orient(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t n
   }
   if (!rc) rc = orient_build(d_rp, d_col, n, nnz, order_mode, s, g);
   if (own_rp || own_col) (void)hipStreamSynchronize(s);
-  (void)hipFree(own_rp);
-  (void)hipFree(own_col);
+  dev_free(own_rp);
+  dev_free(own_col);
   if (rc) {
     free_graph_arrays(g);
     delete g;
@@ -134,11 +134,10 @@ int dist_count_ex(const dist_graph* g, int k, const dist_config* cfg, uint64_t* 
   int rc = search_count(L, out, &st);
   g->stats = st;
   if (host_pr) {
-    if (hipMemcpyAsync(per_root, own, sizeof(u64) * 3 * (size_t)g->n, hipMemcpyDeviceToHost, L.stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(L.stream) != hipSuccess)
+    if (hipMemcpyAsync(per_root, own, sizeof(u64) * 3 * (size_t)g->n, hipMemcpyDeviceToHost, L.stream) != hipSuccess)
       rc = rc ? rc : DIST_E_DEVICE;
-    (void)hipFree(own);
+    if (hipStreamSynchronize(L.stream) != hipSuccess) rc = rc ? rc : DIST_E_DEVICE;
+    dev_free(own);  // reused at once: only after the stream has finished
   }
   return rc;
 }
@@ -165,6 +164,25 @@ int dist_count_batch_ex(const dist_graph* const* gs, const int* ks, int n, const
                             ms);
 }
 
+int dist_count_batch_stream(const dist_graph* const* gs, const int* ks, int n, const dist_config* cfg,
+                            const int64_t* pair_deadline_ms, const double* pair_cost, void* hip_stream,
+                            dist_result* out, int* pair_status, dist_pair_done on_done, void* user) {
+  if (n < 0 || (n > 0 && (!gs || !ks || !out || !on_done))) return DIST_E_INVALID;
+  if (n == 0) return DIST_OK;
+  dist_config c;
+  if (cfg) c = *cfg;
+  else dist_config_init(&c);
+  return search_count_batch(gs, ks, n, c, 0, pair_deadline_ms, (hipStream_t)hip_stream, out, pair_status, nullptr,
+                            on_done, user, pair_cost);
+}
+
+int dist_estimate_cost(const dist_graph* g, int k, double* out) {
+  if (!g || !out) return DIST_E_INVALID;
+  if (k < 1 || k > DIST_K_MAX) return DIST_E_K;
+  *out = estimate_cost(g, k);
+  return DIST_OK;
+}
+
 int dist_count_batch(const dist_graph* const* gs, const int* ks, int n, void* hip_stream, dist_result* out) {
   return dist_count_batch_ex(gs, ks, n, nullptr, 1, nullptr, hip_stream, out, nullptr, nullptr);
 }
@@ -182,10 +200,10 @@ int dist_root_soft_embed(const dist_graph* g, int cap, int32_t* r_out, void* hip
   }
   int rc = search_root_soft_embed(g, cap, d, s);
   if (host) {
-    if (!rc && (hipMemcpyAsync(r_out, own, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess))
+    if (!rc && hipMemcpyAsync(r_out, own, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToHost, s) != hipSuccess)
       rc = DIST_E_DEVICE;
-    (void)hipFree(own);
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = DIST_E_DEVICE;
+    dev_free(own);  // reused at once: only after the stream has finished
   }
   return rc;
 }

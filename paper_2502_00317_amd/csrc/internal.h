@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 #include "../../include/dist.h"
@@ -28,6 +29,7 @@ struct dist_graph {
   int32_t* roots = nullptr;  // all ranks sorted by out-degree descending (ties: rank)
   std::vector<int32_t> root_deg;  // host: out-degree of roots[i], non-increasing
   int32_t* d_root_deg = nullptr;  // the same on the device
+  std::vector<std::pair<int32_t, int64_t>> deg_hist;  // (out-degree, roots) runs of root_deg
   int32_t max_outdeg = 0;
   int32_t order_bound = 0;
   double orient_ms = 0;
@@ -53,7 +55,11 @@ int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out,
 
 int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const dist_config& cfg, int use_graph,
                        const int64_t* pair_deadline_ms, hipStream_t s, dist_result* out, int* pair_status,
-                       double* ms);
+                       double* ms, dist_pair_done on_done = nullptr, void* user = nullptr,
+                       const double* pair_cost = nullptr);
+
+// Upper bound on the search size of (g, k): sum over roots of C(d+, k - 1).
+double estimate_cost(const dist_graph* g, int k);
 
 void batch_forget(const dist_graph* g);  // drop a cached batch plan that uses g
 
@@ -61,8 +67,11 @@ void batch_forget(const dist_graph* g);  // drop a cached batch plan that uses g
 int search_list(const dist_graph* g, int k, const dist_config& cfg,
                 dist_sink sink, void* user, hipStream_t s, dist_result* out);
 
-// ---- small device helpers used by several files -------------------------
-int dev_alloc(void** p, size_t bytes);
+// ---- memory: block cache (frees never wait for the device) ---------------
+int dev_alloc(void** p, size_t bytes);   // device memory of the current device
+void dev_free(void* p);                  // any block from dev_alloc or pinned_alloc
+int pinned_alloc(void** p, size_t bytes, unsigned flags = hipHostMallocDefault);
+void pinned_free(void* p);
 #define DIST_CHECK(call)                         \
   do {                                           \
     hipError_t e_ = (call);                      \

@@ -464,15 +464,20 @@ int bits_for(uint32_t maxkey) {
   return b;
 }
 
+// Freed blocks are reused at once, so scratch is released only after the
+// stream's work (also on an error path) has finished.
 struct Scratch {
+  hipStream_t s;
   std::vector<void*> ptrs;
+  explicit Scratch(hipStream_t st) : s(st) {}
   ~Scratch() {
-    for (void* p : ptrs) (void)hipFree(p);
+    if (!ptrs.empty()) (void)hipStreamSynchronize(s);
+    for (void* p : ptrs) dev_free(p);
   }
   template <class T>
   int get(T** p, size_t count) {
     void* q = nullptr;
-    if (hipMalloc(&q, count * sizeof(T) + 16) != hipSuccess) return DIST_E_NOMEM;
+    if (dev_alloc(&q, count * sizeof(T) + 16) != DIST_OK) return DIST_E_NOMEM;
     ptrs.push_back(q);
     *p = (T*)q;
     return DIST_OK;
@@ -487,25 +492,20 @@ struct Scratch {
 
 }  // namespace
 
-int dev_alloc(void** p, size_t bytes) {
-  *p = nullptr;
-  if (hipMalloc(p, bytes ? bytes : 16) != hipSuccess) {
-    *p = nullptr;
-    return DIST_E_NOMEM;
-  }
-  return DIST_OK;
-}
-
 int orient_build(const int32_t* rp, const int32_t* col, int32_t n, int64_t nnz, int order_mode,
                  hipStream_t s, dist_graph* g) {
-  Scratch sc;
+  Scratch sc(s);
   const int T = 256;
   int32_t* hflags = nullptr;  // pinned host words for small readbacks
-  if (hipHostMalloc((void**)&hflags, 4 * sizeof(int32_t)) != hipSuccess) return DIST_E_NOMEM;
+  if (pinned_alloc((void**)&hflags, 4 * sizeof(int32_t)) != DIST_OK) return DIST_E_NOMEM;
   struct HostFree {
     int32_t* p;
-    ~HostFree() { (void)hipHostFree(p); }
-  } hf{hflags};
+    hipStream_t s;
+    ~HostFree() {
+      (void)hipStreamSynchronize(s);
+      pinned_free(p);
+    }
+  } hf{hflags, s};
   int32_t* dflag;
   TRY(sc.get(&dflag, 4));
 
@@ -650,8 +650,17 @@ int orient_build(const int32_t* rp, const int32_t* col, int32_t n, int64_t nnz, 
   DIST_CHECK(hipGetLastError());
   g->root_deg.resize(n);
   for (int32_t i = 0; i < n; ++i) g->root_deg[i] = g->max_outdeg - (int32_t)hk[i];
+  g->deg_hist.clear();
+  for (int32_t i = 0; i < n; ++i) {
+    if (g->deg_hist.empty() || g->deg_hist.back().first != g->root_deg[i])
+      g->deg_hist.push_back({g->root_deg[i], 0});
+    g->deg_hist.back().second += 1;
+  }
   TRY(dev_alloc((void**)&g->d_root_deg, sizeof(int32_t) * nn));
-  if (n) DIST_CHECK(hipMemcpy(g->d_root_deg, g->root_deg.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  if (n) {
+    DIST_CHECK(hipMemcpyAsync(g->d_root_deg, g->root_deg.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    DIST_CHECK(hipStreamSynchronize(s));
+  }
   float ms = 0;
   DIST_CHECK(hipEventElapsedTime(&ms, e0, e1));
   g->orient_ms = ms;

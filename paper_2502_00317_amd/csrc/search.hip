@@ -42,8 +42,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cmath>
 #include <map>
 #include <mutex>
+#include <thread>
 
 namespace {
 
@@ -65,15 +68,16 @@ struct BatchGraph {
   const int32_t* roots;
   const u64* gw;
   int32_t k;
-  int32_t pad;
-  u64 budget;  // wall-clock ticks this pair may use from the kernel start; 0 = no limit
+  int32_t own_clock;  // 1: the budget runs from the pair's first unit; 0: from the batch's
+  u64 budget;         // wall-clock ticks this pair may use; 0 = no limit
 };
 
 struct BatchSeg {
   uint32_t unit_begin;
   int32_t pair;
-  int32_t a;      // first root (index into the pair's roots array)
-  int32_t upr;    // work units per root in this segment (>= 1)
+  int32_t a;          // first root (index into the pair's roots array)
+  int32_t upr;        // work units per root in this segment (>= 1)
+  uint32_t pair_end;  // end of the pair's units in this launch (they are contiguous)
 };
 
 struct Params {
@@ -100,6 +104,9 @@ struct Params {
   int32_t nsegs;
   u64* pair_out;             // batch: 3 words per pair, accumulated
   int* pair_abort;           // batch: set for a pair that ran out of its budget
+  unsigned* pair_rem;        // batch: units of each pair not finished yet
+  unsigned long long* pair_t0;  // batch: [0] first unit of the batch, [1 + i] first unit of pair i
+  u64* pair_host;            // batch: host-mapped {flag, lo, hi, fp, t_first, t_last} per pair
   uint32_t units;            // work units in this bucket
   int chunk_work;            // children per unit = max(1, chunk_work / d) for d > 64
   u64* wave_out;
@@ -239,6 +246,55 @@ __device__ __forceinline__ void write_record(int32_t* dst, const int32_t* pre, i
   }
 }
 
+// Every unit of a batch ends here (searched, skipped or cut off); n units
+// at once when a wave skips the rest of a cut-off pair.  The last unit of a
+// pair publishes the pair's result to host-mapped memory, so the host can
+// complete that query while the rest of the batch still runs.
+__device__ void finish_units(const Params& p, int pair, uint32_t n) {
+  if (!p.pair_rem || pair < 0) return;
+  if (lane_id() == 0) {
+    __threadfence();  // this unit's additions to pair_out come first
+    unsigned left = atomicSub(p.pair_rem + pair, n);
+    if (left == n) {
+      __threadfence();
+      const u64* o = p.pair_out + 3 * (u64)pair;
+      u64 lo = __hip_atomic_load(o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      u64 hi = __hip_atomic_load(o + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      u64 fp = __hip_atomic_load(o + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int ab = __hip_atomic_load(p.pair_abort + pair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      u64 t1 = __hip_atomic_load(p.pair_t0 + 1 + pair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      u64* h = p.pair_host + 6 * (u64)pair;
+      __hip_atomic_store(h + 1, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(h + 2, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(h + 3, fp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(h + 4, t1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(h + 5, (u64)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __threadfence_system();
+      __hip_atomic_store(h, ab ? 2ull : 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
+
+// A cut-off pair: hand out none of its remaining units in this launch (its
+// units are contiguous up to pair_end) and count them as finished.
+__device__ uint32_t skip_rest(const Params& p, uint32_t pair_end) {
+  uint32_t skipped = 0;
+  if (lane_id() == 0) {
+    uint32_t old = atomicMax(p.cursor, pair_end);
+    skipped = old < pair_end ? pair_end - old : 0u;
+  }
+  return __shfl(skipped, 0);
+}
+
+// The first wall-clock time stored in *slot (set by whichever wave gets
+// there first).
+__device__ u64 first_time(unsigned long long* slot, u64 now) {
+  u64 t = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (t) return t;
+  u64 old = atomicCAS(slot, 0ull, (unsigned long long)now);
+  return old ? old : now;
+}
+
 // ---- the kernel ----------------------------------------------------------------
 
 template <int W, bool EMIT>
@@ -260,7 +316,9 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
   bool aborted = false;
   const u64 t_start = wall_clock64();
   const u64 deadline = p.deadline ? t_start + p.deadline : 0;
+  u64 pair_budget = 0;
   u64 pair_deadline = 0;
+  int own_clock = 0;
   const u64 tag0 = p.tag_base + (p.epoch ? __hip_atomic_load(p.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull);
 
   int cur_rel = -1;       // root whose G_u is in LDS
@@ -300,7 +358,22 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       Groots = bgr.roots;
       Ggw = bgr.gw;
       k = bgr.k;
-      pair_deadline = bgr.budget ? t_start + bgr.budget : 0;
+      pair_budget = bgr.budget;
+      own_clock = bgr.own_clock;
+    }
+    pair_deadline = 0;
+    if (p.pair_t0) {
+      // first-unit times of the pair and of the batch; a budget runs from one
+      // of them
+      u64 tp = 0, tb = 0;
+      if (lane == 0) {
+        const u64 now = wall_clock64();
+        tp = first_time(p.pair_t0 + 1 + pair, now);
+        if (pair_budget && !own_clock) tb = first_time(p.pair_t0, now);
+      }
+      tp = __shfl(tp, 0);
+      tb = __shfl(tb, 0);
+      if (pair_budget) pair_deadline = (own_clock ? tp : tb) + pair_budget;
     }
     if (p.pair_abort) {
       // a pair out of budget: its remaining units are skipped
@@ -309,7 +382,10 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         if (lane == 0) atomicOr(p.pair_abort + pair, 1);
         ab = 1;
       }
-      if (ab) continue;
+      if (ab) {
+        finish_units(p, pair, 1u + skip_rest(p, sg.pair_end));
+        continue;
+      }
     }
     if (__hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       aborted = true;
@@ -354,6 +430,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
     }
     if (cur_pruned) {
       if (ci == 0 && !p.soft_only) ++n_pruned;
+      finish_units(p, pair, 1u);
       continue;
     }
     // children of frame 0 handled by this unit: local ids [x_lo, x_hi)
@@ -382,7 +459,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
     while (true) {
       if (mode == ENTER) {
         ++n_frames;
-        if ((deadline || pair_deadline) && (n_frames & 255) == 0) {
+        if ((deadline || pair_deadline) && (n_frames & 15) == 0) {
           const u64 now = wall_clock64();
           if (deadline && now > deadline) {
             if (lane == 0) atomicOr(p.abort_flag, 1);
@@ -725,7 +802,10 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       aborted = true;
       break;
     }
-    if (unit_cancel) continue;  // the pair is reported as cancelled
+    if (unit_cancel) {  // the pair is reported as cancelled
+      finish_units(p, pair, 1u + skip_rest(p, sg.pair_end));
+      continue;
+    }
     // root result: cnt, fp * g(root)
     u64 rfp = p.fingerprint ? mulp(Ggw[r], res_fp) : 0;
     if (p.pair_out && lane == 0) {
@@ -755,6 +835,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         cur = atomicCAS((unsigned long long*)&o[2], seen, addp(seen, rfp));
       } while (cur != seen);
     }
+    finish_units(p, pair, 1u);
     __syncthreads();
   }
 
@@ -842,17 +923,17 @@ int ws_ensure(size_t wave_words, size_t memo_bytes) {
     if (dev_alloc((void**)&g_ws.abort_flag, 64)) return DIST_E_NOMEM;
   }
   if (wave_words > g_ws.wave_out_words) {
-    if (g_ws.wave_out) (void)hipFree(g_ws.wave_out);
-    if (g_ws.host_out) (void)hipHostFree(g_ws.host_out);
+    if (g_ws.wave_out) dev_free(g_ws.wave_out);
+    if (g_ws.host_out) pinned_free(g_ws.host_out);
     g_ws.wave_out = nullptr;
     g_ws.host_out = nullptr;
     g_ws.wave_out_words = 0;
     if (dev_alloc((void**)&g_ws.wave_out, wave_words * sizeof(u64))) return DIST_E_NOMEM;
-    if (hipHostMalloc((void**)&g_ws.host_out, wave_words * sizeof(u64)) != hipSuccess) return DIST_E_NOMEM;
+    if (pinned_alloc((void**)&g_ws.host_out, wave_words * sizeof(u64)) != DIST_OK) return DIST_E_NOMEM;
     g_ws.wave_out_words = wave_words;
   }
   if (memo_bytes > g_ws.memo_bytes) {
-    if (g_ws.memo) (void)hipFree(g_ws.memo);
+    if (g_ws.memo) dev_free(g_ws.memo);
     g_ws.memo = nullptr;
     g_ws.memo_bytes = 0;
     if (dev_alloc((void**)&g_ws.memo, memo_bytes)) return DIST_E_NOMEM;
@@ -871,13 +952,13 @@ int width_of(int d) {
 
 int ws_plan(size_t bytes) {
   if (bytes <= g_ws.plan_cap) return DIST_OK;
-  if (g_ws.d_plan) (void)hipFree(g_ws.d_plan);
-  if (g_ws.h_plan) (void)hipHostFree(g_ws.h_plan);
+  if (g_ws.d_plan) dev_free(g_ws.d_plan);
+  if (g_ws.h_plan) pinned_free(g_ws.h_plan);
   g_ws.d_plan = nullptr;
   g_ws.h_plan = nullptr;
   g_ws.plan_cap = 0;
   if (dev_alloc((void**)&g_ws.d_plan, bytes)) return DIST_E_NOMEM;
-  if (hipHostMalloc((void**)&g_ws.h_plan, bytes) != hipSuccess) return DIST_E_NOMEM;
+  if (pinned_alloc((void**)&g_ws.h_plan, bytes) != DIST_OK) return DIST_E_NOMEM;
   g_ws.plan_cap = bytes;
   return DIST_OK;
 }
@@ -890,27 +971,38 @@ const int kSlotWidth[5] = {16, 8, 4, 2, 1};
 // and the same number of units per root form one segment.
 void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, bool whole_roots, int min_w,
                   std::vector<BatchSeg> (&segs)[5], uint64_t (&units)[5], int (&kmax)[5]) {
+  // walks the runs of equal out-degree (roots are in descending out-degree
+  // order), so planning costs O(distinct degrees), not O(roots)
   int32_t a = 0;
-  while (a < nroots) {
-    int d = g->root_deg[a];
+  int cur_sl = -1, cur_upr = 0;
+  int32_t seg_a = 0;
+  size_t first_seg[5];
+  for (int b = 0; b < 5; ++b) first_seg[b] = segs[b].size();
+  auto flush = [&](int32_t end) {
+    if (cur_sl < 0 || end <= seg_a) return;
+    segs[cur_sl].push_back(BatchSeg{(uint32_t)units[cur_sl], pair, seg_a, cur_upr, 0u});
+    units[cur_sl] += (uint64_t)(end - seg_a) * (uint64_t)cur_upr;
+    if (k > kmax[cur_sl]) kmax[cur_sl] = k;
+  };
+  for (const auto& run : g->deg_hist) {
+    if (a >= nroots) break;
+    const int d = run.first;
+    const int32_t b = (int32_t)std::min<int64_t>((int64_t)a + run.second, (int64_t)nroots);
     int W = width_of(d);
     if (W < min_w) W = min_w;
-    int upr = whole_roots ? 1 : units_per_root(d, k, cw);
-    int32_t b = a + 1;
-    while (b < nroots) {
-      int db = g->root_deg[b];
-      int Wb = width_of(db);
-      if (Wb < min_w) Wb = min_w;
-      int ub = whole_roots ? 1 : units_per_root(db, k, cw);
-      if (Wb != W || ub != upr) break;
-      ++b;
+    const int sl = wslot_of_width(W);
+    const int upr = whole_roots ? 1 : units_per_root(d, k, cw);
+    if (sl != cur_sl || upr != cur_upr) {
+      flush(a);
+      cur_sl = sl;
+      cur_upr = upr;
+      seg_a = a;
     }
-    int sl = wslot_of_width(W);
-    segs[sl].push_back(BatchSeg{(uint32_t)units[sl], pair, a, upr});
-    units[sl] += (uint64_t)(b - a) * (uint64_t)upr;
-    if (k > kmax[sl]) kmax[sl] = k;
     a = b;
   }
+  flush(a);
+  for (int b = 0; b < 5; ++b)
+    for (size_t i = first_seg[b]; i < segs[b].size(); ++i) segs[b][i].pair_end = (uint32_t)units[b];
 }
 
 template <int W>
@@ -1272,13 +1364,29 @@ int occupancy_list(size_t lds) {
 
 size_t list_lds_bytes(int W, int k) { return lds_bytes(W, k) + align8(4 * (size_t)64 * W) + align8(4 * (size_t)(k + 1)); }
 
+// Freed blocks are reused at once, so a buffer is released only after the
+// stream's work (also on an error path) has finished.
 struct DevBuf {
+  hipStream_t s;
   void* p = nullptr;
-  ~DevBuf() { if (p) (void)hipFree(p); }
+  explicit DevBuf(hipStream_t st) : s(st) {}
+  ~DevBuf() {
+    if (p) {
+      (void)hipStreamSynchronize(s);
+      dev_free(p);
+    }
+  }
 };
 struct HostBuf {
+  hipStream_t s;
   void* p = nullptr;
-  ~HostBuf() { if (p) (void)hipHostFree(p); }
+  explicit HostBuf(hipStream_t st) : s(st) {}
+  ~HostBuf() {
+    if (p) {
+      (void)hipStreamSynchronize(s);
+      pinned_free(p);
+    }
+  }
 };
 
 }  // namespace
@@ -1319,7 +1427,7 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
   }
   if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
   // 1. per-root clique counts (count kernel), gathered in root order
-  DevBuf per, cnts, wide;
+  DevBuf per(s), cnts(s), wide(s);
   if (dev_alloc(&per.p, sizeof(u64) * 3 * ((size_t)g->n + 1))) return DIST_E_NOMEM;
   if (dev_alloc(&cnts.p, sizeof(u64) * (size_t)nroots)) return DIST_E_NOMEM;
   if (dev_alloc(&wide.p, 64)) return DIST_E_NOMEM;
@@ -1347,14 +1455,14 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
     if (c > cap) return DIST_E_UNSUPPORTED;  // one root's output exceeds the buffer
   if (total < cap) cap = total > 0 ? total : 1;
   // 2. buffers
-  DevBuf obuf, ocur;
-  HostBuf stage;
+  DevBuf obuf(s), ocur(s);
+  HostBuf stage(s);
   if (dev_alloc(&obuf.p, cap * rec_bytes)) return DIST_E_NOMEM;
   if (dev_alloc(&ocur.p, 64)) return DIST_E_NOMEM;
   size_t stage_bytes = cap * rec_bytes < kListStageBytes ? cap * rec_bytes : kListStageBytes;
   stage_bytes = stage_bytes / rec_bytes * rec_bytes;
   if (stage_bytes == 0) stage_bytes = rec_bytes;
-  if (hipHostMalloc(&stage.p, stage_bytes) != hipSuccess) return DIST_E_NOMEM;
+  if (pinned_alloc(&stage.p, stage_bytes) != DIST_OK) return DIST_E_NOMEM;
   std::vector<Bucket> buckets = make_buckets(g, nroots);
   int rc = ws_ensure(16 * kOutWords, 0);
   if (rc) return rc;
@@ -1496,6 +1604,11 @@ __global__ void k_zero_i32(int* p, int n) {
   for (; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// cost tiers of a streamed batch (the cursor array holds 64 launch cursors)
+constexpr int kTiers = 8;
+constexpr double kTierDecades = 2.0;
+static_assert(kTiers * 5 <= 64, "one cursor per launch");
+
 struct BatchLaunch {
   int W;
   int grid;
@@ -1506,7 +1619,7 @@ struct BatchLaunch {
 template <class T>
 int grow_dev(T** p, size_t& cap, size_t need) {
   if (need <= cap && *p) return DIST_OK;
-  if (*p) (void)hipFree(*p);
+  if (*p) dev_free(*p);
   *p = nullptr;
   cap = 0;
   if (dev_alloc((void**)p, need * sizeof(T))) return DIST_E_NOMEM;
@@ -1524,6 +1637,15 @@ struct BatchWs {
   size_t cap_out = 0;
   int* d_pair_abort = nullptr;
   size_t cap_pab = 0;
+  unsigned* d_pair_rem = nullptr;       // per run: units left per pair
+  unsigned* d_pair_rem_init = nullptr;  // units per pair
+  size_t cap_rem = 0, cap_rem_init = 0;
+  unsigned long long* d_pair_t0 = nullptr;
+  size_t cap_t0 = 0;
+  u64* h_pair_host = nullptr;           // pinned, device-visible: {flag, lo, hi, fp} per pair
+  u64* d_pair_host = nullptr;           // its device address
+  size_t cap_ph = 0;
+  bool stream_done = false;             // publish per-pair completions
   u64* h_out = nullptr;       // pinned: pair_out, abort word, pair abort flags
   size_t cap_h = 0;
   unsigned* d_cursor = nullptr;
@@ -1540,6 +1662,7 @@ struct BatchWs {
   std::vector<int64_t> dls;
   dist_config cfg{};
   std::vector<int> status;
+  std::vector<uint32_t> units;          // units per pair
   std::vector<BatchLaunch> launches;
   u64 units_total = 0;
   hipGraph_t graph = nullptr;
@@ -1554,16 +1677,20 @@ struct BatchWs {
   }
   ~BatchWs() {
     drop_graph();
-    (void)hipFree(d_bg);
-    (void)hipFree(d_segs);
-    (void)hipFree(d_pair_out);
-    (void)hipFree(d_pair_abort);
-    (void)hipFree(d_cursor);
-    (void)hipFree(d_abort);
-    (void)hipFree(d_epoch);
-    (void)hipFree(d_wave_out);
-    (void)hipFree(d_memo);
-    if (h_out) (void)hipHostFree(h_out);
+    dev_free(d_bg);
+    dev_free(d_segs);
+    dev_free(d_pair_out);
+    dev_free(d_pair_abort);
+    dev_free(d_cursor);
+    dev_free(d_abort);
+    dev_free(d_epoch);
+    dev_free(d_wave_out);
+    dev_free(d_memo);
+    dev_free(d_pair_rem);
+    dev_free(d_pair_rem_init);
+    dev_free(d_pair_t0);
+    if (h_out) pinned_free(h_out);
+    if (h_pair_host) pinned_free(h_pair_host);
   }
 };
 
@@ -1605,7 +1732,7 @@ int launch_any(int W, const Params& prm, int grid, size_t lds, hipStream_t s) {
 
 // Lays out the batch in ws and uploads its descriptors (synchronous on s).
 int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int64_t* dls, int n,
-               const dist_config& cfg, hipStream_t s) {
+               const dist_config& cfg, hipStream_t s, bool stream_done, const double* pair_cost) {
   P->drop_graph();
   P->launches.clear();
   P->status.assign(n, DIST_OK);
@@ -1616,16 +1743,41 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
   DIST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   DIST_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
   std::vector<BatchGraph> bg(n);
-  std::vector<BatchSeg> segs[5];
-  uint64_t units64[5] = {0, 0, 0, 0, 0};
-  int kmax[5] = {0, 0, 0, 0, 0};
+  // Launch groups: tier-major, then width class.  A plain batch has one
+  // tier.  When pairs are reported as they finish, or have budgets, pairs go
+  // into tiers by predicted cost (kTierDecades decades each) and are taken
+  // cheapest first, so a cheap pair never waits for the launch of an
+  // expensive one.
+  std::vector<BatchSeg> segs[kTiers][5];
+  uint64_t units64[kTiers][5] = {};
+  int kmax[kTiers][5] = {};
   const int min_w = cfg.min_width > 1 ? cfg.min_width : 1;
   const int cw = cfg.chunk_work > 0 ? cfg.chunk_work : 512;
-  for (int i = 0; i < n; ++i) {
+  std::vector<int> order(n), tier(n, 0);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  const bool own_clock = cfg.budget_from_pair_start != 0;
+  bool by_cost = stream_done || pair_cost;
+  for (int i = 0; i < n && dls && !by_cost; ++i) by_cost = dls[i] > 0;
+  if (by_cost) {
+    // With budgets that run from each pair's own start, a pair that waits
+    // loses nothing: one tier.  With budgets from the batch start, a cheap
+    // pair must not wait for the launch of an expensive one: cost tiers.
+    std::vector<double> est(n);
+    for (int i = 0; i < n; ++i) {
+      est[i] = pair_cost ? pair_cost[i] : estimate_cost(gs[i], ks[i]);
+      int t = (!own_clock && est[i] > 1) ? (int)(std::log10(est[i]) / kTierDecades) : 0;
+      tier[i] = t < kTiers - 1 ? t : kTiers - 1;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return est[a] < est[b]; });
+  }
+  std::vector<uint32_t> rem_init(n > 0 ? n : 1, 0);
+  for (int oi = 0; oi < n; ++oi) {
+    const int i = order[oi];
+    const int t = tier[i];
     const dist_graph* g = gs[i];
     const int k = ks[i];
     u64 budget = (dls && dls[i] > 0) ? (u64)dls[i] * (u64)rate_khz : 0;
-    bg[i] = BatchGraph{g->dptr, g->dcol, g->orig, g->roots, g->gw, k, 0, budget};
+    bg[i] = BatchGraph{g->dptr, g->dcol, g->orig, g->roots, g->gw, k, own_clock ? 1 : 0, budget};
     if (k < 2) continue;  // k = 1 is answered on the host side
     int32_t lo = 0, hi = g->n;
     while (lo < hi) {
@@ -1637,21 +1789,41 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
       P->status[i] = DIST_E_UNSUPPORTED;
       continue;
     }
-    add_segments(g, i, nroots, k, cw, false, min_w, segs, units64, kmax);
+    uint64_t* u = units64[t];
+    uint64_t before = u[0] + u[1] + u[2] + u[3] + u[4];
+    add_segments(g, i, nroots, k, cw, false, min_w, segs[t], units64[t], kmax[t]);
+    rem_init[i] = (uint32_t)(u[0] + u[1] + u[2] + u[3] + u[4] - before);
   }
   std::vector<BatchSeg> all;
-  size_t seg_off[5];
-  for (int b = 0; b < 5; ++b) {
-    if (units64[b] >= 0xffffffffull) return DIST_E_UNSUPPORTED;
-    seg_off[b] = all.size();
-    all.insert(all.end(), segs[b].begin(), segs[b].end());
-  }
+  size_t seg_off[kTiers][5];
+  for (int t = 0; t < kTiers; ++t)
+    for (int b = 0; b < 5; ++b) {
+      if (units64[t][b] >= 0xffffffffull) return DIST_E_UNSUPPORTED;
+      seg_off[t][b] = all.size();
+      all.insert(all.end(), segs[t][b].begin(), segs[t][b].end());
+    }
   const size_t nn = (size_t)(n > 0 ? n : 1);
   int rc = DIST_OK;
   if ((rc = grow_dev(&P->d_bg, P->cap_bg, nn))) return rc;
   if ((rc = grow_dev(&P->d_segs, P->cap_segs, all.size() + 1))) return rc;
   if ((rc = grow_dev(&P->d_pair_out, P->cap_out, 3 * nn + 1))) return rc;
   if ((rc = grow_dev(&P->d_pair_abort, P->cap_pab, nn))) return rc;
+  if ((rc = grow_dev(&P->d_pair_rem, P->cap_rem, nn))) return rc;
+  if ((rc = grow_dev(&P->d_pair_rem_init, P->cap_rem_init, nn))) return rc;
+  if ((rc = grow_dev(&P->d_pair_t0, P->cap_t0, nn + 1))) return rc;
+  if (6 * nn > P->cap_ph) {
+    if (P->h_pair_host) pinned_free(P->h_pair_host);
+    P->h_pair_host = nullptr;
+    P->cap_ph = 0;
+    if (pinned_alloc((void**)&P->h_pair_host, 6 * nn * sizeof(u64), hipHostMallocMapped | hipHostMallocCoherent) !=
+        DIST_OK)
+      return DIST_E_NOMEM;
+    DIST_CHECK(hipHostGetDevicePointer((void**)&P->d_pair_host, P->h_pair_host, 0));
+    P->cap_ph = 6 * nn;
+  }
+  DIST_CHECK(hipMemcpyAsync(P->d_pair_rem_init, rem_init.data(), sizeof(uint32_t) * nn, hipMemcpyHostToDevice, s));
+  P->stream_done = stream_done;
+  P->units.assign(rem_init.begin(), rem_init.begin() + n);
   if (!P->d_cursor && dev_alloc((void**)&P->d_cursor, 64 * sizeof(unsigned))) return DIST_E_NOMEM;
   if (!P->d_abort && dev_alloc((void**)&P->d_abort, 64)) return DIST_E_NOMEM;
   if (!P->d_epoch) {
@@ -1663,14 +1835,15 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
       base = g_tag_next;
       g_tag_next += (u64)1 << 44;
     }
-    DIST_CHECK(hipMemcpy(P->d_epoch, &base, sizeof(u64), hipMemcpyHostToDevice));
+    DIST_CHECK(hipMemcpyAsync(P->d_epoch, &base, sizeof(u64), hipMemcpyHostToDevice, s));
+    DIST_CHECK(hipStreamSynchronize(s));
   }
   const size_t hneed = 3 * nn + 1 + nn;  // pair_out, abort word, pair aborts (as u64 slots)
   if (hneed > P->cap_h) {
-    if (P->h_out) (void)hipHostFree(P->h_out);
+    if (P->h_out) pinned_free(P->h_out);
     P->h_out = nullptr;
     P->cap_h = 0;
-    if (hipHostMalloc((void**)&P->h_out, hneed * sizeof(u64)) != hipSuccess) return DIST_E_NOMEM;
+    if (pinned_alloc((void**)&P->h_out, hneed * sizeof(u64)) != DIST_OK) return DIST_E_NOMEM;
     P->cap_h = hneed;
   }
   if (n) DIST_CHECK(hipMemcpyAsync(P->d_bg, bg.data(), sizeof(BatchGraph) * n, hipMemcpyHostToDevice, s));
@@ -1678,38 +1851,43 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     DIST_CHECK(hipMemcpyAsync(P->d_segs, all.data(), sizeof(BatchSeg) * all.size(), hipMemcpyHostToDevice, s));
   DIST_CHECK(hipStreamSynchronize(s));  // bg and all are host locals
   int maxgrid = 0, maxW = 1;
+  for (int t = 0; t < kTiers; ++t)
   for (int b = 0; b < 5; ++b) {
-    if (units64[b] == 0) continue;
+    if (units64[t][b] == 0) continue;
     BatchLaunch L{};
     L.W = kSlotWidth[b];
-    L.lds = lds_bytes(L.W, kmax[b]);
+    L.lds = lds_bytes(L.W, kmax[t][b]);
     if (L.lds > (size_t)maxlds) {
-      for (auto& sg : segs[b]) P->status[sg.pair] = DIST_E_UNSUPPORTED;
+      for (auto& sg : segs[t][b]) P->status[sg.pair] = DIST_E_UNSUPPORTED;
       continue;
     }
     int occ = occupancy_any(L.W, L.lds);
     int64_t grid = (int64_t)occ * (cus > 0 ? cus : 256);
-    if (grid > (int64_t)units64[b]) grid = (int64_t)units64[b];
+    if (cfg.grid_pct > 0 && cfg.grid_pct < 100) grid = grid * cfg.grid_pct / 100;
+    if (grid > (int64_t)units64[t][b]) grid = (int64_t)units64[t][b];
     L.grid = (int)(grid < 1 ? 1 : grid);
     Params& prm = L.prm;
     prm = Params{};
-    prm.k = kmax[b];
+    prm.k = kmax[t][b];
     prm.prune = cfg.prune;
     prm.memo = cfg.memo;
     prm.fingerprint = cfg.fingerprint;
-    prm.cursor = P->d_cursor + b;
-    prm.units = (uint32_t)units64[b];
+    prm.cursor = P->d_cursor + (t * 5 + b);
+    prm.units = (uint32_t)units64[t][b];
     prm.chunk_work = cw;
     prm.bg = P->d_bg;
-    prm.segs = P->d_segs + seg_off[b];
-    prm.nsegs = (int32_t)segs[b].size();
+    prm.segs = P->d_segs + seg_off[t][b];
+    prm.nsegs = (int32_t)segs[t][b].size();
     prm.pair_out = P->d_pair_out;
     prm.pair_abort = P->d_pair_abort;
+    prm.pair_rem = stream_done ? P->d_pair_rem : nullptr;
+    prm.pair_t0 = P->d_pair_t0;
+    prm.pair_host = stream_done ? P->d_pair_host : nullptr;
     prm.abort_flag = P->d_abort;
     prm.epoch = P->d_epoch;
-    prm.tag_base = P->units_total;  // units of earlier width classes come first
+    prm.tag_base = P->units_total;  // units of earlier launches come first
     if (cfg.deadline_ms > 0) prm.deadline = (u64)cfg.deadline_ms * (u64)rate_khz;
-    P->units_total += units64[b];
+    P->units_total += units64[t][b];
     P->launches.push_back(L);
     if (L.grid > maxgrid) maxgrid = L.grid;
     if (L.W > maxW) maxW = L.W;
@@ -1753,6 +1931,9 @@ int enqueue_batch(BatchWs* P, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)P->d_abort, 16);
   hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, P->d_pair_out, (u64)(3 * nn));
   hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, P->d_pair_abort, (int)nn);
+  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, (u64*)P->d_pair_t0, (u64)(nn + 1));
+  if (P->stream_done)
+    DIST_CHECK(hipMemcpyAsync(P->d_pair_rem, P->d_pair_rem_init, sizeof(unsigned) * nn, hipMemcpyDeviceToDevice, s));
   for (const auto& L : P->launches) {
     hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, P->d_wave_out, (u64)L.grid * kOutWords);
     int rc = launch_any(L.W, L.prm, L.grid, L.lds, s);
@@ -1767,7 +1948,9 @@ int enqueue_batch(BatchWs* P, hipStream_t s) {
 }  // namespace
 
 int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const dist_config& cfg, int use_graph,
-                       const int64_t* dls, hipStream_t s, dist_result* out, int* pair_status, double* ms) {
+                       const int64_t* dls, hipStream_t s, dist_result* out, int* pair_status, double* ms,
+                       dist_pair_done on_done, void* user, const double* pair_cost) {
+  if (on_done) use_graph = 0;
   for (int i = 0; i < n; ++i)
     if (!gs[i] || ks[i] < 1 || ks[i] > DIST_K_MAX) return gs[i] ? DIST_E_K : DIST_E_INVALID;
   int dev = 0;
@@ -1784,7 +1967,8 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
       }
     }
     DIST_CHECK(hipDeviceSynchronize());
-    int rc2 = search_count_batch(gs, ks, n, cfg, use_graph, dls, own, out, pair_status, ms);
+    int rc2 = search_count_batch(gs, ks, n, cfg, use_graph, dls, own, out, pair_status, ms, on_done, user,
+                                 pair_cost);
     DIST_CHECK(hipStreamSynchronize(own));
     return rc2;
   }
@@ -1810,7 +1994,7 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
   DIST_CHECK(hipEventCreate(&e1));
   int rc = DIST_OK;
   if (!reuse) {
-    rc = plan_batch(P, gs, ks, dls, n, cfg, s);
+    rc = plan_batch(P, gs, ks, dls, n, cfg, s, on_done != nullptr, pair_cost);
     if (rc) {
       P->drop_graph();
       return rc;
@@ -1832,6 +2016,24 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
       }
     }
   }
+  const size_t nn0 = (size_t)(n > 0 ? n : 1);
+  std::vector<char> reported;
+  double ticks_per_ms = 1.0;
+  if (on_done) {
+    int rate_khz = 0;
+    DIST_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    ticks_per_ms = rate_khz > 0 ? (double)rate_khz : 1.0;
+    memset(P->h_pair_host, 0, 6 * nn0 * sizeof(u64));
+    reported.assign(n, 0);
+    // pairs with no work (no root deep enough) are done before the launch
+    for (int i = 0; i < n; ++i)
+      if (ks[i] >= 2 && P->status[i] == DIST_OK && P->units[i] == 0) {
+        dist_result r{0, 0, 0};
+        reported[i] = 1;
+        out[i] = r;
+        on_done(i, &r, DIST_OK, 0.0, user);
+      }
+  }
   DIST_CHECK(hipEventRecord(e0, s));
   if (P->exec) {
     DIST_CHECK(hipGraphLaunch(P->exec, s));
@@ -1840,6 +2042,25 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
     if (rc) return rc;
   }
   DIST_CHECK(hipEventRecord(e1, s));
+  if (on_done) {
+    // report pairs as the device finishes them
+    for (;;) {
+      bool finished = hipEventQuery(e1) == hipSuccess;
+      for (int i = 0; i < n; ++i) {
+        if (reported[i] || ks[i] < 2 || P->status[i] != DIST_OK) continue;
+        const u64* h = P->h_pair_host + 6 * i;
+        u64 flag = __atomic_load_n(h, __ATOMIC_ACQUIRE);
+        if (!flag) continue;
+        dist_result r{h[1], h[2], cfg.fingerprint ? h[3] : 0};
+        int st = flag == 2 ? DIST_E_CANCELLED : (r.count_hi ? DIST_E_OVERFLOW : DIST_OK);
+        double dms = h[5] > h[4] ? (double)(h[5] - h[4]) / ticks_per_ms : 0.0;
+        reported[i] = 1;
+        on_done(i, &r, st, dms, user);
+      }
+      if (finished) break;
+      std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
+  }
   DIST_CHECK(hipEventSynchronize(e1));
   float t = 0;
   DIST_CHECK(hipEventElapsedTime(&t, e0, e1));
@@ -1862,6 +2083,7 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
     if (st == DIST_OK && r.count_hi) st = DIST_E_OVERFLOW;
     out[i] = r;
     if (pair_status) pair_status[i] = st;
+    if (on_done && !reported[i]) on_done(i, &r, st, -1.0, user);
     if (st != DIST_OK && first == DIST_OK) first = st;
   }
   if (!use_graph) P->serials.clear();  // nothing captured to replay
@@ -1878,4 +2100,16 @@ void batch_forget(const dist_graph* g) {
         break;
       }
   }
+}
+
+double estimate_cost(const dist_graph* g, int k) {
+  if (k <= 1) return (double)g->n;
+  const int r = k - 1;
+  double total = 0;
+  for (const auto& dc : g->deg_hist) {
+    if (dc.first < r) continue;
+    double lc = std::lgamma((double)dc.first + 1) - std::lgamma((double)r + 1) - std::lgamma((double)(dc.first - r) + 1);
+    total += (double)dc.second * std::exp(lc);
+  }
+  return total;
 }

@@ -34,7 +34,8 @@ class Config(ctypes.Structure):
     _fields_ = [("memo", ctypes.c_int32), ("prune", ctypes.c_int32),
                 ("fingerprint", ctypes.c_int32), ("memo_entries", ctypes.c_int32),
                 ("memo_bytes", ctypes.c_int64), ("deadline_ms", ctypes.c_int64),
-                ("chunk_work", ctypes.c_int32), ("min_width", ctypes.c_int32)]
+                ("chunk_work", ctypes.c_int32), ("grid_pct", ctypes.c_int32),
+                ("budget_from_pair_start", ctypes.c_int32), ("min_width", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -69,6 +70,9 @@ class GraphInfo(ctypes.Structure):
                 ("max_outdeg", ctypes.c_int32), ("order_bound", ctypes.c_int32),
                 ("orient_ms", ctypes.c_double)]
 
+
+PAIR_DONE = ctypes.CFUNCTYPE(None, ctypes.c_int, ctypes.POINTER(Result), ctypes.c_int,
+                             ctypes.c_double, ctypes.c_void_p)
 
 SINK = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint64,
                         ctypes.c_int, ctypes.c_void_p)
@@ -108,6 +112,19 @@ def _load():
                                         ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_double)]
     lib.dist_count_batch_ex.restype = ctypes.c_int
+    lib.dist_count_batch_stream.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
+                                            ctypes.c_int, ctypes.POINTER(Config),
+                                            ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_double), vp,
+                                            ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_int),
+                                            PAIR_DONE, vp]
+    lib.dist_count_batch_stream.restype = ctypes.c_int
+    lib.dist_estimate_cost.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.dist_estimate_cost.restype = ctypes.c_int
+    lib.dist_mem_cached.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.dist_mem_cached.restype = ctypes.c_int
+    lib.dist_mem_trim.argtypes = []
+    lib.dist_mem_trim.restype = ctypes.c_int
     lib.dist_root_soft_embed.argtypes = [vp, ctypes.c_int, vp, vp]
     lib.dist_root_soft_embed.restype = ctypes.c_int
     lib.dist_graph_ranks.argtypes = [vp, vp, vp]
@@ -259,6 +276,59 @@ def count_batch(graphs, ks, cfg: Config | None = None, use_graph=True, stream=No
     if with_status:
         return res, rc, ms.value, [int(st[i]) for i in range(n)]
     return res, rc, ms.value
+
+
+def count_batch_stream(graphs, ks, on_done, cfg: Config | None = None, stream=None,
+                       deadlines_ms=None, costs=None):
+    """dist_count_batch_stream: on_done(i, count, fp, status, device_ms) is
+    called for every pair as soon as the device has finished it; pairs are
+    scheduled in ascending order of costs (None: the library's estimate).
+    Returns ([(count, fp)] per pair, status, per-pair statuses)."""
+    n = len(graphs)
+    arr = (ctypes.c_void_p * max(n, 1))(*[g.handle for g in graphs])
+    karr = (ctypes.c_int * max(n, 1))(*[int(k) for k in ks])
+    out = (Result * max(n, 1))()
+    st = (ctypes.c_int * max(n, 1))()
+    dl = None
+    if deadlines_ms is not None:
+        dl = (ctypes.c_int64 * max(n, 1))(*[int(x) for x in deadlines_ms])
+    cost = None
+    if costs is not None:
+        cost = (ctypes.c_double * max(n, 1))(*[float(x) for x in costs])
+    errors = []
+
+    def _cb(i, res, status, dms, user):
+        try:
+            r = res.contents
+            on_done(int(i), r.count, int(r.fp), int(status), float(dms))
+        except BaseException as e:  # never unwind through C
+            errors.append(e)
+
+    cb = PAIR_DONE(_cb)
+    rc = _load().dist_count_batch_stream(arr, karr, n, ctypes.byref(cfg) if cfg is not None else None,
+                                         dl, cost, _stream_ptr(stream), out, st, cb, None)
+    if errors:
+        raise errors[0]
+    if rc not in (OK, E_OVERFLOW, E_CANCELLED):
+        _check(rc, "dist_count_batch_stream")
+    return [(out[i].count, int(out[i].fp)) for i in range(n)], rc, [int(st[i]) for i in range(n)]
+
+
+def mem_cached():
+    """(device bytes, pinned host bytes) held in the library's block cache."""
+    d, h = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(_load().dist_mem_cached(ctypes.byref(d), ctypes.byref(h)), "dist_mem_cached")
+    return d.value, h.value
+
+
+def mem_trim():
+    _check(_load().dist_mem_trim(), "dist_mem_trim")
+
+
+def estimate_cost(g: Graph, k: int) -> float:
+    v = ctypes.c_double(0)
+    _check(_load().dist_estimate_cost(g.handle, int(k), ctypes.byref(v)), "dist_estimate_cost")
+    return v.value
 
 
 def list_cliques(g: Graph, k: int, sink=None, stream=None):

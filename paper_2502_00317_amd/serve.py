@@ -14,9 +14,17 @@ resident pool plus the admitted ad-hoc graphs fit the memory limit, and its
 memory is released when its query completes.  Pool queries need no memory
 and are never held back by an ad-hoc query that does not fit.
 
-Each query carries a time budget; a query whose search exceeds it is
-stopped on the device (the other queries of its batch go on) and reported
-as DNF.  Latency is completion time minus arrival time.
+Within a batch, queries are scheduled cheapest first (by the predicted
+search size) and each one is completed as soon as the device has finished
+it, not when its whole batch ends; each slot's launches take a share of the
+device's wavefront slots so that the batches of all slots run side by side.
+
+Each query carries a latency budget counted from its arrival.  When its
+batch is dispatched, what is left of the budget becomes its device budget;
+a query whose search runs past it is stopped on the device (the other
+queries of its batch go on) and reported as DNF, and a query whose budget
+ran out while it waited is reported as DNF without running.  Latency is
+completion time minus arrival time.
 
 The device work goes through a backend object, so the scheduling logic can
 be exercised on the CPU with a simulated device (tests/fake_device.py).
@@ -24,6 +32,7 @@ be exercised on the CPU with a simulated device (tests/fake_device.py).
 from __future__ import annotations
 
 import collections
+import math
 import threading
 import time
 from dataclasses import dataclass, field
@@ -45,7 +54,7 @@ class Query:
     t_arrival: float                 # seconds after the server start
     graph: int | None = None         # pool graph id
     adhoc: tuple | None = None       # (row_ptr, col) uploaded with the query
-    deadline_ms: int = 0
+    deadline_ms: int = 0             # latency budget from arrival; 0 = none
     # filled in by the server
     count: int | None = None
     fp: int | None = None
@@ -54,6 +63,13 @@ class Query:
     t_done: float | None = None
     slot: int | None = None
     batch_size: int = 0
+    lane: str = ""                   # express | bulk
+    moves: int = 0                   # times moved from the express to the bulk lane
+    handle: object = None            # oriented ad-hoc graph while the query lives
+    owner: int = 0                   # batch that holds the query now
+    admitted: bool = False           # its memory is counted
+    est: float | None = None         # cost estimate used for routing
+    released: bool = False
     done: threading.Event = field(default_factory=threading.Event)
 
     @property
@@ -70,14 +86,26 @@ class Query:
 class DeviceBackend:
     """The real device: dist (libdist.so) with one torch stream per slot."""
 
-    def __init__(self, slots: int, cfg_kwargs=None):
+    def __init__(self, slots: int, cfg_kwargs=None, grid_pcts=None, slot_cfgs=None):
+        """grid_pcts[s]: share of the device's wavefront slots that the
+        launches of slot s may take (default: an equal share each), so that
+        the batches of all slots are resident together; slot_cfgs[s]: further
+        switches for slot s."""
         import torch
         from . import dist
         self.dist = dist
         self.torch = torch
         torch.cuda.init()
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
-        self.cfg = dist.config(**(cfg_kwargs or {}))
+        if grid_pcts is None:
+            grid_pcts = [max(1, 100 // slots)] * slots
+        slot_cfgs = slot_cfgs or [{}] * slots
+        self.cfgs = [dist.config(**dict(cfg_kwargs or {}, grid_pct=int(p), **sc))
+                     for p, sc in zip(grid_pcts, slot_cfgs)]
+        self.cfg_one = dist.config(**dict(cfg_kwargs or {}))
+
+    def estimate(self, g, k):
+        return self.dist.estimate_cost(g, k)
 
     def orient(self, row_ptr, col, slot):
         return self.dist.orient(row_ptr, col, stream=self.streams[slot])
@@ -85,19 +113,65 @@ class DeviceBackend:
     def free(self, g):
         g.free()
 
-    def count_batch(self, slot, graphs, ks, deadlines_ms):
-        res, rc, ms, st = self.dist.count_batch(graphs, ks, cfg=self.cfg, use_graph=False,
-                                                stream=self.streams[slot],
-                                                deadlines_ms=deadlines_ms, with_status=True)
+    def count_batch(self, slot, graphs, ks, deadlines_ms, on_done=None, costs=None):
+        """Counts every pair; on_done(i, count, fp, status, device_ms) is
+        called for each pair as soon as it is finished on the device; pairs
+        run in ascending order of costs."""
         D = self.dist
         names = {D.OK: "ok", D.E_OVERFLOW: "overflow", D.E_CANCELLED: "dnf"}
+        cb = None
+        if on_done is not None:
+            def cb(i, c, f, st, dms):
+                on_done(i, c, f, names.get(st, "error"), dms)
+        t = time.perf_counter()
+        if cb is None:
+            res, rc, ms, st = D.count_batch(graphs, ks, cfg=self.cfgs[slot], use_graph=False,
+                                            stream=self.streams[slot],
+                                            deadlines_ms=deadlines_ms, with_status=True)
+        else:
+            res, rc, st = D.count_batch_stream(graphs, ks, cb, cfg=self.cfgs[slot],
+                                               stream=self.streams[slot],
+                                               deadlines_ms=deadlines_ms, costs=costs)
+            ms = (time.perf_counter() - t) * 1e3
         return res, [names.get(s, "error") for s in st], ms
+
+    def count_one(self, slot, g, k, budget_ms):
+        """The per-graph call (dist_count_ex) for one query, with the whole
+        device."""
+        import ctypes
+        D = self.dist
+        cfg = D.Config()
+        ctypes.memmove(ctypes.byref(cfg), ctypes.byref(self.cfg_one), ctypes.sizeof(cfg))
+        cfg.deadline_ms = int(budget_ms)
+        try:
+            c, f, rc = D.count(g, k, cfg=cfg, stream=self.streams[slot])
+        except D.DistError as e:
+            return (None, None), ("dnf" if e.status == D.E_CANCELLED else "error")
+        return (c, f), ("overflow" if rc == D.E_OVERFLOW else "ok")
 
 
 class Server:
+    """Continuous-batching server.
+
+    slots      -- concurrent batches (one host thread and one stream each);
+    express_ms -- when > 0 and slots >= 2, slot 0 is an express lane: its
+                  batches give every query at most express_ms of device time;
+                  a query cut off there moves to the bulk lane (the other
+                  slots) with what is left of its latency budget, and later
+                  queries with the same (pool graph, k) go to the bulk lane
+                  directly.  This is a two-level feedback queue: light
+                  queries never wait behind heavy ones;
+    plain      -- one query at a time through the per-graph call (the
+                  baseline without batching);
+    stream_results -- complete each query as soon as the device reports it,
+                  not when its whole batch ends.
+    """
+
     def __init__(self, backend, pool_handles: dict, slots: int = 2,
                  mem_limit: int = 1 << 62, pool_bytes: int = 0, max_batch: int = 4096,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, stream_results: bool = True, express_ms: int = 0,
+                 plain: bool = False):
+        self.stream_results = stream_results
         self.pool_bytes = pool_bytes
         self.backend = backend
         self.pool = pool_handles
@@ -105,15 +179,26 @@ class Server:
         self.mem_limit = mem_limit
         self.mem_used = pool_bytes
         self.peak_mem = pool_bytes
-        self.max_batch = max_batch
+        self.max_batch = 1 if plain else max_batch
+        self.plain = plain
         self.clock = clock
+        self.express_ms = express_ms if (express_ms > 0 and slots >= 2 and not plain) else 0
+        self.lanes = (["express"] + ["bulk"] * (slots - 1)) if self.express_ms else ["bulk"] * slots
         self.t0 = None
-        self.pending = collections.deque()
+        self.queues = {"express": collections.deque(), "bulk": collections.deque()}
+        self.heavy = set()    # (pool graph, k) cut off in the express lane
+        self.service_ms = {}  # (pool graph, k) -> last measured device service time
+        self.light_max = {}   # k -> largest estimate completed in the express lane
+        self.heavy_min = {}   # k -> smallest estimate cut off in the express lane
+        self.routed_bulk = 0  # queries sent to the bulk lane on arrival
+        self.demoted = 0
         self.cv = threading.Condition()
         self.stopping = False
         self.threads = []
-        self.batches = []     # (slot, size, t_start, t_end, device ms)
+        self.batches = []     # (slot, size, t_start, t_end, device ms, t_count_start)
         self.errors = []
+        self._batch_ids = 0
+        self._running = {}    # slot -> batch id while a batch runs
 
     # ---- lifecycle ------------------------------------------------------------
     def start(self):
@@ -126,9 +211,41 @@ class Server:
     def now(self):
         return self.clock() - self.t0
 
+    def _estimate(self, q):
+        """The library's cost bound for a pool query, with the clique size
+        capped at 5 (sum over roots of C(d+, min(k - 1, 4))): it orders the
+        light queries well, and its scale is learned per k (see _route)."""
+        if q.adhoc is not None or not hasattr(self.backend, "estimate"):
+            return None
+        if q.est is None:
+            q.est = self.backend.estimate(self.pool[q.graph], min(q.k, 5))
+        return q.est
+
+    def _route(self, q):
+        """express or bulk.  A (graph, k) cut off in the express lane before
+        goes to the bulk lane.  Otherwise a monotone threshold per k: the
+        smallest estimate cut off in the express lane so far, unless a query
+        with at least that estimate has completed there.  Lock held."""
+        if not self.express_ms:
+            return "bulk"
+        if q.adhoc is not None:
+            return "express"
+        if (q.graph, q.k) in self.heavy:
+            return "bulk"
+        est = self._estimate(q)
+        hmin = self.heavy_min.get(q.k)
+        if est is not None and hmin is not None and est >= hmin and est > self.light_max.get(q.k, -1.0):
+            return "bulk"
+        return "express"
+
     def submit(self, q: Query):
+        if self.express_ms and q.adhoc is None:
+            self._estimate(q)  # outside the lock: a library call
         with self.cv:
-            self.pending.append(q)
+            q.lane = self._route(q)
+            if q.lane == "bulk" and self.express_ms:
+                self.routed_bulk += 1
+            self.queues[q.lane].append(q)
             self.cv.notify_all()
         return q
 
@@ -140,13 +257,20 @@ class Server:
             t.join()
 
     # ---- scheduling -----------------------------------------------------------
-    def _take(self):
-        """Every admissible pending query, in arrival order, up to
-        max_batch.  Called with the lock held."""
+    def _idle(self):
+        return not self.queues["express"] and not self.queues["bulk"]
+
+    def _take(self, lane):
+        """Every admissible pending query of the lane, in arrival order, up
+        to max_batch.  Called with the lock held."""
         taken = []
         keep = collections.deque()
-        while self.pending and len(taken) < self.max_batch:
-            q = self.pending.popleft()
+        pending = self.queues[lane]
+        while pending and len(taken) < self.max_batch:
+            q = pending.popleft()
+            if q.admitted:  # moved here from the express lane; memory held
+                taken.append(q)
+                continue
             need = q.need_bytes()
             if need > self.mem_limit - self.pool_bytes:
                 # can never fit, even with nothing else admitted
@@ -159,54 +283,159 @@ class Server:
                 continue
             self.mem_used += need
             self.peak_mem = max(self.peak_mem, self.mem_used)
+            q.admitted = True
             taken.append(q)
-        keep.extend(self.pending)
-        self.pending = keep
+        keep.extend(pending)
+        self.queues[lane] = keep
         return taken
 
     def _slot_loop(self, slot):
+        lane = self.lanes[slot]
         while True:
             with self.cv:
-                batch = self._take()
+                batch = self._take(lane)
                 while not batch:
-                    if self.stopping and not self.pending:
+                    if self.stopping and self._idle() and not self._in_flight():
+                        self.cv.notify_all()
                         return
                     self.cv.wait(0.05)
-                    batch = self._take()
-            self._run(slot, batch)
+                    batch = self._take(lane)
+                self._batch_ids += 1
+                bid = self._batch_ids
+                for q in batch:
+                    q.owner = bid
+                self._running[slot] = bid
+            self._run(slot, lane, bid, batch)
 
-    def _run(self, slot, batch):
+    def _in_flight(self):
+        # a running batch of the express lane may still move queries to the bulk lane
+        return any(b is not None for b in self._running.values())
+
+    def _complete(self, q, count, fp, status, t):
+        """Called with the lock held."""
+        if q.done.is_set():
+            return
+        q.count, q.fp, q.status = count, fp, status
+        q.t_done = t
+        q.done.set()
+
+    def _settle(self, lane, q, res, status, cut, t, dms=-1.0):
+        """A reported pair: complete it, or move it to the bulk lane when the
+        express lane's budget (not its own) cut it off.  Lock held."""
+        if q.adhoc is None and status in ("ok", "overflow") and dms >= 0:
+            self.service_ms[(q.graph, q.k)] = dms
+        if lane == "express" and q.est is not None:
+            if status in ("ok", "overflow"):
+                self.light_max[q.k] = max(self.light_max.get(q.k, -1.0), q.est)
+            elif status == "dnf" and cut:
+                self.heavy_min[q.k] = min(self.heavy_min.get(q.k, float("inf")), q.est)
+        if status == "dnf" and lane == "express" and cut:
+            if q.adhoc is None:
+                self.heavy.add((q.graph, q.k))
+            q.lane = "bulk"
+            q.moves += 1
+            self.demoted += 1
+            self.queues["bulk"].append(q)
+            self.cv.notify_all()
+            return
+        self._complete(q, res[0], res[1], status, t)
+
+    def _costs(self, live, graphs):
+        """Scheduling order of a batch: pairs measured before by their last
+        service time, then the others by the library's cost bound."""
+        out = []
+        for q, g in zip(live, graphs):
+            ms = self.service_ms.get((q.graph, q.k)) if q.adhoc is None else None
+            if ms is not None:
+                out.append(ms)
+            else:
+                est = self.backend.estimate(g, min(q.k, 5)) if hasattr(self.backend, "estimate") else 0.0
+                out.append(1e9 + math.log10(1.0 + est))
+        return out
+
+    def _release(self, bid, batch):
+        """Frees the ad-hoc graphs of finished queries this batch owns."""
+        for q in batch:
+            if q.done.is_set() and q.owner == bid and not q.released:
+                q.released = True
+                if q.handle is not None:
+                    self.backend.free(q.handle)
+                    q.handle = None
+                with self.cv:
+                    if q.admitted:
+                        self.mem_used -= q.need_bytes()
+
+    def _run(self, slot, lane, bid, batch):
         t_start = self.now()
-        adhoc = []
-        graphs = []
-        try:
-            for q in batch:
-                q.t_start = t_start
-                q.slot = slot
-                q.batch_size = len(batch)
-                if q.adhoc is not None:
-                    g = self.backend.orient(q.adhoc[0], q.adhoc[1], slot)
-                    adhoc.append(g)
-                    graphs.append(g)
-                else:
-                    graphs.append(self.pool[q.graph])
-            res, status, ms = self.backend.count_batch(slot, graphs, [q.k for q in batch],
-                                                       [q.deadline_ms for q in batch])
-        except Exception as e:  # reported per query; the server keeps running
-            self.errors.append(repr(e))
-            res = [(None, None)] * len(batch)
-            status = ["error"] * len(batch)
-            ms = 0.0
-        for g in adhoc:
-            self.backend.free(g)
-        t_end = self.now()
+        # queries whose latency budget ran out in the queue are not run
         with self.cv:
-            for q, (c, f), st in zip(batch, res, status):
-                q.count, q.fp, q.status = c, f, st
-                q.t_done = t_end
-                self.mem_used -= q.need_bytes()
-                q.done.set()
-            self.batches.append((slot, len(batch), t_start, t_end, ms))
+            for q in batch:
+                if q.deadline_ms and (t_start - q.t_arrival) * 1e3 >= q.deadline_ms:
+                    q.t_start = q.t_start if q.t_start is not None else t_start
+                    q.slot = slot
+                    self._complete(q, None, None, "dnf", t_start)
+            self.cv.notify_all()
+        live = [q for q in batch if not q.done.is_set()]
+        budgets, cut = [], []
+        for q in live:
+            rem = int(q.deadline_ms - (t_start - q.t_arrival) * 1e3) if q.deadline_ms else 0
+            rem = max(1, rem) if q.deadline_ms else 0
+            if lane == "express" and (rem == 0 or self.express_ms < rem):
+                budgets.append(self.express_ms)
+                cut.append(True)
+            else:
+                budgets.append(rem)
+                cut.append(False)
+        reported = [False] * len(live)
+        ms = 0.0
+        t_dev = t_start
+        if live:
+            try:
+                graphs = []
+                for q in live:
+                    if q.t_start is None:
+                        q.t_start = t_start
+                    q.slot = slot
+                    q.batch_size = len(live)
+                    if q.adhoc is not None:
+                        if q.handle is None:
+                            q.handle = self.backend.orient(q.adhoc[0], q.adhoc[1], slot)
+                        graphs.append(q.handle)
+                    else:
+                        graphs.append(self.pool[q.graph])
+                ks = [q.k for q in live]
+                t_dev = self.now()
+                if self.plain:
+                    res, status = [], []
+                    for g, k, b in zip(graphs, ks, budgets):
+                        r, st = self.backend.count_one(slot, g, k, b)
+                        res.append(r)
+                        status.append(st)
+                else:
+                    on_done = None
+                    if self.stream_results:
+                        def on_done(i, count, fp, st, dms=-1.0):
+                            t = self.now()
+                            with self.cv:
+                                reported[i] = True
+                                self._settle(lane, live[i], (count, fp), st, cut[i], t, dms)
+                    kw = {"on_done": on_done} if on_done is not None else {}
+                    kw["costs"] = self._costs(live, graphs)
+                    res, status, ms = self.backend.count_batch(slot, graphs, ks, budgets, **kw)
+            except Exception as e:  # reported per query; the server keeps running
+                self.errors.append(repr(e))
+                res = [(None, None)] * len(live)
+                status = ["error"] * len(live)
+            t_end = self.now()
+            with self.cv:
+                for i, q in enumerate(live):
+                    if not reported[i]:
+                        self._settle(lane, q, res[i], status[i], cut[i], t_end)
+        t_end = self.now()
+        self._release(bid, batch)
+        with self.cv:
+            self.batches.append((slot, len(live), t_start, t_end, ms, t_dev))
+            self._running[slot] = None
             self.cv.notify_all()
 
 
@@ -223,7 +452,10 @@ def replay(server: Server, queries, sleep=time.sleep, log=None):
         if log and (i + 1) % 500 == 0:
             log("serving: %d/%d submitted at t=%.2f s" % (i + 1, len(order), server.now()))
     for q in order:
-        q.done.wait()
+        while not q.done.wait(10.0):
+            if log:
+                log("serving: waiting, %d/%d done at t=%.1f s" % (
+                    sum(x.done.is_set() for x in order), len(order), server.now()))
 
 
 def summarize(queries, wall_s: float):

@@ -18,8 +18,11 @@ class FakeGraph:
 
 
 class FakeBackend:
-    def __init__(self, oracle, cost_fn, seconds_per_cost=1e-3, pool_bytes=0, mem_limit=None):
+    def __init__(self, oracle, cost_fn, seconds_per_cost=1e-3, pool_bytes=0, mem_limit=None,
+                 estimate_fn=None):
         self.oracle = oracle
+        if estimate_fn is not None:
+            self.estimate = estimate_fn
         self.cost_fn = cost_fn
         self.scale = seconds_per_cost
         self.lock = threading.Lock()
@@ -44,25 +47,37 @@ class FakeBackend:
         with self.lock:
             self.live -= g.nbytes
 
-    def count_batch(self, slot, graphs, ks, deadlines_ms):
+    def count_one(self, slot, g, k, budget_ms):
+        res, st, _ = self.count_batch(slot, [g], [k], [budget_ms])
+        return res[0], st[0]
+
+    def count_batch(self, slot, graphs, ks, deadlines_ms, on_done=None, costs=None):
+        """Runs the pairs one after another, cheapest first; with on_done
+        each pair is reported as soon as its simulated time has passed.  A
+        pair's budget runs from its own start."""
         with self.lock:
             self.active += 1
             self.max_active = max(self.max_active, self.active)
             self.calls.append((slot, len(graphs), time.perf_counter()))
-        res, st = [], []
+        n = len(graphs)
+        res, st = [None] * n, [None] * n
+        costs = [self.cost_fn(g, k) for g, k in zip(graphs, ks)]
         total = 0.0
-        for g, k, dl in zip(graphs, ks, deadlines_ms):
-            c = self.cost_fn(g, k)
+        for i in sorted(range(n), key=lambda i: costs[i]):
+            g, k, dl, c = graphs[i], ks[i], deadlines_ms[i], costs[i]
             if dl and c * self.scale * 1e3 > dl:
-                res.append((0, 0))
-                st.append("dnf")
-                total += dl / 1e3
-                continue
-            total += c * self.scale
-            cnt, fp = self.oracle.count(g.row_ptr, g.col, k, nthreads=1)
-            res.append((cnt, fp))
-            st.append("overflow" if cnt >= 1 << 64 else "ok")
-        time.sleep(total)
+                res[i], st[i] = (0, 0), "dnf"
+                dt = dl / 1e3
+            else:
+                cnt, fp = self.oracle.count(g.row_ptr, g.col, k, nthreads=1)
+                res[i], st[i] = (cnt, fp), ("overflow" if cnt >= 1 << 64 else "ok")
+                dt = c * self.scale
+            total += dt
+            if on_done is not None:
+                time.sleep(dt)
+                on_done(i, res[i][0], res[i][1], st[i], dt * 1e3)
+        if on_done is None:
+            time.sleep(total)
         with self.lock:
             self.active -= 1
         return res, st, total * 1e3

@@ -70,3 +70,41 @@ def test_graph_replays_repeat_eager(D):
         # eager work between replays
         D.count(G[rep], ks[rep])
         torch.cuda.synchronize()
+
+
+def test_stream_reports_every_pair_once(D, oracle_mod):
+    """dist_count_batch_stream: each pair is reported exactly once, with the
+    same result the batch returns and the oracle computes; graphs of every
+    width class, k = 1 and pairs with no deep-enough root included."""
+    import threading
+    graphs, ks = _small_batch(seed=13, count=40)
+    G = [D.orient(g.row_ptr, g.col) for g in graphs]
+    want = [oracle_mod.count(g.row_ptr, g.col, k) for g, k in zip(graphs, ks)]
+    seen = {}
+    me = threading.get_ident()
+
+    def on_done(i, c, f, st, dms):
+        assert threading.get_ident() == me
+        assert i not in seen
+        seen[i] = ((c, f), st)
+
+    for cfg in (D.config(), D.config(grid_pct=25, fingerprint=1), D.config(memo=0, chunk_work=64)):
+        seen.clear()
+        res, rc, st = D.count_batch_stream(G, ks, on_done, cfg=cfg)
+        assert rc in (D.OK, D.E_OVERFLOW)
+        assert res == want
+        assert sorted(seen) == list(range(len(G)))
+        for i in range(len(G)):
+            assert seen[i] == (want[i], st[i]), i
+
+
+def test_estimate_cost_orders_work(D):
+    g = gg.complete(40)
+    G = D.orient(g.row_ptr, g.col)
+    import math
+    # complete graph: out-degrees 0..39, cost = sum_d C(d, k-1) = C(40, k)
+    for k in (2, 3, 5, 8):
+        assert abs(D.estimate_cost(G, k) - math.comb(40, k)) <= 1e-9 * math.comb(40, k) + 1e-6
+    z = gg.empty(4)
+    e = D.orient(z.row_ptr, z.col)
+    assert D.estimate_cost(e, 3) == 0.0

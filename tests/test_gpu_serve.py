@@ -24,7 +24,7 @@ def test_served_equals_alone(D, oracle_mod):
     from paper_2502_00317_amd.serve import DeviceBackend, Query, Server, oriented_bytes, replay, summarize
     pool = [gg.chung_lu(int(n), 2.4, 12.0, None, [31, i], plants=[10, 12])
             for i, n in enumerate(np.geomspace(2000, 20000, 6))]
-    be = DeviceBackend(slots=2)
+    be = DeviceBackend(slots=2, grid_pcts=[40, 60], slot_cfgs=[{"budget_from_pair_start": 1}, {}])
     handles = {i: D.orient(g.row_ptr, g.col) for i, g in enumerate(pool)}
     pool_bytes = sum(oriented_bytes(g.n, g.m) for g in pool)
     rng = np.random.default_rng(5)
@@ -38,7 +38,8 @@ def test_served_equals_alone(D, oracle_mod):
         else:
             qs.append(Query(qid=i, k=k, t_arrival=float(t[i]), graph=int(rng.integers(0, len(pool))),
                             deadline_ms=30000))
-    srv = Server(be, handles, slots=2, pool_bytes=pool_bytes, mem_limit=pool_bytes + (64 << 20))
+    srv = Server(be, handles, slots=2, pool_bytes=pool_bytes, mem_limit=pool_bytes + (64 << 20),
+                 express_ms=5)
     srv.start()
     replay(srv, qs)
     srv.stop()
@@ -46,6 +47,7 @@ def test_served_equals_alone(D, oracle_mod):
     print(s, flush=True)
     assert s["completed"] == len(qs), [q.status for q in qs if q.status != "ok"]
     assert len(srv.batches) < len(qs)  # queries were batched
+    print("moved to the bulk lane:", srv.demoted, flush=True)
     for q in qs:
         if q.adhoc is not None:
             G = D.orient(q.adhoc[0], q.adhoc[1])
@@ -71,3 +73,53 @@ def test_pair_budget_stops_only_that_pair(D, oracle_mod):
     assert res[1] == oracle_mod.count(light.row_ptr, light.col, 4)
     assert res[2] == oracle_mod.count(light.row_ptr, light.col, 5)
     assert ms < 5000
+
+
+def test_stream_budget_and_early_reports(D, oracle_mod):
+    """Streaming: light pairs are reported before the heavy pair is stopped
+    by its budget; the heavy pair is reported as cancelled."""
+    import time
+    heavy = gg.gnp(300, 0.9, 3)
+    light = gg.small_powerlaw()
+    Gh = D.orient(heavy.row_ptr, heavy.col)
+    Gl = D.orient(light.row_ptr, light.col)
+    t0 = time.perf_counter()
+    when = {}
+
+    def on_done(i, c, f, st, dms):
+        when[i] = (time.perf_counter() - t0, st)
+
+    res, rc, st = D.count_batch_stream([Gh, Gl, Gl], [20, 4, 5], on_done,
+                                       deadlines_ms=[400, 400, 400])
+    assert st == [D.E_CANCELLED, D.OK, D.OK]
+    assert res[1] == oracle_mod.count(light.row_ptr, light.col, 4)
+    assert res[2] == oracle_mod.count(light.row_ptr, light.col, 5)
+    assert when[0][1] == D.E_CANCELLED and when[1][1] == D.OK
+    assert when[1][0] < when[0][0] and when[2][0] < when[0][0]
+
+
+def test_budget_origin_pair_or_batch(D, oracle_mod):
+    """budget_from_pair_start: with the heavy pair scheduled first, light
+    pairs still get their whole budget when it runs from their own start,
+    and none of it when it runs from the batch start."""
+    heavy = gg.gnp(300, 0.9, 3)
+    light = gg.small_powerlaw()
+    Gh = D.orient(heavy.row_ptr, heavy.col)
+    Gl = D.orient(light.row_ptr, light.col)
+    want4 = oracle_mod.count(light.row_ptr, light.col, 4)
+    want5 = oracle_mod.count(light.row_ptr, light.col, 5)
+    got = {}
+
+    def on_done(i, c, f, st, dms):
+        got[i] = (st, dms)
+
+    cfg = D.config(budget_from_pair_start=1)
+    res, rc, st = D.count_batch_stream([Gh, Gl, Gl], [20, 4, 5], on_done, cfg=cfg,
+                                       deadlines_ms=[300, 300, 300], costs=[1.0, 1e6, 1e6])
+    assert st == [D.E_CANCELLED, D.OK, D.OK]
+    assert res[1] == want4 and res[2] == want5
+    assert 250 <= got[0][1] < 5000          # the heavy pair ran about its budget
+    assert 0 <= got[1][1] < 300 and 0 <= got[2][1] < 300
+    res, rc, st = D.count_batch_stream([Gh, Gl, Gl], [20, 4, 5], on_done, cfg=D.config(),
+                                       deadlines_ms=[300, 300, 300], costs=[1.0, 1e6, 1e6])
+    assert st == [D.E_CANCELLED, D.E_CANCELLED, D.E_CANCELLED]

@@ -30,6 +30,21 @@ def test_weight_matches_python_definition(oracle_mod):
     assert all(1 <= R.g(v) < R.P61 for v in range(1000))
 
 
+def test_weight_published_splitmix64_outputs(oracle_mod):
+    """The mixing step is SplitMix64: from state 0 its first three outputs
+    are the published 0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4,
+    0x06c45d188009454f (state advances by the golden gamma before mixing).
+    g(v) mixes 0x44495354 ^ v, so v = (i * gamma) ^ 0x44495354 reproduces
+    output i + 1."""
+    gamma = 0x9E3779B97F4A7C15
+    published = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    for i, z in enumerate(published):
+        v = ((i * gamma) & R.MASK64) ^ 0x44495354
+        if v >= 1 << 63:
+            v -= 1 << 64
+        assert oracle_mod.weight(v) == 1 + z % (R.P61 - 1)
+
+
 # ---- worked example (Figure 2, Table 2, Examples 3 and 5) ------------------
 
 def test_fig2_fixture_reproduces_table2():

@@ -94,3 +94,133 @@ def test_deadline_dnf_does_not_stop_the_batch(oracle_mod):
     assert [q.status for q in qs] == ["dnf", "ok", "ok"]
     s = summarize(qs, 1.0)
     assert s["dnf"] == 1 and s["completed"] == 2
+
+
+def test_streamed_completion_cheap_first(oracle_mod):
+    """A cheap query batched with an expensive one completes when its own
+    result is known, not when the batch ends; results stay exact."""
+    graphs, handles = _pool(2)
+    cost = lambda g, k: 200.0 if k == 6 else 1.0
+    be = FakeBackend(oracle_mod, cost, seconds_per_cost=1e-3)
+    srv = Server(be, handles, slots=1)
+    qs = [Query(qid=0, k=6, t_arrival=0.0, graph=1),
+          Query(qid=1, k=3, t_arrival=0.0, graph=0),
+          Query(qid=2, k=4, t_arrival=0.0, graph=0)]
+    srv.start()
+    replay(srv, qs)
+    srv.stop()
+    assert all(q.status == "ok" for q in qs)
+    for q in qs:
+        g = graphs[q.graph]
+        assert (q.count, q.fp) == oracle_mod.count(g.row_ptr, g.col, q.k)
+    if len(be.calls) == 1:  # all three went into one batch
+        assert qs[1].t_done < qs[0].t_done - 0.1 and qs[2].t_done < qs[0].t_done - 0.1
+    # without streaming every query of a batch ends with the batch
+    srv2 = Server(FakeBackend(oracle_mod, cost, seconds_per_cost=1e-3), handles, slots=1,
+                  stream_results=False)
+    qs2 = [Query(qid=q.qid, k=q.k, t_arrival=0.0, graph=q.graph) for q in qs]
+    srv2.start()
+    replay(srv2, qs2)
+    srv2.stop()
+    if len(srv2.batches) == 1:
+        assert len({q.t_done for q in qs2}) == 1
+
+
+def test_express_lane_moves_heavy_queries(oracle_mod):
+    """Slot 0 is an express lane with a 20 ms device budget.  A heavy query
+    cut off there moves to the bulk lane and still completes exactly; a later
+    query with the same (graph, k) goes to the bulk lane directly; light
+    queries are not held behind heavy ones."""
+    graphs, handles = _pool(3)
+    cost = lambda g, k: 150.0 if k == 6 else 1.0      # 150 ms vs 1 ms
+    be = FakeBackend(oracle_mod, cost, seconds_per_cost=1e-3)
+    srv = Server(be, handles, slots=2, express_ms=20)
+    qs = [Query(qid=0, k=6, t_arrival=0.0, graph=1, deadline_ms=5000)]
+    qs += [Query(qid=1 + i, k=3 + i % 3, t_arrival=0.01 * i, graph=i % 3, deadline_ms=5000) for i in range(20)]
+    qs += [Query(qid=50, k=6, t_arrival=0.5, graph=1, deadline_ms=5000)]
+    srv.start()
+    replay(srv, qs)
+    srv.stop()
+    for q in qs:
+        assert q.status == "ok", (q.qid, q.status)
+        g = graphs[q.graph]
+        assert (q.count, q.fp) == oracle_mod.count(g.row_ptr, g.col, q.k)
+    assert qs[0].moves == 1 and qs[0].lane == "bulk"
+    assert qs[-1].moves == 0 and qs[-1].lane == "bulk"     # known heavy: bulk lane directly
+    assert (1, 6) in srv.heavy and srv.demoted == 1
+    light = [q.latency for q in qs[1:-1]]
+    assert max(light) < 0.12, light                          # never waited for the 150 ms query
+
+
+def test_express_moves_keep_adhoc_memory_once(oracle_mod):
+    graphs, handles = _pool(1)
+    pool_bytes = sum(h.nbytes for h in handles.values())
+    a = gg.chung_lu(800, 2.5, 8.0, None, [21, 0])
+    cost = lambda g, k: 100.0 if g.n == a.n else 1.0
+    be = FakeBackend(oracle_mod, cost, seconds_per_cost=1e-3, pool_bytes=pool_bytes)
+    srv = Server(be, handles, slots=3, express_ms=10, pool_bytes=pool_bytes)
+    qs = [Query(qid=0, k=4, t_arrival=0.0, adhoc=(a.row_ptr, a.col), deadline_ms=5000),
+          Query(qid=1, k=3, t_arrival=0.0, graph=0, deadline_ms=5000)]
+    srv.start()
+    replay(srv, qs)
+    srv.stop()
+    assert [q.status for q in qs] == ["ok", "ok"]
+    assert qs[0].moves == 1
+    assert (qs[0].count, qs[0].fp) == oracle_mod.count(a.row_ptr, a.col, 4)
+    assert srv.mem_used == pool_bytes and be.live == pool_bytes   # oriented once, freed once
+
+
+def test_plain_mode_one_query_at_a_time(oracle_mod):
+    graphs, handles = _pool(2)
+    be = FakeBackend(oracle_mod, _cost, seconds_per_cost=1e-3)
+    srv = Server(be, handles, slots=1, plain=True)
+    qs = [Query(qid=i, k=3 + i % 4, t_arrival=0.0, graph=i % 2) for i in range(8)]
+    srv.start()
+    replay(srv, qs)
+    srv.stop()
+    assert all(b[1] == 1 for b in srv.batches) and len(srv.batches) == 8
+    for q in qs:
+        g = graphs[q.graph]
+        assert (q.count, q.fp) == oracle_mod.count(g.row_ptr, g.col, q.k)
+
+
+def test_budget_spent_in_queue_is_dnf(oracle_mod):
+    graphs, handles = _pool(1)
+    be = FakeBackend(oracle_mod, lambda g, k: 300.0, seconds_per_cost=1e-3)
+    srv = Server(be, handles, slots=1, max_batch=1)
+    qs = [Query(qid=0, k=3, t_arrival=0.0, graph=0, deadline_ms=1000),
+          Query(qid=1, k=4, t_arrival=0.0, graph=0, deadline_ms=100)]
+    srv.start()
+    replay(srv, qs)
+    srv.stop()
+    assert qs[0].status == "ok" and qs[1].status == "dnf"
+
+
+def test_route_by_learned_threshold(oracle_mod):
+    """Once a query with estimate E was cut off in the express lane, a new
+    (graph, k) with an estimate above E goes to the bulk lane on arrival;
+    one below the largest completed estimate stays in the express lane."""
+    graphs, handles = _pool(4)              # n = 200, 350, 500, 650
+    cost = lambda g, k: 120.0 if g.n >= 500 else 1.0
+    be = FakeBackend(oracle_mod, cost, seconds_per_cost=1e-3, estimate_fn=lambda g, k: float(g.n))
+    srv = Server(be, handles, slots=2, express_ms=20)
+    srv.start()
+    first = [Query(qid=0, k=4, t_arrival=0.0, graph=2, deadline_ms=5000),
+             Query(qid=1, k=4, t_arrival=0.0, graph=0, deadline_ms=5000)]
+    replay(srv, first)
+    assert first[0].moves == 1 and first[1].lane == "express"
+    assert srv.heavy_min[4] == 500.0 and srv.light_max[4] == 200.0
+    t = srv.now()
+    second = [Query(qid=2, k=4, t_arrival=t, graph=3, deadline_ms=5000),   # 650 >= 500: bulk
+              Query(qid=3, k=4, t_arrival=t, graph=1, deadline_ms=5000),   # 350: express
+              Query(qid=4, k=5, t_arrival=t, graph=3, deadline_ms=5000)]   # k = 5 not learned yet
+    replay(srv, second)
+    srv.stop()
+    assert second[0].lane == "bulk" and second[0].moves == 0
+    assert second[1].lane == "express"
+    assert second[2].moves == 1
+    assert srv.routed_bulk == 1
+    for q in first + second:
+        assert q.status == "ok"
+        g = graphs[q.graph]
+        assert (q.count, q.fp) == oracle_mod.count(g.row_ptr, g.col, q.k)

@@ -62,6 +62,8 @@ def _load():
     lib.oracle_count_roots.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int,
                                        i32p, ctypes.c_int64, ctypes.c_int, u64p]
     lib.oracle_count_roots.restype = ctypes.c_int
+    lib.oracle_pivot_count_roots.argtypes = lib.oracle_count_roots.argtypes
+    lib.oracle_pivot_count_roots.restype = ctypes.c_int
     lib.oracle_list.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int,
                                 i32p, ctypes.c_int64]
     lib.oracle_list.restype = ctypes.c_int64
@@ -119,6 +121,25 @@ def count_roots(row_ptr, col, k: int, roots, nthreads: int = 0):
         out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
     if rc != 0:
         raise ValueError("oracle_count_roots rejected the input (rc=%d)" % rc)
+    res = []
+    for i in range(nr):
+        res.append((int(out[3 * i]) | (int(out[3 * i + 1]) << 64),
+                    int(out[3 * i + 2])))
+    return res
+
+
+def pivot_count_roots(row_ptr, col, k: int, roots, nthreads: int = 0):
+    """The same per-root (count, fp) as count_roots, by pivoting (secondary
+    reference for dense neighbourhoods; k <= 16)."""
+    rp, rpp, c, cp = _csr(row_ptr, col)
+    r, rptr = _i32(roots if len(roots) else np.zeros(1, np.int32))
+    nr = len(roots)
+    out = np.zeros(3 * max(nr, 1), dtype=np.uint64)
+    rc = _load().oracle_pivot_count_roots(
+        len(rp) - 1, rpp, cp, int(k), rptr, nr, int(nthreads),
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    if rc != 0:
+        raise ValueError("oracle_pivot_count_roots rejected the input (rc=%d)" % rc)
     res = []
     for i in range(nr):
         res.append((int(out[3 * i]) | (int(out[3 * i + 1]) << 64),

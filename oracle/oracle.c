@@ -482,3 +482,141 @@ int32_t oracle_degeneracy(int32_t n, const int32_t* row_ptr, const int32_t* col,
   free(deg); free(gone); free(heap);
   return delta;
 }
+
+/* ---- secondary reference: pivot-based per-root counting --------------- */
+
+typedef struct {
+  int k;
+  int32_t d;              /* members of the root's out-neighbourhood */
+  unsigned char* adj;     /* d x d adjacency of G[N+(root)] */
+  uint64_t* w;            /* g() of each member */
+  int32_t* buf;           /* candidate lists, one row of d per depth */
+  unsigned char* gone;    /* members excluded by an earlier sibling */
+  uint64_t* piv;          /* g() of the pivots on the current path */
+  u128 count;
+  uint64_t fp;
+} pivot_t;
+
+static u128 binom_u128(int q, int r) {
+  if (r < 0 || r > q) return 0;
+  u128 c = 1;
+  for (int i = 0; i < r; ++i) c = c * (u128)(q - i) / (u128)(i + 1);
+  return c;
+}
+
+/* S: candidate members (all adjacent to every held and pivot vertex so far);
+ * h held vertices with weight product fh; q pivots in t->piv[0..q). */
+static void pivot_rec(pivot_t* t, const int32_t* S, int32_t ns, int h, int q,
+                      uint64_t fh, int depth) {
+  if (h > t->k || h + q + ns < t->k) return;
+  if (h == t->k) {  /* only the held set itself has exactly k vertices */
+    t->count += 1;
+    t->fp = add_p(t->fp, fh);
+    return;
+  }
+  if (ns == 0) {
+    const int need = t->k - h;  /* pivots to add */
+    if (need > q) return;
+    t->count += binom_u128(q, need);
+    uint64_t e[17] = {1};       /* elementary symmetric sums of pivot weights */
+    for (int j = 1; j <= need; ++j) e[j] = 0;
+    for (int i = 0; i < q; ++i)
+      for (int j = (i + 1 < need ? i + 1 : need); j >= 1; --j)
+        e[j] = add_p(e[j], mul_p(e[j - 1], t->piv[i]));
+    t->fp = add_p(t->fp, mul_p(fh, e[need]));
+    return;
+  }
+  const int32_t d = t->d;
+  /* pivot: the candidate with the most candidate neighbours */
+  int32_t p = S[0], best = -1;
+  for (int32_t i = 0; i < ns; ++i) {
+    int32_t c = 0;
+    for (int32_t j = 0; j < ns; ++j) c += t->adj[(size_t)S[i] * d + S[j]];
+    if (c > best) { best = c; p = S[i]; }
+  }
+  int32_t* next = t->buf + (size_t)(depth + 1) * d;
+  /* cliques avoiding every non-neighbour of p: p is optional (a pivot) */
+  int32_t nn = 0;
+  for (int32_t j = 0; j < ns; ++j)
+    if (t->adj[(size_t)p * d + S[j]]) next[nn++] = S[j];
+  t->piv[q] = t->w[p];
+  pivot_rec(t, next, nn, h, q + 1, fh, depth + 1);
+  /* cliques containing a non-neighbour v of p, split by the first such v */
+  for (int32_t i = 0; i < ns; ++i) {
+    const int32_t v = S[i];
+    if (v == p || t->adj[(size_t)p * d + v]) continue;
+    nn = 0;
+    for (int32_t j = 0; j < ns; ++j)
+      if (t->adj[(size_t)v * d + S[j]] && !t->gone[S[j]]) next[nn++] = S[j];
+    pivot_rec(t, next, nn, h + 1, q, mul_p(fh, t->w[v]), depth + 1);
+    t->gone[v] = 1;
+  }
+  for (int32_t i = 0; i < ns; ++i) t->gone[S[i]] = 0;
+}
+
+static int pivot_root(const dag_t* g, int k, int32_t r, u128* count, uint64_t* fp) {
+  const int64_t b = g->optr[r];
+  const int32_t d = (int32_t)(g->optr[r + 1] - b);
+  *count = 0;
+  *fp = 0;
+  if (k == 1) { *count = 1; *fp = g->gw[r]; return 0; }
+  if (d < k - 1) return 0;
+  pivot_t t;
+  memset(&t, 0, sizeof(t));
+  t.k = k;
+  t.d = d;
+  t.adj = (unsigned char*)calloc((size_t)d * d, 1);
+  t.w = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)d);
+  t.buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)d * (size_t)(d + 2));
+  t.gone = (unsigned char*)calloc((size_t)d, 1);
+  t.piv = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(d + 1));
+  int err = !t.adj || !t.w || !t.buf || !t.gone || !t.piv;
+  if (!err) {
+    /* local ids: position in the (sorted) out-list of r */
+    for (int32_t i = 0; i < d; ++i) {
+      const int32_t a = g->ocol[b + i];
+      t.w[i] = g->gw[a];
+      /* neighbours of a of higher rank that are members too: merge */
+      int64_t x = g->optr[a], xe = g->optr[a + 1];
+      int32_t j = i + 1;
+      while (x < xe && j < d) {
+        if (g->ocol[x] < g->ocol[b + j]) ++x;
+        else if (g->ocol[x] > g->ocol[b + j]) ++j;
+        else {
+          t.adj[(size_t)i * d + j] = t.adj[(size_t)j * d + i] = 1;
+          ++x; ++j;
+        }
+      }
+    }
+    for (int32_t i = 0; i < d; ++i) t.buf[i] = i;
+    pivot_rec(&t, t.buf, d, 1, 0, g->gw[r], 0);
+    *count = t.count;
+    *fp = t.fp;
+  }
+  free(t.adj); free(t.w); free(t.buf); free(t.gone); free(t.piv);
+  return err;
+}
+
+int oracle_pivot_count_roots(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                             int k, const int32_t* roots, int64_t nroots,
+                             int nthreads, uint64_t* out) {
+  if (k < 1 || k > 16 || n < 0 || !out || nroots < 0) return 1;
+  if (oracle_validate(n, row_ptr, col)) return 1;
+  for (int64_t i = 0; i < nroots; ++i)
+    if (roots[i] < 0 || roots[i] >= n) return 1;
+  dag_t d;
+  if (build_dag(n, row_ptr, col, &d)) { free_dag(&d); return 1; }
+  int err = 0;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(|| : err)
+  for (int64_t i = 0; i < nroots; ++i) {
+    u128 c;
+    uint64_t f;
+    if (pivot_root(&d, k, d.rank[roots[i]], &c, &f)) err = 1;
+    out[3 * i + 0] = (uint64_t)c;
+    out[3 * i + 1] = (uint64_t)(c >> 64);
+    out[3 * i + 2] = f;
+  }
+  free_dag(&d);
+  return err;
+}

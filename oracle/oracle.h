@@ -84,6 +84,21 @@ int32_t oracle_degeneracy(int32_t n, const int32_t* row_ptr, const int32_t* col,
  * vertices are sorted by (degree ascending, id ascending). */
 int oracle_degree_rank(int32_t n, const int32_t* row_ptr, int32_t* rank);
 
+/* Secondary reference: the same per-root results as oracle_count_roots
+ * (cliques whose minimum under the (degree, id) order is roots[i]), computed
+ * by pivoting instead of enumeration (Jain and Seshadhri, "The Power of
+ * Pivoting for Exact Clique Counting", WSDM 2020 -- the pivot-based exact
+ * counter the paper cites among related work).  Each clique of a root's
+ * out-neighbourhood is represented once in a tree of (held, pivot) sets, so
+ * dense neighbourhoods are counted in closed form: a leaf with h held and q
+ * pivot vertices holds C(q, k - h) k-cliques, whose fingerprint sum is
+ * prod(g(held)) * e_{k-h}(g(pivots)).  Used where enumeration cannot finish
+ * (dense cores at k = 7, 9); pinned against oracle_count_roots, brute force
+ * and closed forms.  k must be in 1..16. */
+int oracle_pivot_count_roots(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                             int k, const int32_t* roots, int64_t nroots,
+                             int nthreads, uint64_t* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,133 @@
+"""Parity at full size, in the launch configuration the benchmark times.
+
+The one-large-graph workload (Chung-Lu n = 10^6, exponent 2.2, mean degree
+20, cap 5,000, 200 planted K30) has ~5e16 9-cliques: the oracle cannot
+enumerate them, but it can recount single roots.  Each test runs the whole
+graph on the GPU with per-root output, checks that the per-root results add
+up to the total of the plain call (the benchmark's call, no per-root
+output), and compares seeded samples of roots one by one: roots whose
+search the enumerating oracle finishes quickly (C(d+, k-1) below a bound),
+and the dense core (the heaviest roots and a sample of roots with d+ >= 64)
+through the oracle's pivot-based counter.
+
+The batched workload (4,096 graphs) is checked on a seeded sample of pairs
+and on the 30 heaviest pairs through the pivot-based counter, and on the
+smallest sampled graphs through the enumerating oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2502_00317_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    from paper_2502_00317_amd import dist
+    dist.lib()
+    return dist
+
+
+@pytest.fixture(scope="module")
+def big(D):
+    g = gg.large_powerlaw()
+    G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+    # out-degrees under the (degree, id) order, by original id
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    ks = deg[src] * (g.n + 1) + src
+    kd = deg[g.col] * (g.n + 1) + g.col
+    outd = np.bincount(src[ks < kd], minlength=g.n)
+    return g, G, outd
+
+
+def _sample_roots(outd, k, bound, n_uniform, n_heavy, seed):
+    ok = np.array([d >= k - 1 and math.comb(int(d), k - 1) <= bound for d in outd])
+    cand = np.flatnonzero(ok)
+    rng = np.random.default_rng(seed)
+    pick = set(rng.choice(cand, size=min(n_uniform, len(cand)), replace=False).tolist())
+    heavy = cand[np.argsort(-outd[cand], kind="stable")[:n_heavy]]
+    pick.update(int(x) for x in heavy)
+    return np.array(sorted(pick), dtype=np.int32)
+
+
+@pytest.mark.parametrize("k,fp,bound", [(5, 1, 2e7), (7, 0, 2e6), (9, 0, 2e6)])
+def test_large_graph_sampled_roots(D, oracle_mod, big, k, fp, bound):
+    g, G, outd = big
+    cfg = D.config(fingerprint=fp)
+    print("full-size k=%d fp=%d" % (k, fp), flush=True)
+    total, tfp, rc = D.count(G, k, cfg=cfg)          # the benchmark's call
+    assert rc == D.OK
+    per = np.zeros(3 * g.n, np.uint64)
+    total2, tfp2, rc2 = D.count(G, k, cfg=cfg, per_root=per)
+    assert (total2, tfp2, rc2) == (total, tfp, rc)
+    lo = per[0::3].astype(object)
+    hi = per[1::3].astype(object)
+    assert int(sum(lo)) + (int(sum(hi)) << 64) == total
+    if fp:
+        P61 = (1 << 61) - 1
+        assert sum(int(x) for x in per[2::3]) % P61 == tfp
+
+    def check(roots, want):
+        for v, (wc, wf) in zip(roots, want):
+            got_c = int(per[3 * v]) | (int(per[3 * v + 1]) << 64)
+            assert got_c == wc, (int(v), int(outd[v]))
+            if fp:
+                assert int(per[3 * v + 2]) == wf, int(v)
+
+    # roots the plain oracle enumerates quickly
+    roots = _sample_roots(outd, k, bound, 3000, 40, 100 + k)
+    print("  %d enumerable roots, heaviest d+ = %d" % (len(roots), int(outd[roots].max())), flush=True)
+    check(roots, oracle_mod.count_roots(g.row_ptr, g.col, k, roots))
+    # the dense core: the 64 heaviest roots and 100 more with d+ >= 64, by
+    # the pivot-based reference (pinned against the enumerating oracle)
+    order = np.argsort(-outd, kind="stable")
+    rng = np.random.default_rng(200 + k)
+    mid = np.flatnonzero(outd >= 64)
+    heavy = np.unique(np.concatenate([order[:64], rng.choice(mid, size=min(100, len(mid)), replace=False)]))
+    heavy = heavy.astype(np.int32)
+    print("  %d dense-core roots, d+ up to %d" % (len(heavy), int(outd[heavy].max())), flush=True)
+    want = oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, heavy)
+    check(heavy, want)
+    print("  sampled roots hold %.3g of %.3g cliques" % (
+        sum(c for c, _ in want), float(total)), flush=True)
+
+
+def test_batched_workload_sampled_pairs(D, oracle_mod):
+    """Pairs of the full 4,096-pair batch, graph-captured as the benchmark
+    runs it, against the oracle."""
+    specs = gg.batch_specs()
+    graphs = gg.batch_graphs(specs)
+    ks = [s["k"] for s in specs]
+    G = [D.orient(g.row_ptr, g.col) for g in graphs]
+    res, rc, ms = D.count_batch(G, ks, cfg=D.config(), use_graph=True)
+    assert rc in (D.OK, D.E_OVERFLOW)
+    P61 = (1 << 61) - 1
+
+    def pivot_total(i):
+        g = graphs[i]
+        per = oracle_mod.pivot_count_roots(g.row_ptr, g.col, ks[i], np.arange(g.n, dtype=np.int32))
+        return sum(c for c, _ in per), sum(f for _, f in per) % P61
+
+    # a uniform seeded sample of 300 pairs and the 30 heaviest (largest
+    # planted cliques for their k), every root of each graph, through the
+    # pivot-based reference; the 40 smallest sampled graphs also through the
+    # enumerating oracle
+    rng = np.random.default_rng(44)
+    sample = sorted(rng.choice(len(specs), size=300, replace=False).tolist())
+    heavy = sorted(range(len(specs)), key=lambda i: -sum(math.comb(p, ks[i]) for p in specs[i]["plants"]))[:30]
+    print("batched: %d sampled + %d heaviest pairs" % (len(sample), len(heavy)), flush=True)
+    for i in sorted(set(sample) | set(heavy)):
+        assert res[i] == pivot_total(i), i
+    for i in sorted(sample, key=lambda i: specs[i]["n"])[:40]:
+        g = graphs[i]
+        assert res[i] == oracle_mod.count(g.row_ptr, g.col, ks[i]), i
+    # a replay of the captured launch gives the same results for every pair
+    res2, rc2, _ = D.count_batch(G, ks, cfg=D.config(), use_graph=True)
+    assert res2 == res

@@ -342,3 +342,53 @@ def test_validation_rejects(oracle_mod):
     assert not oracle_mod.validate(np.array([0, 1, 2], np.int32), np.array([2, 0], np.int32))  # out of range
     with pytest.raises(ValueError):
         oracle_mod.count(np.array([0, 1, 1], np.int32), np.array([1], np.int32), 3)
+
+
+# ---- secondary reference: pivot-based per-root counts ----------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pivot_matches_enumeration_random(oracle_mod, seed):
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(10, 70))
+    g = gg.gnp(n, float(rng.uniform(0.2, 0.8)), 900 + seed)
+    roots = np.arange(g.n, dtype=np.int32)
+    for k in range(1, 10):
+        assert oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, roots) == \
+            oracle_mod.count_roots(g.row_ptr, g.col, k, roots), k
+
+
+def test_pivot_matches_brute_force_and_fig2(oracle_mod):
+    fx = _fig2_fixture()
+    g = gg.fig2()
+    per = oracle_mod.pivot_count_roots(g.row_ptr, g.col, 4, np.arange(g.n, dtype=np.int32))
+    assert sum(c for c, _ in per) == fx["k4"]["count"] == 14     # the paper's printed count
+    for seed in range(4):
+        g = gg.gnp(18, 0.55, 950 + seed)
+        for k in range(2, 8):
+            per = oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, np.arange(g.n, dtype=np.int32))
+            tot = sum(c for c, _ in per)
+            fp = sum(f for _, f in per) % R.P61
+            cl = R.brute_cliques(g.row_ptr, g.col, k)
+            assert (tot, fp) == (len(cl), R.fingerprint(cl)), (seed, k)
+
+
+@pytest.mark.parametrize("n,k", [(40, 3), (70, 9), (120, 12), (200, 16)])
+def test_pivot_complete_graphs(oracle_mod, n, k):
+    g = gg.complete(n)
+    per = oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, np.arange(n, dtype=np.int32))
+    assert (sum(c for c, _ in per), sum(f for _, f in per) % R.P61) == R.complete_graph_result(n, k)
+
+
+@pytest.mark.parametrize("n,r,k", [(40, 6, 5), (60, 7, 5), (49, 7, 4), (30, 10, 8)])
+def test_pivot_turan_graphs(oracle_mod, n, r, k):
+    g = gg.turan(n, r)
+    per = oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, np.arange(n, dtype=np.int32))
+    assert (sum(c for c, _ in per), sum(f for _, f in per) % R.P61) == R.turan_result(n, r, k)
+
+
+def test_pivot_matches_enumeration_powerlaw(oracle_mod):
+    g = gg.small_powerlaw()
+    roots = np.arange(g.n, dtype=np.int32)
+    for k in (3, 5, 7, 9):
+        assert oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, roots) == \
+            oracle_mod.count_roots(g.row_ptr, g.col, k, roots), k

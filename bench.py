@@ -53,6 +53,10 @@ def parse():
                     help="device budget of the express lane (0: no express lane)")
     ap.add_argument("--serve-trace", default="", help="write per-query and per-batch serving records here")
     ap.add_argument("--serve-bulk-slots", type=int, default=1)
+    ap.add_argument("--serve-express-batch-ms", type=float, default=0.0,
+                    help="predicted device time of one express batch (0: 4 x express-ms)")
+    ap.add_argument("--serve-shed-frac", type=float, default=0.5,
+                    help="report a (graph, k) DNF at once after a bulk cut-off that ran this share of the budget")
     ap.add_argument("--serve-modes", default="served,plain")
     ap.add_argument("--serve-express-pct", type=int, default=40,
                     help="share of the device's wavefront slots for the express lane")
@@ -455,8 +459,9 @@ def run_serving(a, dist, torch, inputs, log):
            "pool_edges": sum(g.m for g in pool_graphs), "pool_gb": pool_bytes / 1e9,
            "mem_limit_gb": mem_limit / 1e9, "orient_pool_s": orient_s}
     nb = max(1, a.serve_bulk_slots)
-    bulk_pct = max(1, (100 - a.serve_express_pct) // nb)
-    modes = [("served", dict(slots=1 + nb, express_ms=a.serve_express_ms), [a.serve_express_pct] + [bulk_pct] * nb,
+    bulk_pct = max(1, (90 - a.serve_express_pct) // nb)  # 10% headroom: kernels of different widths co-reside
+    modes = [("served", dict(slots=1 + nb, express_ms=a.serve_express_ms, express_batch_ms=a.serve_express_batch_ms,
+                             shed_frac=a.serve_shed_frac), [a.serve_express_pct] + [bulk_pct] * nb,
               [{"budget_from_pair_start": 1}] + [{}] * nb),
              ("plain", dict(slots=1, plain=True), [100], [{}])]
     modes = [m for m in modes if m[0] in a.serve_modes.split(",")]
@@ -476,8 +481,9 @@ def run_serving(a, dist, torch, inputs, log):
                      "max_batch": max(sizes) if sizes else 0, "peak_mem_gb": srv.peak_mem / 1e9,
                      "error_msgs": srv.errors[:3]})
         if name == "served":
-            summ.update({"express_ms": srv.express_ms, "moved_to_bulk": srv.demoted,
-                         "routed_to_bulk": srv.routed_bulk, "heavy_keys": len(srv.heavy)})
+            summ.update({"express_ms": srv.express_ms, "express_batch_ms": srv.express_batch_ms,
+                         "moved_to_bulk": srv.demoted, "routed_to_bulk": srv.routed_bulk,
+                         "heavy_keys": len(srv.heavy), "shed": srv.shed, "shed_frac": srv.shed_frac})
         ans[name] = {(q.qid): (q.count, q.fp) for q in qs if q.status in ("ok", "overflow")}
         if a.serve_trace:
             with open(a.serve_trace + "." + name + ".json", "w") as f:

@@ -123,12 +123,19 @@ struct Params {
 // ---- per-wave memo table (Induced Subgraph Trie nodes, counting form) --------
 // Entry: [tag][key W words][cnt_lo][cnt_hi][fp]; tag = (root tag << 8) | l.
 
+// Keys are candidate sets read from LDS: P (W words), optionally cut to its
+// members >= x (x < 0: no cut), i.e. the trie node P & [x, inf).
+__device__ __forceinline__ u64 cut_mask(int x, int w) {
+  const int lo_b = w * 64;
+  return (x <= lo_b) ? ~0ull : (x >= lo_b + 64 ? 0ull : (~0ull << (x - lo_b)));
+}
+
 template <int W>
-__device__ __forceinline__ u64 memo_hash(u64 tag, const u64 (&key)[W]) {
+__device__ __forceinline__ u64 memo_hash(u64 tag, const u64* P, int x) {
   u64 h = tag * 0x9E3779B97F4A7C15ull;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    h ^= key[w];
+    h ^= P[w] & cut_mask(x, w);
     h *= 0xBF58476D1CE4E5B9ull;
     h ^= h >> 29;
   }
@@ -136,59 +143,77 @@ __device__ __forceinline__ u64 memo_hash(u64 tag, const u64 (&key)[W]) {
   return h;
 }
 
+// The wave's lanes cover (probe slot, entry word) pairs: every word of every
+// probed entry is loaded by its own lane in one round, so a lookup or an
+// insert costs one memory latency and each lane holds a single word.
+
+// Wave-collective lookup of the keys P & [cut_i, inf), i = 0..ncut-1, where
+// cut_i = cuts[i] (cuts == nullptr: one key, no cut).  Returns the smallest i
+// whose key is in the table (its count and fingerprint in lo, hi, fp), or -1.
 template <int W>
-__device__ __forceinline__ bool memo_find(const Params& p, u64* table, u64 tag, const u64 (&key)[W],
-                                          u64& lo, u64& hi, u64& fp) {
-  const int ES = W + 4;
-  u64 h = memo_hash<W>(tag, key);
-  u64 t[kMemoProbe];
-#pragma unroll
-  for (int i = 0; i < kMemoProbe; ++i) t[i] = ld_coherent(table + ((h + i) & p.memo_mask) * ES);
-#pragma unroll
-  for (int i = 0; i < kMemoProbe; ++i) {
-    if (t[i] != tag) continue;
-    const u64* e = table + ((h + i) & p.memo_mask) * ES;
-    bool eq = true;
-#pragma unroll
-    for (int w = 0; w < W; ++w) eq = eq && (ld_coherent(e + 1 + w) == key[w]);
-    if (eq) {
-      lo = ld_coherent(e + 1 + W);
-      hi = ld_coherent(e + 2 + W);
-      fp = ld_coherent(e + 3 + W);
-      return true;
+__device__ __forceinline__ int memo_find(const Params& p, const u64* table, u64 tag, const u64* P,
+                                         const uint16_t* cuts, int ncut, u64& lo, u64& hi, u64& fp) {
+  constexpr int ES = W + 4;
+  constexpr int GPR = kWave / ES;  // (key, slot) groups per round
+  const int lane = lane_id();
+  const int groups = ncut * kMemoProbe;
+  for (int g0 = 0; g0 < groups; g0 += GPR) {
+    const int gi = lane / ES, w = lane % ES, g = g0 + gi;
+    bool ok = false;
+    u64 v = 0;
+    if (gi < GPR && g < groups) {
+      const int i = g / kMemoProbe, t = g % kMemoProbe;
+      const int x = cuts ? (int)cuts[i] : -1;
+      const u64 h = memo_hash<W>(tag, P, x);
+      v = ld_coherent(table + ((h + (u64)t) & p.memo_mask) * ES + w);
+      ok = w > W || v == (w == 0 ? tag : (P[w - 1] & cut_mask(x, w - 1)));
+    }
+    const u64 b = __ballot(ok);
+    constexpr u64 kFull = (ES >= 64) ? ~0ull : ((1ull << ES) - 1);
+    for (int q = 0; q < GPR && g0 + q < groups; ++q) {
+      if (((b >> (q * ES)) & kFull) == kFull) {
+        lo = __shfl(v, q * ES + W + 1);
+        hi = __shfl(v, q * ES + W + 2);
+        fp = __shfl(v, q * ES + W + 3);
+        return (g0 + q) / kMemoProbe;
+      }
     }
   }
-  return false;
+  return -1;
 }
 
-// Called by one lane.  Reuses the slot holding the same key, else the
-// first slot not owned by the current root, else evicts the home slot.
+// Wave-collective insert of (tag, P & [x, inf)) -> (lo, hi, fp).  Reuses the
+// slot holding the same key, else the first slot not owned by the current
+// root, else evicts the home slot; the entry is written one word per lane.
 template <int W>
-__device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, u64 root_tag,
-                                         const u64 (&key)[W], u64 lo, u64 hi, u64 fp) {
-  const int ES = W + 4;
-  u64 h = memo_hash<W>(tag, key);
-  u64* slot = table + (h & p.memo_mask) * ES;
-  for (int i = 0; i < kMemoProbe; ++i) {
-    u64* e = table + ((h + i) & p.memo_mask) * ES;
-    u64 t = ld_coherent(e);
-    if (t == tag) {
-      bool eq = true;
-#pragma unroll
-      for (int w = 0; w < W; ++w) eq = eq && (ld_coherent(e + 1 + w) == key[w]);
-      if (eq) { slot = e; break; }
-    } else if ((t >> 8) != root_tag) {
-      slot = e;
-      break;
+__device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, u64 root_tag, const u64* P, int x,
+                                         u64 lo, u64 hi, u64 fp) {
+  constexpr int ES = W + 4;
+  constexpr int KS = W + 1;  // tag and key words
+  constexpr int GPR = kWave / KS;
+  const int lane = lane_id();
+  const u64 h = memo_hash<W>(tag, P, x);
+  int same = -1, free_slot = -1;
+  for (int g0 = 0; g0 < kMemoProbe; g0 += GPR) {
+    const int gi = lane / KS, w = lane % KS, t = g0 + gi;
+    bool ok = false, fr = false;
+    if (gi < GPR && t < kMemoProbe) {
+      const u64 v = ld_coherent(table + ((h + (u64)t) & p.memo_mask) * ES + w);
+      ok = v == (w == 0 ? tag : (P[w - 1] & cut_mask(x, w - 1)));
+      fr = w == 0 && (v >> 8) != root_tag;
+    }
+    const u64 b = __ballot(ok), bf = __ballot(fr);
+    constexpr u64 kFull = (KS >= 64) ? ~0ull : ((1ull << KS) - 1);
+    for (int q = 0; q < GPR && g0 + q < kMemoProbe; ++q) {
+      if (same < 0 && ((b >> (q * KS)) & kFull) == kFull) same = g0 + q;
+      if (free_slot < 0 && ((bf >> (q * KS)) & 1ull)) free_slot = g0 + q;
     }
   }
-#pragma unroll
-  for (int w = 0; w < W; ++w) slot[1 + w] = key[w];
-  slot[1 + W] = lo;
-  slot[2 + W] = hi;
-  slot[3 + W] = fp;
-  slot[0] = tag;
-  __threadfence_block();
+  const int pick = same >= 0 ? same : (free_slot >= 0 ? free_slot : 0);
+  if (lane < ES) {
+    u64 v = lane == 0 ? tag : (lane <= W ? (P[lane - 1] & cut_mask(x, lane - 1)) : (lane == W + 1 ? lo : (lane == W + 2 ? hi : fp)));
+    table[((h + (u64)pick) & p.memo_mask) * ES + lane] = v;
+  }
 }
 
 // Work units per root.  A root with more than 64 out-neighbours is cut into
@@ -514,7 +539,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           ++n_look;
           ++r_look;
           u64 a, b, c;
-          if (memo_find<W>(p, table, tag, Pr, a, b, c)) {
+          if (memo_find<W>(p, table, tag, s.stP + j * W, nullptr, 1, a, b, c) >= 0) {
             ++n_hit;
             ++r_hit;
             res_lo = a; res_hi = b; res_fp = c;
@@ -623,7 +648,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           res_lo = wave_sum(c_acc);
           res_hi = 0;
           res_fp = p.fingerprint ? wave_sum_p(f_acc) : 0;
-          if (memo_j && memo_live && j > 0 && lane == 0) memo_put<W>(p, table, tag, root_tag, Pr, res_lo, res_hi, res_fp);
+          if (memo_j && memo_live && j > 0) memo_put<W>(p, table, tag, root_tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
           if (memo_j && memo_live && j > 0) ++n_ins;
           __syncthreads();
           mode = FINISH;
@@ -657,7 +682,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             ++n_look;
             ++r_look;
             u64 a, b, c;
-            if (memo_find<W>(p, table, tag, Pr, a, b, c)) {
+            if (memo_find<W>(p, table, tag, s.stP + j * W, nullptr, 1, a, b, c) >= 0) {
               ++n_hit;
               ++r_hit;
               res_lo = a; res_hi = b; res_fp = c;
@@ -680,32 +705,17 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         }
         if (memo_j && memo_live && np >= 2 && j > 0) {
           // resume from the longest memoised proper prefix P & [m_i, inf),
-          // m_i the i-th smallest member, i = 1..kMemoProbe (one lane each)
-          int i = 1 + lane;
-          bool hit = false;
+          // m_i the i-th smallest member, i = 1..kMemoProbe, all probed at once
+          const int ncut = np - 1 < kMemoProbe ? np - 1 : kMemoProbe;
           u64 a = 0, b = 0, c = 0;
-          int x = 0;
-          if (lane < kMemoProbe && i < np) {
-            x = s.mem[i];
-            u64 key[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-              int lo_b = w * 64;
-              u64 msk = (x <= lo_b) ? ~0ull : (x >= lo_b + 64 ? 0ull : (~0ull << (x - lo_b)));
-              key[w] = Pr[w] & msk;
-            }
-            hit = memo_find<W>(p, table, tag, key, a, b, c);
-          }
-          u64 nl = (u64)__popcll(__ballot(lane < kMemoProbe && i < np));
-          n_look += nl;
-          r_look += nl;
-          u64 hb = __ballot(hit);
-          if (hb) {
-            int src = __ffsll((unsigned long long)hb) - 1;  // lowest lane = smallest member
-            int best = __shfl(x, src);
-            acc_lo = __shfl(a, src);
-            acc_hi = __shfl(b, src);
-            acc_fp = __shfl(c, src);
+          const int hi_ = memo_find<W>(p, table, tag, s.stP + j * W, s.mem + 1, ncut, a, b, c);
+          n_look += (u64)ncut;
+          r_look += (u64)ncut;
+          if (hi_ >= 0) {
+            const int best = s.mem[1 + hi_];
+            acc_lo = a;
+            acc_hi = b;
+            acc_fp = c;
             ++n_hit;
             ++r_hit;
             // children >= best are covered by the prefix
@@ -747,8 +757,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             u64 Pr[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) Pr[w] = s.stP[j * W + w];
-            if (lane == 0)
-              memo_put<W>(p, table, (root_tag << 8) | (u64)l, root_tag, Pr, res_lo, res_hi, res_fp);
+            memo_put<W>(p, table, (root_tag << 8) | (u64)l, root_tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
             ++n_ins;
           }
           __syncthreads();
@@ -784,14 +793,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         }
         if (s.stMemo[j] && memo_live && j > 0) {
           // trie node t_i = P & [x, inf) is now complete for l
-          u64 key[W];
-#pragma unroll
-          for (int w = 0; w < W; ++w) {
-            int lo_b = w * 64;
-            u64 msk = (x <= lo_b) ? ~0ull : (x >= lo_b + 64 ? 0ull : (~0ull << (x - lo_b)));
-            key[w] = s.stP[j * W + w] & msk;
-          }
-          if (lane == 0) memo_put<W>(p, table, (root_tag << 8) | (u64)l, root_tag, key, lo, hi, f);
+          memo_put<W>(p, table, (root_tag << 8) | (u64)l, root_tag, s.stP + j * W, x, lo, hi, f);
           ++n_ins;
         }
         __syncthreads();

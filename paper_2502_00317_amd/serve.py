@@ -161,6 +161,16 @@ class Server:
                   queries with the same (pool graph, k) go to the bulk lane
                   directly.  This is a two-level feedback queue: light
                   queries never wait behind heavy ones;
+    express_batch_ms -- an express batch takes queries, cheapest predicted
+                  first, while their predicted device times add up to at most
+                  this (a query never seen counts as express_ms), so an
+                  express batch stays short;
+    shed_frac  -- a (graph, k) that ran for at least shed_frac of the latency
+                  budget in the bulk lane and was cut off is reported DNF at
+                  once when it arrives again, without using the device; so is
+                  a new query whose estimate is at least the smallest such
+                  cut-off's for its k (unless a query with at least that
+                  estimate has completed in the bulk lane);
     plain      -- one query at a time through the per-graph call (the
                   baseline without batching);
     stream_results -- complete each query as soon as the device reports it,
@@ -170,7 +180,7 @@ class Server:
     def __init__(self, backend, pool_handles: dict, slots: int = 2,
                  mem_limit: int = 1 << 62, pool_bytes: int = 0, max_batch: int = 4096,
                  clock=time.perf_counter, stream_results: bool = True, express_ms: int = 0,
-                 plain: bool = False):
+                 plain: bool = False, express_batch_ms: float = 0.0, shed_frac: float = 0.0):
         self.stream_results = stream_results
         self.pool_bytes = pool_bytes
         self.backend = backend
@@ -183,6 +193,12 @@ class Server:
         self.plain = plain
         self.clock = clock
         self.express_ms = express_ms if (express_ms > 0 and slots >= 2 and not plain) else 0
+        self.express_batch_ms = express_batch_ms if express_batch_ms > 0 else 4.0 * self.express_ms
+        self.shed_frac = shed_frac
+        self.bulk_cut_ms = {}  # (pool graph, k) -> longest device time before a bulk cut-off
+        self.bulk_heavy_min = {}  # k -> smallest estimate cut off in the bulk lane (hopeless)
+        self.bulk_light_max = {}  # k -> largest estimate completed in the bulk lane
+        self.shed = 0
         self.lanes = (["express"] + ["bulk"] * (slots - 1)) if self.express_ms else ["bulk"] * slots
         self.t0 = None
         self.queues = {"express": collections.deque(), "bulk": collections.deque()}
@@ -221,6 +237,16 @@ class Server:
             q.est = self.backend.estimate(self.pool[q.graph], min(q.k, 5))
         return q.est
 
+    def _hopeless(self, q):
+        """Known or predicted to need more than its budget.  Lock held."""
+        if not self.shed_frac or q.adhoc is not None or not q.deadline_ms:
+            return False
+        key = (q.graph, q.k)
+        if key in self.bulk_cut_ms:
+            return self.bulk_cut_ms[key] >= self.shed_frac * q.deadline_ms
+        est, hmin = q.est, self.bulk_heavy_min.get(q.k)
+        return est is not None and hmin is not None and est >= hmin and est > self.bulk_light_max.get(q.k, -1.0)
+
     def _route(self, q):
         """express or bulk.  A (graph, k) cut off in the express lane before
         goes to the bulk lane.  Otherwise a monotone threshold per k: the
@@ -242,6 +268,12 @@ class Server:
         if self.express_ms and q.adhoc is None:
             self._estimate(q)  # outside the lock: a library call
         with self.cv:
+            if self._hopeless(q):
+                q.lane = "shed"
+                self.shed += 1
+                self._complete(q, None, None, "dnf", self.now())
+                self.cv.notify_all()
+                return q
             q.lane = self._route(q)
             if q.lane == "bulk" and self.express_ms:
                 self.routed_bulk += 1
@@ -266,8 +298,19 @@ class Server:
         taken = []
         keep = collections.deque()
         pending = self.queues[lane]
+        budget = None
+        if lane == "express" and self.express_ms:
+            # cheapest predicted first, while the predictions fit the batch budget
+            pending = collections.deque(sorted(pending, key=self._predict_ms))
+            budget = self.express_batch_ms
         while pending and len(taken) < self.max_batch:
             q = pending.popleft()
+            if budget is not None:
+                c = self._predict_ms(q)
+                if taken and c > budget:
+                    keep.append(q)
+                    continue
+                budget -= c
             if q.admitted:  # moved here from the express lane; memory held
                 taken.append(q)
                 continue
@@ -324,6 +367,13 @@ class Server:
         express lane's budget (not its own) cut it off.  Lock held."""
         if q.adhoc is None and status in ("ok", "overflow") and dms >= 0:
             self.service_ms[(q.graph, q.k)] = dms
+        if q.adhoc is None and lane == "bulk" and status == "dnf" and dms >= 0:
+            key = (q.graph, q.k)
+            self.bulk_cut_ms[key] = max(self.bulk_cut_ms.get(key, 0.0), dms)
+            if q.est is not None and q.deadline_ms and dms >= self.shed_frac * q.deadline_ms:
+                self.bulk_heavy_min[q.k] = min(self.bulk_heavy_min.get(q.k, float("inf")), q.est)
+        if q.adhoc is None and lane == "bulk" and status in ("ok", "overflow") and q.est is not None:
+            self.bulk_light_max[q.k] = max(self.bulk_light_max.get(q.k, -1.0), q.est)
         if lane == "express" and q.est is not None:
             if status in ("ok", "overflow"):
                 self.light_max[q.k] = max(self.light_max.get(q.k, -1.0), q.est)
@@ -339,6 +389,10 @@ class Server:
             self.cv.notify_all()
             return
         self._complete(q, res[0], res[1], status, t)
+
+    def _predict_ms(self, q):
+        ms = self.service_ms.get((q.graph, q.k)) if q.adhoc is None else None
+        return ms if ms is not None else float(self.express_ms)
 
     def _costs(self, live, graphs):
         """Scheduling order of a batch: pairs measured before by their last

@@ -224,3 +224,39 @@ def test_route_by_learned_threshold(oracle_mod):
         assert q.status == "ok"
         g = graphs[q.graph]
         assert (q.count, q.fp) == oracle_mod.count(g.row_ptr, g.col, q.k)
+
+
+def test_express_batches_bounded_by_predicted_time(oracle_mod):
+    """An express batch takes never-seen queries only while their predicted
+    time (express_ms each) fits express_batch_ms."""
+    graphs, handles = _pool(3)
+    be = FakeBackend(oracle_mod, lambda g, k: 2.0, seconds_per_cost=1e-3)
+    srv = Server(be, handles, slots=2, express_ms=10, express_batch_ms=30)
+    qs = [Query(qid=i, k=3 + i % 5, t_arrival=0.0, graph=i % 3, deadline_ms=10000) for i in range(12)]
+    srv.start()
+    replay(srv, qs)
+    srv.stop()
+    assert all(q.status == "ok" for q in qs)
+    express = [b for b in srv.batches if b[0] == 0 and b[1] > 0]
+    assert max(b[1] for b in express) <= 3
+
+
+def test_shed_queries_known_to_exceed_budget(oracle_mod):
+    """A (graph, k) cut off in the bulk lane after running for at least
+    shed_frac of the budget is reported DNF at once when it comes again."""
+    graphs, handles = _pool(2)
+    cost = lambda g, k: 10000.0 if k == 8 else 1.0
+    be = FakeBackend(oracle_mod, cost, seconds_per_cost=1e-3)
+    srv = Server(be, handles, slots=2, express_ms=10, shed_frac=0.5)
+    srv.start()
+    first = [Query(qid=0, k=8, t_arrival=0.0, graph=1, deadline_ms=300)]
+    replay(srv, first)
+    t = srv.now()
+    second = [Query(qid=1, k=8, t_arrival=t, graph=1, deadline_ms=300),
+              Query(qid=2, k=3, t_arrival=t, graph=1, deadline_ms=300)]
+    replay(srv, second)
+    srv.stop()
+    assert first[0].status == "dnf" and first[0].moves == 1
+    assert second[0].status == "dnf" and second[0].lane == "shed" and srv.shed == 1
+    assert second[0].latency < 0.05
+    assert second[1].status == "ok"

@@ -46,12 +46,12 @@ __device__ __forceinline__ u64 ld_coherent(const u64* p) {
 }
 
 // ---- LDS layout -------------------------------------------------------------
-// u64 part: A (D*W), gl (D), per-level stacks, R (W).  Then a union of the
+// u64 part: A (D*W), gl (D, only with fingerprints), per-level stacks, R (W).  Then a union of the
 // arrays used only while G_u is built (nb, rowbeg, rowptr) with the arrays
 // used only afterwards (mem, pos, rcap).  Then the small per-level arrays.
 struct Lds {
   u64* A;        // D * W
-  u64* gl;       // D
+  u64* gl;       // D (null without fingerprints)
   u64* stP;      // (k-1) * W
   u64* stQ;      // (k-1) * W
   u64* stCnt;    // (k-1) * 2
@@ -69,9 +69,11 @@ struct Lds {
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
 
-__host__ __device__ inline size_t lds_bytes(int W, int k) {
+// fp = 0 leaves out the fingerprint weights: 8 * D bytes less, which at
+// W = 8 lets one more wavefront share a CU.
+__host__ __device__ inline size_t lds_bytes(int W, int k, int fp) {
   size_t D = 64 * (size_t)W, L = (size_t)(k > 1 ? k - 1 : 1);
-  size_t b = 8 * (D * W + D + 2 * L * W + 3 * L + W);
+  size_t b = 8 * (D * W + (fp ? D : 0) + 2 * L * W + 3 * L + W);
   size_t build = 4 * (3 * D + 1), post = 5 * D;
   b += align8(build > post ? build : post);
   b += align8(3 * L);
@@ -79,12 +81,16 @@ __host__ __device__ inline size_t lds_bytes(int W, int k) {
 }
 
 template <int W>
-__device__ inline Lds carve(char* base, int k) {
+__device__ inline Lds carve(char* base, int k, int fp) {
   const size_t D = 64 * W, L = (size_t)(k > 1 ? k - 1 : 1);
   Lds s;
   u64* p = (u64*)base;
   s.A = p; p += D * W;
-  s.gl = p; p += D;
+  s.gl = nullptr;
+  if (fp) {
+    s.gl = p;
+    p += D;
+  }
   s.stP = p; p += L * W;
   s.stQ = p; p += L * W;
   s.stCnt = p; p += 2 * L;
@@ -223,7 +229,7 @@ __device__ u64 build_subgraph(const Lds& s, const int32_t* dptr, const int32_t* 
   for (int i = lane; i < d; i += kWave) {
     int32_t v = dcol[beg + i];
     s.nb[i] = v;
-    s.gl[i] = gw[v];
+    if (s.gl) s.gl[i] = gw[v];
     if (oid) oid[i] = orig[v];
     int32_t b = dptr[v];
     s.rowptr[i] = b;

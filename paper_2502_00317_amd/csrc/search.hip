@@ -327,9 +327,9 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
   extern __shared__ __align__(16) char smem[];
   const int lane = lane_id();
   int k = p.k;  // batch mode: the largest k of the launch (sizes the stacks)
-  const Lds s = carve<W>(smem, p.k);
+  const Lds s = carve<W>(smem, p.k, p.fingerprint);
   // listing only: input ids of the local vertices and the sorted prefix
-  int32_t* const oid = EMIT ? (int32_t*)(smem + lds_bytes(W, p.k)) : nullptr;
+  int32_t* const oid = EMIT ? (int32_t*)(smem + lds_bytes(W, p.k, p.fingerprint)) : nullptr;
   int32_t* const pre = EMIT ? oid + 64 * W : nullptr;
   const int ES = W + 4;
   u64* table = p.memo_base ? p.memo_base + (u64)blockIdx.x * (p.memo_mask + 1) * ES : nullptr;
@@ -1072,14 +1072,14 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     DIST_CHECK(hipGetDevice(&dev));
     DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     for (auto& b : buckets)
-      if (lds_bytes(b.W, base.k) > (size_t)maxlds) return DIST_E_UNSUPPORTED;
+      if (lds_bytes(b.W, base.k, base.fingerprint) > (size_t)maxlds) return DIST_E_UNSUPPORTED;
   }
   // grids and memo sizing
   int maxgrid = 0;
   std::vector<int> grids(buckets.size());
   for (size_t b = 0; b < buckets.size(); ++b) {
     int W = buckets[b].W;
-    size_t lds = lds_bytes(W, base.k);
+    size_t lds = lds_bytes(W, base.k, base.fingerprint);
     int occ = 1;
     switch (W) {
       case 1: occ = occupancy_blocks<1>(lds); break;
@@ -1166,7 +1166,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     prm.epoch = nullptr;
     prm.deadline = deadline;
     g_tag_next += (u64)units[b] + 1;
-    size_t lds = lds_bytes(buckets[b].W, base.k);
+    size_t lds = lds_bytes(buckets[b].W, base.k, base.fingerprint);
     hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grids[b] * kOutWords);
     DIST_CHECK(hipEventRecord(kb0, s));
     switch (buckets[b].W) {
@@ -1364,7 +1364,9 @@ int occupancy_list(size_t lds) {
   return nb > 0 ? nb : 1;
 }
 
-size_t list_lds_bytes(int W, int k) { return lds_bytes(W, k) + align8(4 * (size_t)64 * W) + align8(4 * (size_t)(k + 1)); }
+size_t list_lds_bytes(int W, int k, int fp) {
+  return lds_bytes(W, k, fp) + align8(4 * (size_t)64 * W) + align8(4 * (size_t)(k + 1));
+}
 
 // Freed blocks are reused at once, so a buffer is released only after the
 // stream's work (also on an error path) has finished.
@@ -1474,7 +1476,7 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
   bool cancelled = false;
   for (auto& bk : buckets) {
     const int W = bk.W;
-    const size_t lds = list_lds_bytes(W, k);
+    const size_t lds = list_lds_bytes(W, k, cfg.fingerprint);
     if (lds > (size_t)maxlds) return DIST_E_UNSUPPORTED;
     int occ = 1;
     switch (W) {
@@ -1500,7 +1502,7 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
       if (rc) return rc;
       {
         BatchGraph bgh{g->dptr, g->dcol, g->orig, g->roots, g->gw, k, 0};
-        BatchSeg sg{0u, 0, b0, 1};
+        BatchSeg sg{0u, 0, b0, 1, (uint32_t)(b1 - b0)};
         memcpy(g_ws.h_plan, &bgh, sizeof(bgh));
         memcpy(g_ws.h_plan + sizeof(BatchGraph), &sg, sizeof(sg));
         DIST_CHECK(hipMemcpyAsync(g_ws.d_plan, g_ws.h_plan, sizeof(BatchGraph) + sizeof(BatchSeg),
@@ -1858,7 +1860,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     if (units64[t][b] == 0) continue;
     BatchLaunch L{};
     L.W = kSlotWidth[b];
-    L.lds = lds_bytes(L.W, kmax[t][b]);
+    L.lds = lds_bytes(L.W, kmax[t][b], cfg.fingerprint);
     if (L.lds > (size_t)maxlds) {
       for (auto& sg : segs[t][b]) P->status[sg.pair] = DIST_E_UNSUPPORTED;
       continue;

@@ -49,12 +49,12 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-queries", type=int, default=2000)
     ap.add_argument("--serve-deadline-ms", type=int, default=2000)
-    ap.add_argument("--serve-express-ms", type=int, default=40,
+    ap.add_argument("--serve-express-ms", type=int, default=30,
                     help="device budget of the express lane (0: no express lane)")
     ap.add_argument("--serve-trace", default="", help="write per-query and per-batch serving records here")
     ap.add_argument("--serve-bulk-slots", type=int, default=1)
-    ap.add_argument("--serve-express-batch-ms", type=float, default=0.0,
-                    help="predicted device time of one express batch (0: 4 x express-ms)")
+    ap.add_argument("--serve-express-batch-ms", type=float, default=120.0,
+                    help="predicted device time of one express batch")
     ap.add_argument("--serve-shed-frac", type=float, default=0.5,
                     help="report a (graph, k) DNF at once after a bulk cut-off that ran this share of the budget")
     ap.add_argument("--serve-modes", default="served,plain")
@@ -116,9 +116,9 @@ def summarize_profiles(d):
              "Commands (repository root, one MI355X; TMPDIR=/tmp):",
              "",
              "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $PWD/gpurun_out/pmc_FETCH_SIZE -o run -- \\",
-             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched",
+             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving",
              "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $PWD/gpurun_out/pmc_WRITE_SIZE -o run -- \\",
-             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched",
+             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving",
              "    rocprofv3 --pmc FETCH_SIZE (and WRITE_SIZE) ... -- python3 $PWD/bench.py --calib-copy 1024",
              "    python3 bench.py --summarize-profiles gpurun_out",
              "",
@@ -134,6 +134,31 @@ def summarize_profiles(d):
                      " / ".join("%.2f" % (x / 1e9) for x in e["WRITE_SIZE"])))
     with open(os.path.join(ROOT, "profiles", "k_search_cfg2_traffic.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
+    stats = glob.glob(os.path.join(d, "prof", "*kernel_stats.csv"))
+    if stats:
+        lines = ["# rocprofv3 kernel summary: plain count, Chung-Lu n=1e6, k = 5 (fingerprint), 7 and 9",
+                 "",
+                 "Command (repository root, one MI355X):",
+                 "",
+                 "    export TMPDIR=/tmp",
+                 "    rocprofv3 --kernel-trace --stats --output-format csv -d $PWD/gpurun_out/prof -o run -- \\",
+                 "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving",
+                 "    python3 bench.py --summarize-profiles gpurun_out",
+                 "",
+                 "One orientation (degree order) and one dist_count per k (one launch per width",
+                 "class per k); k_search<W> is the search kernel for roots whose out-degree",
+                 "needs W 64-bit words per bitmap row.  The average over the three launches is",
+                 "the avg_launch_ms that bench.py reports for the dominant kernel.",
+                 "Kernel source hash: %s" % out["source_hash"],
+                 "",
+                 "| kernel | calls | total ms | average ms | % |",
+                 "|---|---|---|---|---|"]
+        for r in csv.DictReader(open(stats[0])):
+            name = r["Name"].replace("void (anonymous namespace)::", "").replace("((anonymous namespace)::Params)", "(Params)")
+            lines.append("| %s | %s | %.3f | %.3f | %.2f |" % (name, r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                                                           float(r["AverageNs"]) / 1e6, float(r["Percentage"])))
+        with open(os.path.join(ROOT, "profiles", "k_search_cfg2_kernel_stats.md"), "w") as f:
+            f.write("\n".join(lines) + "\n")
     print(json.dumps(out)[:400])
 
 

@@ -320,6 +320,55 @@ __device__ u64 first_time(unsigned long long* slot, u64 now) {
   return old ? old : now;
 }
 
+// ---- complete candidate sets ------------------------------------------------
+// If G[P] is complete every l-subset of P is an l-clique: the node holds
+// C(|P|, l) cliques whose fingerprint sum is the elementary symmetric sum
+// e_l of the weights of P.  Exact; it replaces the search below the node.
+
+// 128-bit value divided by a small d (< 2^31), in 32-bit limbs.
+__device__ __forceinline__ void div_small(u64& hi, u64& lo, u64 d) {
+  u64 r = 0;
+  uint32_t limb[4] = {(uint32_t)(hi >> 32), (uint32_t)hi, (uint32_t)(lo >> 32), (uint32_t)lo};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    u64 cur = (r << 32) | limb[i];
+    limb[i] = (uint32_t)(cur / d);
+    r = cur % d;
+  }
+  hi = ((u64)limb[0] << 32) | limb[1];
+  lo = ((u64)limb[2] << 32) | limb[3];
+}
+
+// C(n, r) as 128 bits; false if it may not fit (then nothing is claimed).
+__device__ __forceinline__ bool binom128(int n, int r, u64& lo, u64& hi) {
+  lo = 1;
+  hi = 0;
+  for (int i = 0; i < r; ++i) {
+    const u64 m = (u64)(n - i);  // < 2^11
+    if (hi >> 52) return false;
+    // (hi:lo) * m
+    const u64 plo = lo * m;
+    const u64 carry = __umul64hi(lo, m);
+    hi = hi * m + carry;
+    lo = plo;
+    div_small(hi, lo, (u64)(i + 1));
+  }
+  return true;
+}
+
+// e_l of the weights of the np members of P (wave-collective): lane j holds
+// e_j while the members are added one at a time.
+__device__ __forceinline__ u64 esym_members(const uint16_t* mem, int np, const u64* gl, int l) {
+  const int lane = lane_id();
+  u64 e = lane == 0 ? 1ull : 0ull;
+  for (int i = 0; i < np; ++i) {
+    const u64 g = gl[mem[i]];
+    const u64 prev = __shfl_up(e, 1);
+    if (lane >= 1 && lane <= l) e = addp(e, mulp(prev, g));
+  }
+  return __shfl(e, l);
+}
+
 // ---- the kernel ----------------------------------------------------------------
 
 template <int W, bool EMIT>
@@ -576,6 +625,32 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             }
             __syncthreads();
           }
+          if (!EMIT && l == 3 && j > 0) {
+            // edges of G[P] first: a complete P needs no leaf search
+            u64 m = 0;
+            for (int i = lane; i < np; i += kWave) {
+              const int x = s.mem[i];
+              int c = 0;
+#pragma unroll
+              for (int w = 0; w < W; ++w) c += __popcll(Pr[w] & s.A[x * W + w]);
+              m += (u64)c;
+            }
+            wops += (u64)((np + kWave - 1 - lane) / kWave) * W;
+            m = wave_sum(m);
+            u64 clo, chi;
+            if (m == (u64)np * (u64)(np - 1) / 2 && binom128(np, 3, clo, chi)) {
+              res_lo = clo;
+              res_hi = chi;
+              res_fp = p.fingerprint ? esym_members(s.mem, np, s.gl, 3) : 0;
+                if (memo_j && memo_live) {
+                memo_put<W>(p, table, tag, root_tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+                ++n_ins;
+              }
+              __syncthreads();
+              mode = FINISH;
+              continue;
+            }
+          }
           u64 c_acc = 0, f_acc = 0;
           for (int base = 0; base < np; base += kWave) {
             int i = base + lane;
@@ -671,6 +746,17 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           if (c >= l - 1 && s.rcap[x] >= l) atomicOr(&Q[x >> 6], 1ull << (x & 63));
         }
         m_edges = wave_sum(m_edges);
+        if (!EMIT && j > 0 && m_edges == (u64)np * (u64)(np - 1) / 2) {
+          u64 clo, chi;
+          if (binom128(np, l, clo, chi)) {
+            res_lo = clo;
+            res_hi = chi;
+            res_fp = p.fingerprint ? esym_members(s.mem, np, s.gl, l) : 0;
+            __syncthreads();
+            mode = FINISH;
+            continue;
+          }
+        }
         if (!memo_j && p.memo == 1 && memo_live) {
           // criterion (1) in integer form: 2 m l > (l - 1) n^2
           u64 lhs = 2ull * m_edges * (u64)l;

@@ -55,7 +55,7 @@ constexpr int kMemoProbe = 4;
 // A root stops using its memo table once at least kMemoMinLook lookups
 // found fewer than one hit in kMemoMinRatio (the table is a cache: using it
 // or not never changes a result).
-constexpr int kMemoMinLook = 64;
+constexpr int kMemoMinLook = 1024;
 constexpr int kMemoMinRatio = 16;
 
 // Batched counting: one entry per (graph, k) pair, and the units of a
@@ -102,7 +102,8 @@ struct Params {
   const BatchGraph* bg;      // batch mode (null: one graph, the fields above)
   const BatchSeg* segs;
   int32_t nsegs;
-  u64* pair_out;             // batch: 3 words per pair, accumulated
+  u64* pair_out;             // batch: 4 words per pair, accumulated: count lo, hi; fingerprint
+                             // residues summed exactly as 128 bits (lo, hi), reduced mod p at the end
   int* pair_abort;           // batch: set for a pair that ran out of its budget
   unsigned* pair_rem;        // batch: units of each pair not finished yet
   unsigned long long* pair_t0;  // batch: [0] first unit of the batch, [1 + i] first unit of pair i
@@ -271,6 +272,20 @@ __device__ __forceinline__ void write_record(int32_t* dst, const int32_t* pre, i
   }
 }
 
+// (hi * 2^64 + lo) mod p, p = 2^61 - 1 (2^64 = 8 mod p).
+__device__ __forceinline__ u64 fold_p(u64 hi, u64 lo) {
+  const u64 l = (lo & DIST_P61) + (lo >> 61);
+  const u64 h = (hi & DIST_P61) + (hi >> 61);
+  return addp(mulp(h % DIST_P61, 8ull), l % DIST_P61);
+}
+
+// 128-bit atomic accumulation (lo word, then the carry into the hi word).
+__device__ __forceinline__ void atomic_add128(u64* o, u64 lo, u64 hi) {
+  const u64 old = atomicAdd((unsigned long long*)o, (unsigned long long)lo);
+  const u64 carry = (old + lo < old) ? 1ull : 0ull;
+  if (hi + carry) atomicAdd((unsigned long long*)(o + 1), (unsigned long long)(hi + carry));
+}
+
 // Every unit of a batch ends here (searched, skipped or cut off); n units
 // at once when a wave skips the rest of a cut-off pair.  The last unit of a
 // pair publishes the pair's result to host-mapped memory, so the host can
@@ -282,10 +297,11 @@ __device__ void finish_units(const Params& p, int pair, uint32_t n) {
     unsigned left = atomicSub(p.pair_rem + pair, n);
     if (left == n) {
       __threadfence();
-      const u64* o = p.pair_out + 3 * (u64)pair;
+      const u64* o = p.pair_out + 4 * (u64)pair;
       u64 lo = __hip_atomic_load(o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       u64 hi = __hip_atomic_load(o + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      u64 fp = __hip_atomic_load(o + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      u64 fp = fold_p(__hip_atomic_load(o + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(o + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       int ab = __hip_atomic_load(p.pair_abort + pair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       u64 t1 = __hip_atomic_load(p.pair_t0 + 1 + pair, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       u64* h = p.pair_host + 6 * (u64)pair;
@@ -897,15 +913,10 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
     // root result: cnt, fp * g(root)
     u64 rfp = p.fingerprint ? mulp(Ggw[r], res_fp) : 0;
     if (p.pair_out && lane == 0) {
-      u64* o = p.pair_out + 3 * (u64)pair;
-      u64 old = atomicAdd((unsigned long long*)&o[0], (unsigned long long)res_lo);
-      u64 carry_in = (old + res_lo < old) ? 1ull : 0ull;
-      if (res_hi + carry_in) atomicAdd((unsigned long long*)&o[1], (unsigned long long)(res_hi + carry_in));
-      u64 cur = o[2], seen;
-      do {
-        seen = cur;
-        cur = atomicCAS((unsigned long long*)&o[2], seen, addp(seen, rfp));
-      } while (cur != seen);
+      // plain atomic adds only: many waves finish units of one pair at once
+      u64* o = p.pair_out + 4 * (u64)pair;
+      atomic_add128(o, res_lo, res_hi);
+      if (rfp) atomic_add128(o + 2, rfp, 0);
     }
     u64 nlo = tot_lo + res_lo;
     tot_hi += res_hi + (nlo < tot_lo ? 1ull : 0ull);
@@ -1723,7 +1734,7 @@ struct BatchWs {
   size_t cap_bg = 0;
   BatchSeg* d_segs = nullptr;
   size_t cap_segs = 0;
-  u64* d_pair_out = nullptr;  // 3 per pair, then one word: the launch abort flag
+  u64* d_pair_out = nullptr;  // 4 per pair, then one word: the launch abort flag
   size_t cap_out = 0;
   int* d_pair_abort = nullptr;
   size_t cap_pab = 0;
@@ -1821,6 +1832,11 @@ int launch_any(int W, const Params& prm, int grid, size_t lds, hipStream_t s) {
 }
 
 // Lays out the batch in ws and uploads its descriptors (synchronous on s).
+u64 fold_p_host(u64 hi, u64 lo) {
+  const unsigned __int128 v = ((unsigned __int128)hi << 64) | lo;
+  return (u64)(v % (unsigned __int128)DIST_P61);
+}
+
 int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int64_t* dls, int n,
                const dist_config& cfg, hipStream_t s, bool stream_done, const double* pair_cost) {
   P->drop_graph();
@@ -1896,7 +1912,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
   int rc = DIST_OK;
   if ((rc = grow_dev(&P->d_bg, P->cap_bg, nn))) return rc;
   if ((rc = grow_dev(&P->d_segs, P->cap_segs, all.size() + 1))) return rc;
-  if ((rc = grow_dev(&P->d_pair_out, P->cap_out, 3 * nn + 1))) return rc;
+  if ((rc = grow_dev(&P->d_pair_out, P->cap_out, 4 * nn + 1))) return rc;
   if ((rc = grow_dev(&P->d_pair_abort, P->cap_pab, nn))) return rc;
   if ((rc = grow_dev(&P->d_pair_rem, P->cap_rem, nn))) return rc;
   if ((rc = grow_dev(&P->d_pair_rem_init, P->cap_rem_init, nn))) return rc;
@@ -1928,7 +1944,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     DIST_CHECK(hipMemcpyAsync(P->d_epoch, &base, sizeof(u64), hipMemcpyHostToDevice, s));
     DIST_CHECK(hipStreamSynchronize(s));
   }
-  const size_t hneed = 3 * nn + 1 + nn;  // pair_out, abort word, pair aborts (as u64 slots)
+  const size_t hneed = 4 * nn + 1 + nn;  // pair_out, abort word, pair aborts (as u64 slots)
   if (hneed > P->cap_h) {
     if (P->h_out) pinned_free(P->h_out);
     P->h_out = nullptr;
@@ -2019,7 +2035,7 @@ int enqueue_batch(BatchWs* P, hipStream_t s) {
   hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, P->d_epoch, P->units_total + 1);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, P->d_cursor, 64);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)P->d_abort, 16);
-  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, P->d_pair_out, (u64)(3 * nn));
+  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, P->d_pair_out, (u64)(4 * nn));
   hipLaunchKernelGGL(k_zero_i32, dim3(64), dim3(256), 0, s, P->d_pair_abort, (int)nn);
   hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, (u64*)P->d_pair_t0, (u64)(nn + 1));
   if (P->stream_done)
@@ -2029,9 +2045,9 @@ int enqueue_batch(BatchWs* P, hipStream_t s) {
     int rc = launch_any(L.W, L.prm, L.grid, L.lds, s);
     if (rc) return rc;
   }
-  DIST_CHECK(hipMemcpyAsync(P->h_out, P->d_pair_out, sizeof(u64) * 3 * nn, hipMemcpyDeviceToHost, s));
-  DIST_CHECK(hipMemcpyAsync(P->h_out + 3 * nn, P->d_abort, sizeof(int), hipMemcpyDeviceToHost, s));
-  DIST_CHECK(hipMemcpyAsync(P->h_out + 3 * nn + 1, P->d_pair_abort, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipMemcpyAsync(P->h_out, P->d_pair_out, sizeof(u64) * 4 * nn, hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipMemcpyAsync(P->h_out + 4 * nn, P->d_abort, sizeof(int), hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipMemcpyAsync(P->h_out + 4 * nn + 1, P->d_pair_abort, sizeof(int) * nn, hipMemcpyDeviceToHost, s));
   return DIST_OK;
 }
 
@@ -2158,11 +2174,12 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
   (void)hipEventDestroy(e1);
   if (ms) *ms = t;
   const size_t nn = (size_t)(n > 0 ? n : 1);
-  const bool aborted = (P->h_out[3 * nn] & 0xffffffffull) != 0;
-  const int* pab = (const int*)(P->h_out + 3 * nn + 1);
+  const bool aborted = (P->h_out[4 * nn] & 0xffffffffull) != 0;
+  const int* pab = (const int*)(P->h_out + 4 * nn + 1);
   int first = aborted ? DIST_E_CANCELLED : DIST_OK;
   for (int i = 0; i < n; ++i) {
-    dist_result r{P->h_out[3 * i], P->h_out[3 * i + 1], cfg.fingerprint ? P->h_out[3 * i + 2] : 0};
+    dist_result r{P->h_out[4 * i], P->h_out[4 * i + 1],
+                  cfg.fingerprint ? fold_p_host(P->h_out[4 * i + 3], P->h_out[4 * i + 2]) : 0};
     int st = P->status[i];
     if (st == DIST_OK && (aborted || pab[i])) st = DIST_E_CANCELLED;
     if (ks[i] == 1 && st == DIST_OK) {

@@ -49,16 +49,16 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-queries", type=int, default=2000)
     ap.add_argument("--serve-deadline-ms", type=int, default=2000)
-    ap.add_argument("--serve-express-ms", type=int, default=30,
+    ap.add_argument("--serve-express-ms", type=int, default=50,
                     help="device budget of the express lane (0: no express lane)")
     ap.add_argument("--serve-trace", default="", help="write per-query and per-batch serving records here")
     ap.add_argument("--serve-bulk-slots", type=int, default=1)
-    ap.add_argument("--serve-express-batch-ms", type=float, default=120.0,
+    ap.add_argument("--serve-express-batch-ms", type=float, default=200.0,
                     help="predicted device time of one express batch")
     ap.add_argument("--serve-shed-frac", type=float, default=0.5,
                     help="report a (graph, k) DNF at once after a bulk cut-off that ran this share of the budget")
     ap.add_argument("--serve-modes", default="served,plain")
-    ap.add_argument("--serve-express-pct", type=int, default=40,
+    ap.add_argument("--serve-express-pct", type=int, default=45,
                     help="share of the device's wavefront slots for the express lane")
     ap.add_argument("--summarize-profiles", default="", metavar="DIR",
                     help="turn rocprofv3 CSVs under DIR into the summaries under profiles/")

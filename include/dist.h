@@ -82,13 +82,14 @@ typedef struct {
                             0: off */
   int32_t fingerprint;   /* 1 (default): compute fp; 0: fp reported as 0 */
   int32_t memo_entries;  /* memo table entries per wave (power of two); 0 = auto */
-  int64_t memo_bytes;    /* total memo budget in bytes; 0 = auto (4 GiB) */
+  int64_t memo_bytes;    /* total memo budget in bytes; 0 = auto (16 GiB) */
   int64_t deadline_ms;   /* stop after this many milliseconds of kernel time
                             and return DIST_E_CANCELLED; 0 = no deadline */
   int32_t chunk_work;    /* work-unit size for roots with more than 64
                             out-neighbours: such a root is split into ranges of
                             max(1, chunk_work / d) depth-1 children that
-                            different wavefronts take; 0 = auto (512) */
+                            different wavefronts take; 0 = auto (256 for
+                            k >= 9, else 512) */
   int32_t grid_pct;      /* batches: percent of the full persistent grid a
                             launch may use (so that batches of several streams
                             share the device); 0 = 100 */

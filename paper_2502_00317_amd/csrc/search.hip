@@ -221,6 +221,12 @@ __device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, u
 // ranges of max(1, chunk_work / d) depth-1 children so that many waves share
 // it (each wave rebuilds G_u in its own LDS); lighter roots stay one unit,
 // which keeps the memo reuse between the children of a root inside one wave.
+// chunk_work 0 = automatic: deeper searches (k >= 9) make each depth-1
+// child heavier, so they get smaller units (256) for balance; else 512.
+__host__ __device__ inline int auto_chunk(int chunk_work, int k) {
+  return chunk_work > 0 ? chunk_work : (k >= 9 ? 256 : 512);
+}
+
 __host__ __device__ inline int units_per_root(int d, int k, int chunk_work) {
   if (k <= 3 || d <= 64) return 1;
   int c = chunk_work / d;  // depth-1 children per unit
@@ -1090,7 +1096,7 @@ void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, 
     int W = width_of(d);
     if (W < min_w) W = min_w;
     const int sl = wslot_of_width(W);
-    const int upr = whole_roots ? 1 : units_per_root(d, k, cw);
+    const int upr = whole_roots ? 1 : units_per_root(d, k, auto_chunk(cw, k));
     if (sl != cur_sl || upr != cur_upr) {
       flush(a);
       cur_sl = sl;
@@ -1147,7 +1153,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   for (int i = 0; i < kOutWords; ++i) totals[i] = 0;
   if (nroots <= 0) return DIST_OK;
   if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
-  const int cw = base.chunk_work > 0 ? base.chunk_work : 512;
+  const int cw = base.chunk_work;  // 0: automatic per k
   std::vector<BatchSeg> segs[5];
   uint64_t units64[5] = {0, 0, 0, 0, 0};
   int kmax[5] = {0, 0, 0, 0, 0};
@@ -1197,7 +1203,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   size_t memo_total = 0;
   u64 entries = 0;
   if (want_memo) {
-    size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)4 << 30);
+    size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)16 << 30);
     int maxW = 1;
     for (auto& b : buckets) maxW = b.W > maxW ? b.W : maxW;
     size_t es = (size_t)(maxW + 4) * 8;
@@ -1858,7 +1864,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
   uint64_t units64[kTiers][5] = {};
   int kmax[kTiers][5] = {};
   const int min_w = cfg.min_width > 1 ? cfg.min_width : 1;
-  const int cw = cfg.chunk_work > 0 ? cfg.chunk_work : 512;
+  const int cw = cfg.chunk_work;  // 0: automatic per pair's k
   std::vector<int> order(n), tier(n, 0);
   for (int i = 0; i < n; ++i) order[i] = i;
   const bool own_clock = cfg.budget_from_pair_start != 0;
@@ -2002,7 +2008,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
   u64 entries = 0;
   size_t memo_bytes = 0;
   if (cfg.memo != 0 && maxgrid > 0) {
-    size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)4 << 30);
+    size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)16 << 30);
     size_t es = (size_t)(maxW + 4) * 8;
     entries = cfg.memo_entries > 0 ? 1 : (1 << 16);
     if (cfg.memo_entries > 0)

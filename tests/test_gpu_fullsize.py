@@ -131,3 +131,28 @@ def test_batched_workload_sampled_pairs(D, oracle_mod):
     # a replay of the captured launch gives the same results for every pair
     res2, rc2, _ = D.count_batch(G, ks, cfg=D.config(), use_graph=True)
     assert res2 == res
+
+
+def test_dense_core_rmat_orientation_and_budget(D):
+    """The dense-core stress graph (R-MAT scale 22, 64M edges): degeneracy
+    order bounds every out-degree by the degeneracy the oracle computes
+    (stored by tests/golden/make_rmat_degeneracy.py); both orders keep every
+    root within the widest (1024-bit) class; a search of its ~1000-wide dense
+    core is cut off cleanly by a deadline in either order (an exact count at
+    k >= 6 is beyond a search here)."""
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rmat_s22_degeneracy.json")))
+    g = gg.dense_core_rmat()
+    assert (g.n, g.m) == (fx["n"], fx["m"])
+    G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGENERACY)
+    info = G.info()
+    assert info.order_bound == fx["degeneracy"]
+    assert info.max_outdeg <= fx["degeneracy"] <= 1024
+    assert np.array_equal(np.sort(G.ranks()), np.arange(g.n))
+    H = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+    assert fx["degeneracy"] <= H.info().max_outdeg <= 1024
+    for X in (G, H):
+        with pytest.raises(D.DistError) as e:
+            D.count(X, 6, cfg=D.config(fingerprint=0, deadline_ms=3000))
+        assert e.value.status == D.E_CANCELLED

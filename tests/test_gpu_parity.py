@@ -153,3 +153,18 @@ def test_empty_graphs(D):
         assert D.count(G, 1)[0] == n
         assert D.count(G, 2)[0] == 0
         assert D.count(G, 5)[0] == 0
+
+
+@pytest.mark.parametrize("n,r,ks", [(700, 700, (3, 4, 6)), (700, 35, (3, 4))])
+def test_wide_roots(D, n, r, ks):
+    """Roots with 513..1023 out-neighbours (16-word rows, one wavefront per
+    CU): complete graphs and Turan graphs against their closed forms."""
+    import refdefs as R
+    g = gg.complete(n) if r == n else gg.turan(n, r)
+    G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+    assert G.info().max_outdeg > 512
+    for k in ks:
+        want = R.complete_graph_result(n, k) if r == n else R.turan_result(n, r, k)
+        for cfg in (dict(memo=1, prune=1), dict(memo=0, prune=1)):
+            print("wide", n, r, k, cfg, flush=True)
+            assert _gpu(D, g, k, D.ORDER_DEGREE, **cfg) == want

@@ -69,10 +69,19 @@ struct Lds {
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
 
-// fp = 0 leaves out the fingerprint weights: 8 * D bytes less, which at
-// W = 8 lets one more wavefront share a CU.
-__host__ __device__ inline size_t lds_bytes(int W, int k, int fp) {
-  size_t D = 64 * (size_t)W, L = (size_t)(k > 1 ? k - 1 : 1);
+// Rows of a launch: its largest root out-degree rounded up to 16, within
+// the width class.
+__host__ __device__ inline int lds_rows(int W, int dmax) {
+  int D = (dmax + 15) & ~15;
+  if (D < 16) D = 16;
+  return D < 64 * W ? D : 64 * W;
+}
+
+// D = rows: the largest out-degree among the launch's roots (at most 64 W),
+// so that a launch whose roots are narrower than its class uses less LDS.
+// fp = 0 leaves out the fingerprint weights (8 D bytes).
+__host__ __device__ inline size_t lds_bytes(int W, int k, int fp, int Drows) {
+  size_t D = (size_t)Drows, L = (size_t)(k > 1 ? k - 1 : 1);
   size_t b = 8 * (D * W + (fp ? D : 0) + 2 * L * W + 3 * L + W);
   size_t build = 4 * (3 * D + 1), post = 5 * D;
   b += align8(build > post ? build : post);
@@ -81,8 +90,8 @@ __host__ __device__ inline size_t lds_bytes(int W, int k, int fp) {
 }
 
 template <int W>
-__device__ inline Lds carve(char* base, int k, int fp) {
-  const size_t D = 64 * W, L = (size_t)(k > 1 ? k - 1 : 1);
+__device__ inline Lds carve(char* base, int k, int fp, int Drows) {
+  const size_t D = (size_t)Drows, L = (size_t)(k > 1 ? k - 1 : 1);
   Lds s;
   u64* p = (u64*)base;
   s.A = p; p += D * W;

@@ -110,6 +110,7 @@ struct Params {
   u64* pair_host;            // batch: host-mapped {flag, lo, hi, fp, t_first, t_last} per pair
   uint32_t units;            // work units in this bucket
   int chunk_work;            // children per unit = max(1, chunk_work / d) for d > 64
+  int32_t drows;             // LDS rows of G_u for this launch (>= every root's out-degree)
   u64* wave_out;
   u64* per_root;
   u64* memo_base;
@@ -393,15 +394,15 @@ __device__ __forceinline__ u64 esym_members(const uint16_t* mem, int np, const u
 
 // ---- the kernel ----------------------------------------------------------------
 
-template <int W, bool EMIT>
+template <int W, bool EMIT, bool FP>
 __global__ __launch_bounds__(64) void k_search(Params p) {
   extern __shared__ __align__(16) char smem[];
   const int lane = lane_id();
   int k = p.k;  // batch mode: the largest k of the launch (sizes the stacks)
-  const Lds s = carve<W>(smem, p.k, p.fingerprint);
+  const Lds s = carve<W>(smem, p.k, FP, p.drows);
   // listing only: input ids of the local vertices and the sorted prefix
-  int32_t* const oid = EMIT ? (int32_t*)(smem + lds_bytes(W, p.k, p.fingerprint)) : nullptr;
-  int32_t* const pre = EMIT ? oid + 64 * W : nullptr;
+  int32_t* const oid = EMIT ? (int32_t*)(smem + lds_bytes(W, p.k, FP, p.drows)) : nullptr;
+  int32_t* const pre = EMIT ? oid + p.drows : nullptr;
   const int ES = W + 4;
   u64* table = p.memo_base ? p.memo_base + (u64)blockIdx.x * (p.memo_mask + 1) * ES : nullptr;
 
@@ -593,7 +594,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             }
           }
           u64 f = 0;
-          if (p.fingerprint) {
+          if (FP) {
             u64 tmpb = 0;
             f = weight_sum<W>(Pr, s.gl, tmpb);
             bits += (lane == 0) ? tmpb : 0;
@@ -663,7 +664,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             if (m == (u64)np * (u64)(np - 1) / 2 && binom128(np, 3, clo, chi)) {
               res_lo = clo;
               res_hi = chi;
-              res_fp = p.fingerprint ? esym_members(s.mem, np, s.gl, 3) : 0;
+              res_fp = FP ? esym_members(s.mem, np, s.gl, 3) : 0;
                 if (memo_j && memo_live) {
                 memo_put<W>(p, table, tag, root_tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
                 ++n_ins;
@@ -692,13 +693,13 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
               if (l == 2) {
                 c_acc += (u64)c;
                 mine = (u64)c;
-                if (p.fingerprint && c) f_acc = addp(f_acc, mulp(s.gl[x], weight_sum<W>(q, s.gl, bits)));
+                if (FP && c) f_acc = addp(f_acc, mulp(s.gl[x], weight_sum<W>(q, s.gl, bits)));
               } else if (c >= 2 && s.rcap[x] >= 3) {
                 u64 ec = 0, ef = 0;
-                edges_in<W>(q, s.A, s.gl, p.fingerprint, ec, ef, wops, bits);
+                edges_in<W>(q, s.A, s.gl, FP, ec, ef, wops, bits);
                 c_acc += ec;
                 mine = ec;
-                if (p.fingerprint && ec) f_acc = addp(f_acc, mulp(s.gl[x], ef));
+                if (FP && ec) f_acc = addp(f_acc, mulp(s.gl[x], ef));
               }
             }
             if constexpr (EMIT) {
@@ -744,7 +745,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           }
           res_lo = wave_sum(c_acc);
           res_hi = 0;
-          res_fp = p.fingerprint ? wave_sum_p(f_acc) : 0;
+          res_fp = FP ? wave_sum_p(f_acc) : 0;
           if (memo_j && memo_live && j > 0) memo_put<W>(p, table, tag, root_tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
           if (memo_j && memo_live && j > 0) ++n_ins;
           __syncthreads();
@@ -773,7 +774,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           if (binom128(np, l, clo, chi)) {
             res_lo = clo;
             res_hi = chi;
-            res_fp = p.fingerprint ? esym_members(s.mem, np, s.gl, l) : 0;
+            res_fp = FP ? esym_members(s.mem, np, s.gl, l) : 0;
             __syncthreads();
             mode = FINISH;
             continue;
@@ -892,7 +893,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         u64 nlo = lo + res_lo;
         hi += res_hi + (nlo < lo ? 1ull : 0ull);
         lo = nlo;
-        if (p.fingerprint) f = addp(f, mulp(s.gl[x], res_fp));
+        if (FP) f = addp(f, mulp(s.gl[x], res_fp));
         __syncthreads();
         if (lane == 0) {
           s.stCnt[2 * j] = lo;
@@ -917,7 +918,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       continue;
     }
     // root result: cnt, fp * g(root)
-    u64 rfp = p.fingerprint ? mulp(Ggw[r], res_fp) : 0;
+    u64 rfp = FP ? mulp(Ggw[r], res_fp) : 0;
     if (p.pair_out && lane == 0) {
       // plain atomic adds only: many waves finish units of one pair at once
       u64* o = p.pair_out + 4 * (u64)pair;
@@ -1110,18 +1111,31 @@ void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, 
     for (size_t i = first_seg[b]; i < segs[b].size(); ++i) segs[b][i].pair_end = (uint32_t)units[b];
 }
 
+// The fingerprint switch is a template parameter: a count without
+// fingerprints runs a kernel without their registers.
 template <int W>
-int occupancy_blocks(size_t lds) {
+const void* search_kernel(bool fp) {
+  return fp ? (const void*)k_search<W, false, true> : (const void*)k_search<W, false, false>;
+}
+
+template <int W>
+int occupancy_blocks(size_t lds, bool fp) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, false>, 64, lds) != hipSuccess) return 1;
+  hipError_t e = fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, false, true>, 64, lds)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, false, false>, 64, lds);
+  if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
 template <int W>
 int launch_bucket(Params prm, int grid, size_t lds, hipStream_t s, bool set_attr = true) {
+  const bool fp = prm.fingerprint != 0;
   if (set_attr)
-    DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_search<W, false>), dim3(grid), dim3(64), lds, s, prm);
+    DIST_CHECK(hipFuncSetAttribute(search_kernel<W>(fp), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (fp)
+    hipLaunchKernelGGL((k_search<W, false, true>), dim3(grid), dim3(64), lds, s, prm);
+  else
+    hipLaunchKernelGGL((k_search<W, false, false>), dim3(grid), dim3(64), lds, s, prm);
   DIST_CHECK(hipGetLastError());
   return DIST_OK;
 }
@@ -1130,6 +1144,7 @@ int launch_bucket(Params prm, int grid, size_t lds, hipStream_t s, bool set_attr
 struct Bucket {
   int W;
   int32_t begin, end;  // range in g->roots
+  int D = 0;           // LDS rows (lds_rows of the largest out-degree)
 };
 
 // Roots [0, nroots) of g->roots split into width buckets (widest first).
@@ -1140,7 +1155,7 @@ std::vector<Bucket> make_buckets(const dist_graph* g, int32_t nroots) {
     int W = width_of(g->root_deg[i]);
     int32_t j = i;
     while (j < nroots && width_of(g->root_deg[j]) == W) ++j;
-    out.push_back({W, i, j});
+    out.push_back({W, i, j, lds_rows(W, g->root_deg[i])});
     i = j;
   }
   return out;
@@ -1165,7 +1180,8 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   for (int sl = 0; sl < 5; ++sl) {
     if (units64[sl] == 0) continue;
     if (units64[sl] >= 0xffffffffull) return DIST_E_UNSUPPORTED;
-    buckets.push_back(Bucket{kSlotWidth[sl], 0, 0});
+    // roots are in descending out-degree order: a class's first root is its widest
+    buckets.push_back(Bucket{kSlotWidth[sl], 0, 0, lds_rows(kSlotWidth[sl], g->root_deg[segs[sl][0].a])});
     units.push_back((uint32_t)units64[sl]);
     seg_off.push_back(nseg_total);
     nseg_total += segs[sl].size();
@@ -1175,21 +1191,22 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     DIST_CHECK(hipGetDevice(&dev));
     DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     for (auto& b : buckets)
-      if (lds_bytes(b.W, base.k, base.fingerprint) > (size_t)maxlds) return DIST_E_UNSUPPORTED;
+      if (lds_bytes(b.W, base.k, base.fingerprint, b.D) > (size_t)maxlds) return DIST_E_UNSUPPORTED;
   }
   // grids and memo sizing
   int maxgrid = 0;
   std::vector<int> grids(buckets.size());
   for (size_t b = 0; b < buckets.size(); ++b) {
     int W = buckets[b].W;
-    size_t lds = lds_bytes(W, base.k, base.fingerprint);
+    size_t lds = lds_bytes(W, base.k, base.fingerprint, buckets[b].D);
     int occ = 1;
+    const bool fp = base.fingerprint != 0;
     switch (W) {
-      case 1: occ = occupancy_blocks<1>(lds); break;
-      case 2: occ = occupancy_blocks<2>(lds); break;
-      case 4: occ = occupancy_blocks<4>(lds); break;
-      case 8: occ = occupancy_blocks<8>(lds); break;
-      default: occ = occupancy_blocks<16>(lds); break;
+      case 1: occ = occupancy_blocks<1>(lds, fp); break;
+      case 2: occ = occupancy_blocks<2>(lds, fp); break;
+      case 4: occ = occupancy_blocks<4>(lds, fp); break;
+      case 8: occ = occupancy_blocks<8>(lds, fp); break;
+      default: occ = occupancy_blocks<16>(lds, fp); break;
     }
     int cus = g_ws.cus > 0 ? g_ws.cus : 256;
     int64_t grid = (int64_t)occ * cus;
@@ -1269,7 +1286,8 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     prm.epoch = nullptr;
     prm.deadline = deadline;
     g_tag_next += (u64)units[b] + 1;
-    size_t lds = lds_bytes(buckets[b].W, base.k, base.fingerprint);
+    size_t lds = lds_bytes(buckets[b].W, base.k, base.fingerprint, buckets[b].D);
+    prm.drows = buckets[b].D;
     hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grids[b] * kOutWords);
     DIST_CHECK(hipEventRecord(kb0, s));
     switch (buckets[b].W) {
@@ -1454,21 +1472,28 @@ __global__ void k_gather_counts(const u64* per_root, const int32_t* orig, const 
 
 template <int W>
 int launch_list(Params prm, int grid, size_t lds, hipStream_t s) {
-  DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_search<W, true>), dim3(grid), dim3(64), lds, s, prm);
+  if (prm.fingerprint) {
+    DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_search<W, true, true>), dim3(grid), dim3(64), lds, s, prm);
+  } else {
+    DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_search<W, true, false>), dim3(grid), dim3(64), lds, s, prm);
+  }
   DIST_CHECK(hipGetLastError());
   return DIST_OK;
 }
 
 template <int W>
-int occupancy_list(size_t lds) {
+int occupancy_list(size_t lds, bool fp) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, true>, 64, lds) != hipSuccess) return 1;
+  hipError_t e = fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, true, true>, 64, lds)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, true, false>, 64, lds);
+  if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
-size_t list_lds_bytes(int W, int k, int fp) {
-  return lds_bytes(W, k, fp) + align8(4 * (size_t)64 * W) + align8(4 * (size_t)(k + 1));
+size_t list_lds_bytes(int W, int k, int fp, int D) {
+  return lds_bytes(W, k, fp, D) + align8(4 * (size_t)D) + align8(4 * (size_t)(k + 1));
 }
 
 // Freed blocks are reused at once, so a buffer is released only after the
@@ -1579,15 +1604,15 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
   bool cancelled = false;
   for (auto& bk : buckets) {
     const int W = bk.W;
-    const size_t lds = list_lds_bytes(W, k, cfg.fingerprint);
+    const size_t lds = list_lds_bytes(W, k, cfg.fingerprint, bk.D);
     if (lds > (size_t)maxlds) return DIST_E_UNSUPPORTED;
     int occ = 1;
     switch (W) {
-      case 1: occ = occupancy_list<1>(lds); break;
-      case 2: occ = occupancy_list<2>(lds); break;
-      case 4: occ = occupancy_list<4>(lds); break;
-      case 8: occ = occupancy_list<8>(lds); break;
-      default: occ = occupancy_list<16>(lds); break;
+      case 1: occ = occupancy_list<1>(lds, cfg.fingerprint != 0); break;
+      case 2: occ = occupancy_list<2>(lds, cfg.fingerprint != 0); break;
+      case 4: occ = occupancy_list<4>(lds, cfg.fingerprint != 0); break;
+      case 8: occ = occupancy_list<8>(lds, cfg.fingerprint != 0); break;
+      default: occ = occupancy_list<16>(lds, cfg.fingerprint != 0); break;
     }
     const int cus = g_ws.cus > 0 ? g_ws.cus : 256;
     int32_t b0 = bk.begin;
@@ -1617,6 +1642,7 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
       prm.nsegs = 1;
       prm.pair_out = nullptr;
       prm.k = k;
+      prm.drows = bk.D;
       prm.prune = cfg.prune;
       prm.memo = 0;
       prm.fingerprint = cfg.fingerprint;
@@ -1806,23 +1832,23 @@ std::map<hipStream_t, BatchWs*> g_batch;
 
 bool same_cfg(const dist_config& a, const dist_config& b) { return memcmp(&a, &b, sizeof(a)) == 0; }
 
-int occupancy_any(int W, size_t lds) {
+int occupancy_any(int W, size_t lds, bool fp) {
   switch (W) {
-    case 1: return occupancy_blocks<1>(lds);
-    case 2: return occupancy_blocks<2>(lds);
-    case 4: return occupancy_blocks<4>(lds);
-    case 8: return occupancy_blocks<8>(lds);
-    default: return occupancy_blocks<16>(lds);
+    case 1: return occupancy_blocks<1>(lds, fp);
+    case 2: return occupancy_blocks<2>(lds, fp);
+    case 4: return occupancy_blocks<4>(lds, fp);
+    case 8: return occupancy_blocks<8>(lds, fp);
+    default: return occupancy_blocks<16>(lds, fp);
   }
 }
 
-const void* kernel_of(int W) {
+const void* kernel_of(int W, bool fp) {
   switch (W) {
-    case 1: return (const void*)k_search<1, false>;
-    case 2: return (const void*)k_search<2, false>;
-    case 4: return (const void*)k_search<4, false>;
-    case 8: return (const void*)k_search<8, false>;
-    default: return (const void*)k_search<16, false>;
+    case 1: return search_kernel<1>(fp);
+    case 2: return search_kernel<2>(fp);
+    case 4: return search_kernel<4>(fp);
+    case 8: return search_kernel<8>(fp);
+    default: return search_kernel<16>(fp);
   }
 }
 
@@ -1968,12 +1994,15 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     if (units64[t][b] == 0) continue;
     BatchLaunch L{};
     L.W = kSlotWidth[b];
-    L.lds = lds_bytes(L.W, kmax[t][b], cfg.fingerprint);
+    int dmax = 1;  // widest root of the launch: each segment's first root is its widest
+    for (const auto& sg : segs[t][b]) dmax = std::max(dmax, (int)gs[sg.pair]->root_deg[sg.a]);
+    const int drows = lds_rows(L.W, dmax);
+    L.lds = lds_bytes(L.W, kmax[t][b], cfg.fingerprint, drows);
     if (L.lds > (size_t)maxlds) {
       for (auto& sg : segs[t][b]) P->status[sg.pair] = DIST_E_UNSUPPORTED;
       continue;
     }
-    int occ = occupancy_any(L.W, L.lds);
+    int occ = occupancy_any(L.W, L.lds, cfg.fingerprint != 0);
     int64_t grid = (int64_t)occ * (cus > 0 ? cus : 256);
     if (cfg.grid_pct > 0 && cfg.grid_pct < 100) grid = grid * cfg.grid_pct / 100;
     if (grid > (int64_t)units64[t][b]) grid = (int64_t)units64[t][b];
@@ -1981,6 +2010,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     Params& prm = L.prm;
     prm = Params{};
     prm.k = kmax[t][b];
+    prm.drows = drows;
     prm.prune = cfg.prune;
     prm.memo = cfg.memo;
     prm.fingerprint = cfg.fingerprint;
@@ -2022,7 +2052,8 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     L.prm.wave_out = P->d_wave_out;
     L.prm.memo_base = memo_bytes ? P->d_memo : nullptr;
     L.prm.memo_mask = memo_bytes ? entries - 1 : 0;
-    DIST_CHECK(hipFuncSetAttribute(kernel_of(L.W), hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds));
+    DIST_CHECK(hipFuncSetAttribute(kernel_of(L.W, L.prm.fingerprint != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)L.lds));
   }
   P->n = n;
   P->ks.assign(ks, ks + n);

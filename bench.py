@@ -28,7 +28,7 @@ PEAK_INT_LANE_OPS = 256 * 64 * 2.4e9
 # algorithmic lane-ops per unit of work:
 OPS_PER_WORD_OP = 4    # 2 x v_and_b32 + 2 x v_bcnt_u32_b32 on one 64-bit word
 OPS_PER_LEAF_BIT = 2   # one 64-bit add of a fingerprint weight
-BUCKET_W = [1, 2, 4, 8, 16]
+BUCKET_W = [1, 2, 3, 4, 5, 6, 8, 16]   # the library's width classes (DIST_WIDTHS)
 
 
 def parse():

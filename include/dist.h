@@ -60,6 +60,10 @@ extern "C" {
 
 #define DIST_K_MAX 64
 #define DIST_MAX_OUTDEG 1024  /* widest per-root subgraph (16 words per bitmap row) */
+/* A root's subgraph rows take the narrowest of these widths (64-bit words)
+ * that holds its out-degree. */
+#define DIST_WIDTH_CLASSES 8
+#define DIST_WIDTHS {1, 2, 3, 4, 5, 6, 8, 16}
 
 /* ---- types --------------------------------------------------------------- */
 
@@ -96,7 +100,7 @@ typedef struct {
   int32_t budget_from_pair_start; /* batches: 1 = a pair's deadline runs from
                             the moment its first work unit starts on the
                             device; 0 (default) = from the batch start */
-  int32_t min_width;     /* smallest bitmap width in words (1, 2, 4, 8, 16)
+  int32_t min_width;     /* smallest bitmap width in words (one of DIST_WIDTHS)
                             used for a root; a larger value merges the small
                             width classes of a batch into fewer launches;
                             0 = 1 */
@@ -117,12 +121,13 @@ typedef struct {
   uint64_t memo_lookups, memo_hits, memo_inserts;
   uint64_t subgraph_arcs; /* arcs read from HBM to build per-root bitmaps */
   double kernel_ms;       /* device time of the search launches */
-  /* the same, split by bitmap width W = 1, 2, 4, 8, 16 words */
-  double bucket_ms[5];
-  uint64_t bucket_roots[5];
-  uint64_t bucket_word_ops[5];
-  uint64_t bucket_leaf_bits[5];
-  uint64_t bucket_arcs[5];
+  /* the same, split by bitmap width class: W = 1, 2, 3, 4, 5, 6, 8, 16 words
+     (DIST_WIDTHS) */
+  double bucket_ms[DIST_WIDTH_CLASSES];
+  uint64_t bucket_roots[DIST_WIDTH_CLASSES];
+  uint64_t bucket_word_ops[DIST_WIDTH_CLASSES];
+  uint64_t bucket_leaf_bits[DIST_WIDTH_CLASSES];
+  uint64_t bucket_arcs[DIST_WIDTH_CLASSES];
 } dist_stats;
 
 typedef struct {

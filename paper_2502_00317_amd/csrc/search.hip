@@ -47,6 +47,7 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <type_traits>
 
 namespace {
 
@@ -1048,12 +1049,39 @@ int ws_ensure(size_t wave_words, size_t memo_bytes) {
   return DIST_OK;
 }
 
+// Width classes (words per bitmap row), widest first.  A root goes to the
+// narrowest class that holds its out-degree, so little of a row is zero.
+constexpr int kClasses = 8;
+const int kSlotWidth[kClasses] = {16, 8, 6, 5, 4, 3, 2, 1};
+
 int width_of(int d) {
-  if (d <= 64) return 1;
-  if (d <= 128) return 2;
-  if (d <= 256) return 4;
-  if (d <= 512) return 8;
+  for (int c = kClasses - 1; c >= 0; --c)
+    if (d <= 64 * kSlotWidth[c]) return kSlotWidth[c];
   return 16;
+}
+
+int wslot_of_width(int W) {
+  for (int c = 0; c < kClasses; ++c)
+    if (kSlotWidth[c] == W) return c;
+  return 0;
+}
+
+// Index into the per-class statistics (narrowest class first).
+int wslot(int W) { return kClasses - 1 - wslot_of_width(W); }
+
+// Calls f(std::integral_constant<int, W>) for a runtime class width W.
+template <class F>
+auto with_width(int W, F&& f) {
+  switch (W) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    default: return f(std::integral_constant<int, 16>{});
+  }
 }
 
 int ws_plan(size_t bytes) {
@@ -1069,21 +1097,19 @@ int ws_plan(size_t bytes) {
   return DIST_OK;
 }
 
-int wslot_of_width(int W) { return W == 16 ? 0 : W == 8 ? 1 : W == 4 ? 2 : W == 2 ? 3 : 4; }
-const int kSlotWidth[5] = {16, 8, 4, 2, 1};
 
 // Appends the work segments of pair `pair` (roots [0, nroots) of g, clique
 // size k) to the five width classes: consecutive roots with the same width
 // and the same number of units per root form one segment.
 void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, bool whole_roots, int min_w,
-                  std::vector<BatchSeg> (&segs)[5], uint64_t (&units)[5], int (&kmax)[5]) {
+                  std::vector<BatchSeg> (&segs)[kClasses], uint64_t (&units)[kClasses], int (&kmax)[kClasses]) {
   // walks the runs of equal out-degree (roots are in descending out-degree
   // order), so planning costs O(distinct degrees), not O(roots)
   int32_t a = 0;
   int cur_sl = -1, cur_upr = 0;
   int32_t seg_a = 0;
-  size_t first_seg[5];
-  for (int b = 0; b < 5; ++b) first_seg[b] = segs[b].size();
+  size_t first_seg[kClasses];
+  for (int b = 0; b < kClasses; ++b) first_seg[b] = segs[b].size();
   auto flush = [&](int32_t end) {
     if (cur_sl < 0 || end <= seg_a) return;
     segs[cur_sl].push_back(BatchSeg{(uint32_t)units[cur_sl], pair, seg_a, cur_upr, 0u});
@@ -1095,7 +1121,7 @@ void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, 
     const int d = run.first;
     const int32_t b = (int32_t)std::min<int64_t>((int64_t)a + run.second, (int64_t)nroots);
     int W = width_of(d);
-    if (W < min_w) W = min_w;
+    if (W < min_w) W = width_of(64 * min_w);  // the narrowest class of at least min_w words
     const int sl = wslot_of_width(W);
     const int upr = whole_roots ? 1 : units_per_root(d, k, auto_chunk(cw, k));
     if (sl != cur_sl || upr != cur_upr) {
@@ -1107,7 +1133,7 @@ void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, 
     a = b;
   }
   flush(a);
-  for (int b = 0; b < 5; ++b)
+  for (int b = 0; b < kClasses; ++b)
     for (size_t i = first_seg[b]; i < segs[b].size(); ++i) segs[b][i].pair_end = (uint32_t)units[b];
 }
 
@@ -1161,7 +1187,6 @@ std::vector<Bucket> make_buckets(const dist_graph* g, int32_t nroots) {
   return out;
 }
 
-int wslot(int W) { return W == 1 ? 0 : W == 2 ? 1 : W == 4 ? 2 : W == 8 ? 3 : 4; }
 
 int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_config& cfg, hipStream_t s,
                 u64* totals /* 16 */, double* ms_out, dist_stats* bst = nullptr) {
@@ -1169,15 +1194,15 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   if (nroots <= 0) return DIST_OK;
   if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
   const int cw = base.chunk_work;  // 0: automatic per k
-  std::vector<BatchSeg> segs[5];
-  uint64_t units64[5] = {0, 0, 0, 0, 0};
-  int kmax[5] = {0, 0, 0, 0, 0};
+  std::vector<BatchSeg> segs[kClasses];
+  uint64_t units64[kClasses] = {};
+  int kmax[kClasses] = {};
   add_segments(g, 0, nroots, base.k, cw, base.soft_only != 0, 1, segs, units64, kmax);
   std::vector<Bucket> buckets;
   std::vector<uint32_t> units;
   std::vector<size_t> seg_off;
   size_t nseg_total = 0;
-  for (int sl = 0; sl < 5; ++sl) {
+  for (int sl = 0; sl < kClasses; ++sl) {
     if (units64[sl] == 0) continue;
     if (units64[sl] >= 0xffffffffull) return DIST_E_UNSUPPORTED;
     // roots are in descending out-degree order: a class's first root is its widest
@@ -1201,13 +1226,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     size_t lds = lds_bytes(W, base.k, base.fingerprint, buckets[b].D);
     int occ = 1;
     const bool fp = base.fingerprint != 0;
-    switch (W) {
-      case 1: occ = occupancy_blocks<1>(lds, fp); break;
-      case 2: occ = occupancy_blocks<2>(lds, fp); break;
-      case 4: occ = occupancy_blocks<4>(lds, fp); break;
-      case 8: occ = occupancy_blocks<8>(lds, fp); break;
-      default: occ = occupancy_blocks<16>(lds, fp); break;
-    }
+    occ = with_width(W, [&](auto w) { return occupancy_blocks<decltype(w)::value>(lds, fp); });
     int cus = g_ws.cus > 0 ? g_ws.cus : 256;
     int64_t grid = (int64_t)occ * cus;
     int64_t cnt = units[b];
@@ -1244,7 +1263,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     memcpy(g_ws.h_plan, &bgh, sizeof(bgh));
     BatchSeg* hs = (BatchSeg*)(g_ws.h_plan + sizeof(BatchGraph));
     size_t o = 0;
-    for (int sl = 0; sl < 5; ++sl)
+    for (int sl = 0; sl < kClasses; ++sl)
       for (const BatchSeg& x : segs[sl]) hs[o++] = x;
     DIST_CHECK(hipMemcpyAsync(g_ws.d_plan, g_ws.h_plan, plan_bytes, hipMemcpyHostToDevice, s));
   }
@@ -1290,13 +1309,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     prm.drows = buckets[b].D;
     hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grids[b] * kOutWords);
     DIST_CHECK(hipEventRecord(kb0, s));
-    switch (buckets[b].W) {
-      case 1: rc = launch_bucket<1>(prm, grids[b], lds, s); break;
-      case 2: rc = launch_bucket<2>(prm, grids[b], lds, s); break;
-      case 4: rc = launch_bucket<4>(prm, grids[b], lds, s); break;
-      case 8: rc = launch_bucket<8>(prm, grids[b], lds, s); break;
-      default: rc = launch_bucket<16>(prm, grids[b], lds, s); break;
-    }
+    rc = with_width(buckets[b].W, [&](auto w) { return launch_bucket<decltype(w)::value>(prm, grids[b], lds, s); });
     if (rc) break;
     DIST_CHECK(hipEventRecord(kb1, s));
     DIST_CHECK(hipMemcpyAsync(g_ws.host_out, g_ws.wave_out, (size_t)grids[b] * kOutWords * sizeof(u64),
@@ -1607,13 +1620,7 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
     const size_t lds = list_lds_bytes(W, k, cfg.fingerprint, bk.D);
     if (lds > (size_t)maxlds) return DIST_E_UNSUPPORTED;
     int occ = 1;
-    switch (W) {
-      case 1: occ = occupancy_list<1>(lds, cfg.fingerprint != 0); break;
-      case 2: occ = occupancy_list<2>(lds, cfg.fingerprint != 0); break;
-      case 4: occ = occupancy_list<4>(lds, cfg.fingerprint != 0); break;
-      case 8: occ = occupancy_list<8>(lds, cfg.fingerprint != 0); break;
-      default: occ = occupancy_list<16>(lds, cfg.fingerprint != 0); break;
-    }
+    occ = with_width(W, [&](auto w) { return occupancy_list<decltype(w)::value>(lds, cfg.fingerprint != 0); });
     const int cus = g_ws.cus > 0 ? g_ws.cus : 256;
     int32_t b0 = bk.begin;
     while (b0 < bk.end && !cancelled) {
@@ -1666,13 +1673,7 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)g_ws.abort_flag, 16);
       hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)ocur.p, 16);
       hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grid * kOutWords);
-      switch (W) {
-        case 1: rc = launch_list<1>(prm, (int)grid, lds, s); break;
-        case 2: rc = launch_list<2>(prm, (int)grid, lds, s); break;
-        case 4: rc = launch_list<4>(prm, (int)grid, lds, s); break;
-        case 8: rc = launch_list<8>(prm, (int)grid, lds, s); break;
-        default: rc = launch_list<16>(prm, (int)grid, lds, s); break;
-      }
+      rc = with_width(W, [&](auto w) { return launch_list<decltype(w)::value>(prm, (int)grid, lds, s); });
       if (rc) return rc;
       u64 hc[2] = {0, 0};
       DIST_CHECK(hipMemcpyAsync(hc, ocur.p, 16, hipMemcpyDeviceToHost, s));
@@ -1740,7 +1741,7 @@ __global__ void k_zero_i32(int* p, int n) {
 // cost tiers of a streamed batch (the cursor array holds 64 launch cursors)
 constexpr int kTiers = 8;
 constexpr double kTierDecades = 2.0;
-static_assert(kTiers * 5 <= 64, "one cursor per launch");
+static_assert(kTiers * kClasses <= 64, "one cursor per launch");
 
 struct BatchLaunch {
   int W;
@@ -1833,34 +1834,16 @@ std::map<hipStream_t, BatchWs*> g_batch;
 bool same_cfg(const dist_config& a, const dist_config& b) { return memcmp(&a, &b, sizeof(a)) == 0; }
 
 int occupancy_any(int W, size_t lds, bool fp) {
-  switch (W) {
-    case 1: return occupancy_blocks<1>(lds, fp);
-    case 2: return occupancy_blocks<2>(lds, fp);
-    case 4: return occupancy_blocks<4>(lds, fp);
-    case 8: return occupancy_blocks<8>(lds, fp);
-    default: return occupancy_blocks<16>(lds, fp);
-  }
+  return with_width(W, [&](auto w) { return occupancy_blocks<decltype(w)::value>(lds, fp); });
 }
 
 const void* kernel_of(int W, bool fp) {
-  switch (W) {
-    case 1: return search_kernel<1>(fp);
-    case 2: return search_kernel<2>(fp);
-    case 4: return search_kernel<4>(fp);
-    case 8: return search_kernel<8>(fp);
-    default: return search_kernel<16>(fp);
-  }
+  return with_width(W, [&](auto w) { return search_kernel<decltype(w)::value>(fp); });
 }
 
 int launch_any(int W, const Params& prm, int grid, size_t lds, hipStream_t s) {
   // attributes were set before any capture began
-  switch (W) {
-    case 1: return launch_bucket<1>(prm, grid, lds, s, false);
-    case 2: return launch_bucket<2>(prm, grid, lds, s, false);
-    case 4: return launch_bucket<4>(prm, grid, lds, s, false);
-    case 8: return launch_bucket<8>(prm, grid, lds, s, false);
-    default: return launch_bucket<16>(prm, grid, lds, s, false);
-  }
+  return with_width(W, [&](auto w) { return launch_bucket<decltype(w)::value>(prm, grid, lds, s, false); });
 }
 
 // Lays out the batch in ws and uploads its descriptors (synchronous on s).
@@ -1886,9 +1869,9 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
   // into tiers by predicted cost (kTierDecades decades each) and are taken
   // cheapest first, so a cheap pair never waits for the launch of an
   // expensive one.
-  std::vector<BatchSeg> segs[kTiers][5];
-  uint64_t units64[kTiers][5] = {};
-  int kmax[kTiers][5] = {};
+  std::vector<BatchSeg> segs[kTiers][kClasses];
+  uint64_t units64[kTiers][kClasses] = {};
+  int kmax[kTiers][kClasses] = {};
   const int min_w = cfg.min_width > 1 ? cfg.min_width : 1;
   const int cw = cfg.chunk_work;  // 0: automatic per pair's k
   std::vector<int> order(n), tier(n, 0);
@@ -1928,14 +1911,17 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
       continue;
     }
     uint64_t* u = units64[t];
-    uint64_t before = u[0] + u[1] + u[2] + u[3] + u[4];
+    uint64_t before = 0;
+    for (int c = 0; c < kClasses; ++c) before += u[c];
     add_segments(g, i, nroots, k, cw, false, min_w, segs[t], units64[t], kmax[t]);
-    rem_init[i] = (uint32_t)(u[0] + u[1] + u[2] + u[3] + u[4] - before);
+    uint64_t after = 0;
+    for (int c = 0; c < kClasses; ++c) after += u[c];
+    rem_init[i] = (uint32_t)(after - before);
   }
   std::vector<BatchSeg> all;
-  size_t seg_off[kTiers][5];
+  size_t seg_off[kTiers][kClasses];
   for (int t = 0; t < kTiers; ++t)
-    for (int b = 0; b < 5; ++b) {
+    for (int b = 0; b < kClasses; ++b) {
       if (units64[t][b] >= 0xffffffffull) return DIST_E_UNSUPPORTED;
       seg_off[t][b] = all.size();
       all.insert(all.end(), segs[t][b].begin(), segs[t][b].end());
@@ -1990,7 +1976,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
   DIST_CHECK(hipStreamSynchronize(s));  // bg and all are host locals
   int maxgrid = 0, maxW = 1;
   for (int t = 0; t < kTiers; ++t)
-  for (int b = 0; b < 5; ++b) {
+  for (int b = 0; b < kClasses; ++b) {
     if (units64[t][b] == 0) continue;
     BatchLaunch L{};
     L.W = kSlotWidth[b];
@@ -2014,7 +2000,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     prm.prune = cfg.prune;
     prm.memo = cfg.memo;
     prm.fingerprint = cfg.fingerprint;
-    prm.cursor = P->d_cursor + (t * 5 + b);
+    prm.cursor = P->d_cursor + (t * kClasses + b);
     prm.units = (uint32_t)units64[t][b];
     prm.chunk_work = cw;
     prm.bg = P->d_bg;

@@ -19,6 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdist.so")
 
 OK, E_INVALID, E_K, E_NOMEM, E_DEVICE, E_OVERFLOW, E_CANCELLED, E_UNSUPPORTED = range(8)
+WIDTHS = (1, 2, 3, 4, 5, 6, 8, 16)   # DIST_WIDTHS: bitmap width classes (words)
+WIDTH_CLASSES = len(WIDTHS)
 ORDER_DEGREE, ORDER_DEGENERACY = 0, 1
 K_MAX = 64
 P61 = (1 << 61) - 1
@@ -53,9 +55,10 @@ class Stats(ctypes.Structure):
                 ("leaf_bits", ctypes.c_uint64), ("memo_lookups", ctypes.c_uint64),
                 ("memo_hits", ctypes.c_uint64), ("memo_inserts", ctypes.c_uint64),
                 ("subgraph_arcs", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
-                ("bucket_ms", ctypes.c_double * 5), ("bucket_roots", ctypes.c_uint64 * 5),
-                ("bucket_word_ops", ctypes.c_uint64 * 5), ("bucket_leaf_bits", ctypes.c_uint64 * 5),
-                ("bucket_arcs", ctypes.c_uint64 * 5)]
+                ("bucket_ms", ctypes.c_double * WIDTH_CLASSES), ("bucket_roots", ctypes.c_uint64 * WIDTH_CLASSES),
+                ("bucket_word_ops", ctypes.c_uint64 * WIDTH_CLASSES),
+                ("bucket_leaf_bits", ctypes.c_uint64 * WIDTH_CLASSES),
+                ("bucket_arcs", ctypes.c_uint64 * WIDTH_CLASSES)]
 
     def as_dict(self):
         out = {}

@@ -52,7 +52,9 @@
 namespace {
 
 constexpr int kOutWords = 16;
-constexpr int kMemoProbe = 4;
+// The memo table is direct-mapped: a key lives in its home slot only, so an
+// insert is a plain store (no read first) and a lookup reads one entry.
+constexpr int kMemoProbe = 1;
 // A root stops using its memo table once at least kMemoMinLook lookups
 // found fewer than one hit in kMemoMinRatio (the table is a cache: using it
 // or not never changes a result).
@@ -146,9 +148,10 @@ __device__ __forceinline__ u64 memo_hash(u64 tag, const u64* P, int x) {
   return h;
 }
 
-// The wave's lanes cover (probe slot, entry word) pairs: every word of every
-// probed entry is loaded by its own lane in one round, so a lookup or an
-// insert costs one memory latency and each lane holds a single word.
+// A lookup's lanes cover (key, entry word) pairs: every word of every probed
+// entry is loaded by its own lane in one round, so a lookup of one key, or of
+// a node's prefixes together, costs one memory latency and each lane holds a
+// single word.
 
 // Wave-collective lookup of the keys P & [cut_i, inf), i = 0..ncut-1, where
 // cut_i = cuts[i] (cuts == nullptr: one key, no cut).  Returns the smallest i
@@ -185,37 +188,20 @@ __device__ __forceinline__ int memo_find(const Params& p, const u64* table, u64 
   return -1;
 }
 
-// Wave-collective insert of (tag, P & [x, inf)) -> (lo, hi, fp).  Reuses the
-// slot holding the same key, else the first slot not owned by the current
-// root, else evicts the home slot; the entry is written one word per lane.
+// Wave-collective insert of (tag, P & [x, inf)) -> (lo, hi, fp) into the
+// key's home slot, one entry word per lane (a coalesced store; an older entry
+// there is evicted).
 template <int W>
-__device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, u64 root_tag, const u64* P, int x,
-                                         u64 lo, u64 hi, u64 fp) {
+__device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, const u64* P, int x, u64 lo, u64 hi,
+                                         u64 fp) {
   constexpr int ES = W + 4;
-  constexpr int KS = W + 1;  // tag and key words
-  constexpr int GPR = kWave / KS;
   const int lane = lane_id();
-  const u64 h = memo_hash<W>(tag, P, x);
-  int same = -1, free_slot = -1;
-  for (int g0 = 0; g0 < kMemoProbe; g0 += GPR) {
-    const int gi = lane / KS, w = lane % KS, t = g0 + gi;
-    bool ok = false, fr = false;
-    if (gi < GPR && t < kMemoProbe) {
-      const u64 v = ld_coherent(table + ((h + (u64)t) & p.memo_mask) * ES + w);
-      ok = v == (w == 0 ? tag : (P[w - 1] & cut_mask(x, w - 1)));
-      fr = w == 0 && (v >> 8) != root_tag;
-    }
-    const u64 b = __ballot(ok), bf = __ballot(fr);
-    constexpr u64 kFull = (KS >= 64) ? ~0ull : ((1ull << KS) - 1);
-    for (int q = 0; q < GPR && g0 + q < kMemoProbe; ++q) {
-      if (same < 0 && ((b >> (q * KS)) & kFull) == kFull) same = g0 + q;
-      if (free_slot < 0 && ((bf >> (q * KS)) & 1ull)) free_slot = g0 + q;
-    }
-  }
-  const int pick = same >= 0 ? same : (free_slot >= 0 ? free_slot : 0);
   if (lane < ES) {
-    u64 v = lane == 0 ? tag : (lane <= W ? (P[lane - 1] & cut_mask(x, lane - 1)) : (lane == W + 1 ? lo : (lane == W + 2 ? hi : fp)));
-    table[((h + (u64)pick) & p.memo_mask) * ES + lane] = v;
+    const u64 h = memo_hash<W>(tag, P, x);
+    const u64 v = lane == 0 ? tag
+                            : (lane <= W ? (P[lane - 1] & cut_mask(x, lane - 1))
+                                         : (lane == W + 1 ? lo : (lane == W + 2 ? hi : fp)));
+    table[(h & p.memo_mask) * ES + lane] = v;
   }
 }
 
@@ -667,7 +653,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
               res_hi = chi;
               res_fp = FP ? esym_members(s.mem, np, s.gl, 3) : 0;
                 if (memo_j && memo_live) {
-                memo_put<W>(p, table, tag, root_tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+                memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
                 ++n_ins;
               }
               __syncthreads();
@@ -747,7 +733,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           res_lo = wave_sum(c_acc);
           res_hi = 0;
           res_fp = FP ? wave_sum_p(f_acc) : 0;
-          if (memo_j && memo_live && j > 0) memo_put<W>(p, table, tag, root_tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+          if (memo_j && memo_live && j > 0) memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
           if (memo_j && memo_live && j > 0) ++n_ins;
           __syncthreads();
           mode = FINISH;
@@ -867,7 +853,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             u64 Pr[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) Pr[w] = s.stP[j * W + w];
-            memo_put<W>(p, table, (root_tag << 8) | (u64)l, root_tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+            memo_put<W>(p, table, (root_tag << 8) | (u64)l, s.stP + j * W, -1, res_lo, res_hi, res_fp);
             ++n_ins;
           }
           __syncthreads();
@@ -903,7 +889,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         }
         if (s.stMemo[j] && memo_live && j > 0) {
           // trie node t_i = P & [x, inf) is now complete for l
-          memo_put<W>(p, table, (root_tag << 8) | (u64)l, root_tag, s.stP + j * W, x, lo, hi, f);
+          memo_put<W>(p, table, (root_tag << 8) | (u64)l, s.stP + j * W, x, lo, hi, f);
           ++n_ins;
         }
         __syncthreads();

@@ -379,6 +379,101 @@ __device__ __forceinline__ u64 esym_members(const uint16_t* mem, int np, const u
   return __shfl(e, l);
 }
 
+// Nearly complete candidate sets (counts only): if G[P] misses e <= 6 edges,
+// its l-cliques are the l-subsets of P containing none of them; by
+// inclusion-exclusion over the subsets S of the missing edges,
+//   count = sum_S (-1)^|S| C(|P| - |V(S)|, l - |V(S)|),
+// V(S) the endpoints of S.  Lane S takes one subset.  Exact.
+constexpr int kNearMissing = 6;
+
+__device__ __forceinline__ void wave_sum128(u64& lo, u64& hi) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const u64 lo2 = __shfl_xor(lo, off), hi2 = __shfl_xor(hi, off);
+    const u64 nlo = lo + lo2;
+    hi = hi + hi2 + (nlo < lo ? 1ull : 0ull);
+    lo = nlo;
+  }
+}
+
+// pairs: the e missing edges as local-id pairs (2e entries) in LDS.
+__device__ __forceinline__ bool near_complete_count(const uint16_t* pairs, int e, int np, int l, u64& lo, u64& hi) {
+  const int lane = lane_id();
+  u64 plo = 0, phi = 0, nlo = 0, nhi = 0;  // positive and negative terms
+  bool ok = true;
+  if (lane < (1 << e)) {
+    int ends[2 * kNearMissing];
+    int v = 0;
+    for (int i = 0; i < e; ++i) {
+      if (!((lane >> i) & 1)) continue;
+      for (int t = 0; t < 2; ++t) {
+        const int a = pairs[2 * i + t];
+        bool seen = false;
+        for (int q = 0; q < v; ++q) seen = seen || ends[q] == a;
+        if (!seen) ends[v++] = a;
+      }
+    }
+    if (v <= l) {
+      u64 clo, chi;
+      ok = binom128(np - v, l - v, clo, chi);
+      if (__popc((unsigned)lane) & 1) {
+        nlo = clo;
+        nhi = chi;
+      } else {
+        plo = clo;
+        phi = chi;
+      }
+    }
+  }
+  if (__ballot(!ok)) return false;
+  wave_sum128(plo, phi);
+  wave_sum128(nlo, nhi);
+  lo = plo - nlo;
+  hi = phi - nhi - (plo < nlo ? 1ull : 0ull);
+  return true;
+}
+
+// Collects the missing edges of G[P] (members mem[0..np), candidate words Pr)
+// into pairs (at most kNearMissing are stored); returns how many there are.
+template <int W>
+__device__ __forceinline__ int missing_edges(const Lds& s, const u64 (&Pr)[W], int np, uint16_t* pairs) {
+  const int lane = lane_id();
+  int base = 0;
+  for (int b0 = 0; b0 < np; b0 += kWave) {
+    const int i = b0 + lane;
+    int c = 0;
+    int x = 0;
+    if (i < np) {
+      x = s.mem[i];
+#pragma unroll
+      for (int w = 0; w < W; ++w) c += __popcll(Pr[w] & cut_mask(x + 1, w) & ~s.A[x * W + w]);
+    }
+    int incl = c;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int t = __shfl_up(incl, off);
+      if (lane >= off) incl += t;
+    }
+    int o = base + incl - c;
+    if (c) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        u64 b = Pr[w] & cut_mask(x + 1, w) & ~s.A[x * W + w];
+        while (b) {
+          const int t = __ffsll((unsigned long long)b) - 1;
+          b &= b - 1;
+          if (o < kNearMissing) {
+            pairs[2 * o] = (uint16_t)x;
+            pairs[2 * o + 1] = (uint16_t)(w * 64 + t);
+          }
+          ++o;
+        }
+      }
+    }
+    base += __shfl(incl, kWave - 1);
+  }
+  __syncthreads();
+  return base;
+}
+
 // ---- the kernel ----------------------------------------------------------------
 
 template <int W, bool EMIT, bool FP>
@@ -648,6 +743,24 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             wops += (u64)((np + kWave - 1 - lane) / kWave) * W;
             m = wave_sum(m);
             u64 clo, chi;
+            if constexpr (!FP) {
+              const u64 full = (u64)np * (u64)(np - 1) / 2;
+              if (m < full && full - m <= (u64)kNearMissing) {
+                const int e = missing_edges<W>(s, Pr, np, s.pos);
+                if (e == (int)(full - m) && near_complete_count(s.pos, e, np, 3, clo, chi)) {
+                  res_lo = clo;
+                  res_hi = chi;
+                  res_fp = 0;
+                  if (memo_j && memo_live) {
+                    memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+                    ++n_ins;
+                  }
+                  __syncthreads();
+                  mode = FINISH;
+                  continue;
+                }
+              }
+            }
             if (m == (u64)np * (u64)(np - 1) / 2 && binom128(np, 3, clo, chi)) {
               res_lo = clo;
               res_hi = chi;
@@ -765,6 +878,21 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             __syncthreads();
             mode = FINISH;
             continue;
+          }
+        }
+        if constexpr (!EMIT && !FP) {
+          const u64 full = (u64)np * (u64)(np - 1) / 2;
+          if (j > 0 && m_edges < full && full - m_edges <= (u64)kNearMissing) {
+            const int e = missing_edges<W>(s, Pr, np, s.pos);
+            u64 clo, chi;
+            if (e == (int)(full - m_edges) && near_complete_count(s.pos, e, np, l, clo, chi)) {
+              res_lo = clo;
+              res_hi = chi;
+              res_fp = 0;
+              __syncthreads();
+              mode = FINISH;
+              continue;
+            }
           }
         }
         if (!memo_j && p.memo == 1 && memo_live) {

@@ -168,3 +168,27 @@ def test_wide_roots(D, n, r, ks):
         for cfg in (dict(memo=1, prune=1), dict(memo=0, prune=1)):
             print("wide", n, r, k, cfg, flush=True)
             assert _gpu(D, g, k, D.ORDER_DEGREE, **cfg) == want
+
+
+@pytest.mark.parametrize("n,removed,seed", [(40, 1, 0), (40, 3, 1), (60, 5, 2), (90, 6, 3), (90, 9, 4)])
+def test_nearly_complete(D, oracle_mod, n, removed, seed):
+    """Complete graphs minus a few edges: candidate sets that miss 1..6 edges
+    (counted by inclusion-exclusion without fingerprints) and more (searched),
+    against the oracle's pivot-based counter (pinned against enumeration)."""
+    rng = np.random.default_rng(700 + seed)
+    iu, ju = np.triu_indices(n, 1)
+    drop = rng.choice(len(iu), size=removed, replace=False)
+    keep = np.ones(len(iu), bool)
+    keep[drop] = False
+    g = gg.csr_from_edges(n, iu[keep], ju[keep], name="K%d-%d" % (n, removed))
+    P61 = (1 << 61) - 1
+    for k in (3, 4, 5, 7, 9):
+        per = oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, np.arange(n, dtype=np.int32))
+        want = (sum(c for c, _ in per), sum(f for _, f in per) % P61)
+        for order in (D.ORDER_DEGREE, D.ORDER_DEGENERACY):
+            for cfg in (dict(memo=1, prune=1), dict(memo=0, prune=0)):
+                print("near", n, removed, k, order, cfg, flush=True)
+                G = D.orient(g.row_ptr, g.col, order=order)
+                c, f, rc = D.count(G, k, cfg=D.config(fingerprint=0, **cfg))
+                assert c == want[0], (k, order, cfg)
+                assert _gpu(D, g, k, order, **cfg) == want

@@ -379,12 +379,12 @@ __device__ __forceinline__ u64 esym_members(const uint16_t* mem, int np, const u
   return __shfl(e, l);
 }
 
-// Nearly complete candidate sets (counts only): if G[P] misses e <= 6 edges,
+// Nearly complete candidate sets (counts only): if G[P] misses e <= 8 edges,
 // its l-cliques are the l-subsets of P containing none of them; by
 // inclusion-exclusion over the subsets S of the missing edges,
 //   count = sum_S (-1)^|S| C(|P| - |V(S)|, l - |V(S)|),
-// V(S) the endpoints of S.  Lane S takes one subset.  Exact.
-constexpr int kNearMissing = 6;
+// V(S) the endpoints of S.  Lanes take the 2^e subsets in turn.  Exact.
+constexpr int kNearMissing = 8;
 
 __device__ __forceinline__ void wave_sum128(u64& lo, u64& hi) {
   for (int off = 32; off > 0; off >>= 1) {
@@ -400,11 +400,11 @@ __device__ __forceinline__ bool near_complete_count(const uint16_t* pairs, int e
   const int lane = lane_id();
   u64 plo = 0, phi = 0, nlo = 0, nhi = 0;  // positive and negative terms
   bool ok = true;
-  if (lane < (1 << e)) {
+  for (int S = lane; S < (1 << e); S += kWave) {
     int ends[2 * kNearMissing];
     int v = 0;
     for (int i = 0; i < e; ++i) {
-      if (!((lane >> i) & 1)) continue;
+      if (!((S >> i) & 1)) continue;
       for (int t = 0; t < 2; ++t) {
         const int a = pairs[2 * i + t];
         bool seen = false;
@@ -414,13 +414,15 @@ __device__ __forceinline__ bool near_complete_count(const uint16_t* pairs, int e
     }
     if (v <= l) {
       u64 clo, chi;
-      ok = binom128(np - v, l - v, clo, chi);
-      if (__popc((unsigned)lane) & 1) {
-        nlo = clo;
-        nhi = chi;
+      ok = ok && binom128(np - v, l - v, clo, chi);
+      if (__popc((unsigned)S) & 1) {
+        const u64 t = nlo + clo;
+        nhi += chi + (t < nlo ? 1ull : 0ull);
+        nlo = t;
       } else {
-        plo = clo;
-        phi = chi;
+        const u64 t = plo + clo;
+        phi += chi + (t < plo ? 1ull : 0ull);
+        plo = t;
       }
     }
   }

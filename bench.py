@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--cpu-stride", type=int, default=8, help="oracle sample: every s-th vertex as root")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain-equiv", action="store_true",
+                    help="skip the per-root i-clique counts behind the plain-equivalent work figure "
+                         "(--no-cpu skips them too)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (4,096 graph) section")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
@@ -153,10 +156,23 @@ def summarize_profiles(d):
                  "",
                  "| kernel | calls | total ms | average ms | % |",
                  "|---|---|---|---|---|"]
+        per_w = {}
         for r in csv.DictReader(open(stats[0])):
             name = r["Name"].replace("void (anonymous namespace)::", "").replace("((anonymous namespace)::Params)", "(Params)")
             lines.append("| %s | %s | %.3f | %.3f | %.2f |" % (name, r["Calls"], float(r["TotalDurationNs"]) / 1e6,
                                                            float(r["AverageNs"]) / 1e6, float(r["Percentage"])))
+            if name.startswith("k_search<"):
+                e = per_w.setdefault("k_search<%s>" % name.split("<")[1].split(",")[0], [0, 0.0])
+                e[0] += int(r["Calls"])
+                e[1] += float(r["TotalDurationNs"]) / 1e6
+        lines += ["",
+                  "Per width class, all instantiations together (the figure bench.py's",
+                  "roofline.avg_launch_ms is compared with):",
+                  "",
+                  "| kernel | launches | total ms | average ms per launch |",
+                  "|---|---|---|---|"]
+        for kname, (n, ms) in sorted(per_w.items()):
+            lines.append("| %s | %d | %.3f | %.3f |" % (kname, n, ms, ms / max(n, 1)))
         with open(os.path.join(ROOT, "profiles", "k_search_cfg2_kernel_stats.md"), "w") as f:
             f.write("\n".join(lines) + "\n")
     print(json.dumps(out)[:400])
@@ -320,6 +336,39 @@ def main():
         dnf = {"k": a.k_dnf, "deadline_ms": a.dnf_deadline_ms,
                "status": "finished" if rc in (dist.OK, dist.E_OVERFLOW) else "DNF",
                "count": cnt, "fp": fp, "roots_done": st.roots, "kernel_ms": st.kernel_ms}
+
+    # ---- plain-equivalent work (not timed) ----
+    # A plain depth-first search over the same bitmaps computes one candidate
+    # bitmap of W(u) words per i-clique rooted at u, i = 2..k-1; counting all
+    # of them (4 lane-ops per word) overestimates the plain work slightly,
+    # since the plain search skips children whose candidates are too few.
+    if not (a.no_plain_equiv or a.no_cpu):
+        rank = G.ranks(stream=stream).astype(np.int64)
+        deg = np.diff(g.row_ptr).astype(np.int64)
+        src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+        outd = np.bincount(src[rank[src] < rank[g.col]], minlength=g.n)
+        wid = np.zeros(g.n, np.float64)
+        for w in reversed(BUCKET_W):
+            wid[outd <= 64 * w] = w
+        ci = {2: outd.astype(np.float64)}
+        per = torch.zeros(3 * g.n, dtype=torch.int64, device="cuda")
+        for i in range(3, max(ks)):
+            per.zero_()
+            dist.count(G, i, cfg=dist.config(fingerprint=0), per_root=per, stream=stream)
+            torch.cuda.synchronize()
+            h = per.cpu().numpy().view(np.uint64)
+            ci[i] = h[0::3].astype(np.float64) + h[1::3].astype(np.float64) * 2.0 ** 64
+        pe_ops = 0.0
+        pe_ms = 0.0
+        for k in ks:
+            searched = outd >= k - 1
+            pe_ops += OPS_PER_WORD_OP * float(np.sum(wid[searched] * sum(ci[i][searched] for i in range(2, k))))
+            pe_ms += float(np.median(per_k[k]["kernel_ms"]))
+        rate = pe_ops / (pe_ms / 1e3) / 1e12
+        roofline["plain_equiv"] = {"lane_ops": pe_ops, "search_ms": round(pe_ms, 3), "rate": round(rate, 2),
+                                   "unit": "Tlane-op/s", "x_peak": round(rate / peak, 2)}
+        log("plain-equivalent work: %.3g lane-ops in %.0f ms of search, %.3g T lane-op/s (%.1fx the VALU peak)" % (
+            pe_ops, pe_ms, rate, rate / peak))
 
     # ---- sampled parity at full size: per-root results vs the oracle ----
     cpu = None

@@ -34,7 +34,7 @@ BUCKET_W = [1, 2, 3, 4, 5, 6, 8, 16]   # the library's width classes (DIST_WIDTH
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--ks", default="5,7,9")
     ap.add_argument("--fp-ks", default="5", help="ks whose fingerprint is computed (the rest: exact count only)")
@@ -82,6 +82,17 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def summarize_profiles(d):
@@ -372,6 +383,7 @@ def main():
 
     # ---- sampled parity at full size: per-root results vs the oracle ----
     cpu = None
+    cpu_context = None
     parity = None
     if not a.no_cpu:
         import oracle
@@ -396,6 +408,24 @@ def main():
         cpu = {"value": sample_cliques / cpu_s, "unit": "k-cliques/s", "cores": threads, "kind": "oracle",
                "sample": "k=%d, every %d-th vertex id as root (%d roots, %d cliques, %.1f s)" % (
                    kc, a.cpu_stride, len(sample), sample_cliques, cpu_s)}
+        # context: the host CPU, the oracle on one thread and the pivot-based
+        # reference, on a 16x smaller sample of the same roots
+        small = sample[::16]
+        t1 = time.perf_counter()
+        w1 = oracle.count_roots(g.row_ptr, g.col, kc, small, nthreads=1)
+        s1 = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        wp = oracle.pivot_count_roots(g.row_ptr, g.col, kc, small, nthreads=threads)
+        sp = time.perf_counter() - t1
+        assert wp == w1 == [want[i] for i in range(0, len(sample), 16)], "oracle and pivot reference disagree"
+        c1 = sum(c for c, _ in w1)
+        cpu_context = {"cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+                       "sample": "k=%d, every %d-th vertex id as root (%d roots, %d cliques)" % (
+                           kc, a.cpu_stride * 16, len(small), c1),
+                       "oracle_1thread": {"value": c1 / s1, "unit": "k-cliques/s", "s": round(s1, 3)},
+                       "pivot_%dthreads" % threads: {"value": c1 / sp, "unit": "k-cliques/s", "s": round(sp, 3)}}
+        log("oracle on 1 thread: %.3g k-cliques/s; pivot reference on %d threads: %.3g k-cliques/s" % (
+            c1 / s1, threads, c1 / sp))
 
     batched = None
     if batch_graphs is not None:
@@ -429,6 +459,7 @@ def main():
         "k_dnf": dnf,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_context": cpu_context,
         "parity_sampled_roots": parity,
         "batched": batched,
         "serving": serving,

@@ -104,6 +104,11 @@ typedef struct {
                             used for a root; a larger value merges the small
                             width classes of a batch into fewer launches;
                             0 = 1 */
+  int32_t sub_units;     /* k >= 6: each unit of depth-1 children is shared by
+                            this many work units, each taking every
+                            sub_units-th surviving depth-2 child (results do
+                            not depend on it); 0 = auto (more for wide roots
+                            at large k, up to 32); larger values count as 32 */
 } dist_config;
 
 typedef struct {

@@ -81,6 +81,7 @@ struct BatchSeg {
   int32_t a;          // first root (index into the pair's roots array)
   int32_t upr;        // work units per root in this segment (>= 1)
   uint32_t pair_end;  // end of the pair's units in this launch (they are contiguous)
+  int32_t sub;        // units per range of depth-1 children (>= 1; upr is a multiple)
 };
 
 struct Params {
@@ -222,6 +223,9 @@ __host__ __device__ inline int units_per_root(int d, int k, int chunk_work) {
   if (c >= d) return 1;
   return (d + c - 1) / c;
 }
+
+// At most this many units share one range of depth-1 children (k >= 6).
+constexpr int kMaxSub = 32;
 
 // ---- listing: record slots and sorted records ----------------------------------
 
@@ -529,8 +533,12 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
     pair = sg.pair;
     const uint32_t off = u - sg.unit_begin;
     const int rel = sg.a + (int)(off / (uint32_t)sg.upr);
-    const int ci = (int)(off % (uint32_t)sg.upr);
     const int upr = sg.upr;
+    // a root's units: upr / nsub ranges of depth-1 children, each split into
+    // nsub units that take every nsub-th surviving depth-2 child
+    const int nsub = sg.sub;
+    const int ci = (int)(off % (uint32_t)upr) / nsub;
+    const int sub = (int)(off % (uint32_t)upr) % nsub;
     {
       const BatchGraph bgr = p.bg[pair];
       Gdptr = bgr.dptr;
@@ -610,14 +618,17 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
       __syncthreads();
     }
     if (cur_pruned) {
-      if (ci == 0 && !p.soft_only) ++n_pruned;
+      if (ci == 0 && sub == 0 && !p.soft_only) ++n_pruned;
       finish_units(p, pair, 1u);
       continue;
     }
     // children of frame 0 handled by this unit: local ids [x_lo, x_hi)
-    const int ch = (d + upr - 1) / upr;
+    const int ch = (d + upr / nsub - 1) / (upr / nsub);
     const int x_lo = ci * ch < d ? ci * ch : d;
     const int x_hi = x_lo + ch < d ? x_lo + ch : d;
+    // with nsub > 1, frame 1 holds only part of its subtree: it neither reads
+    // nor writes memo entries, and its closed forms count in sub-unit 0 only
+    const int jsplit = nsub > 1 ? 1 : -1;
 
     // ---- 3. depth-first search over candidate bitmaps -----------------------------
     // frame j needs l = k-1-j more vertices from its candidate set stP[j].
@@ -691,7 +702,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         if (p.memo == 2) memo_j = (l >= 3);
         else if (p.memo == 1) memo_j = (l >= 3) && j > 0 && s.stMemo[j - 1];
         const u64 tag = (root_tag << 8) | (u64)l;
-        if (memo_j && memo_live && j > 0) {
+        if (memo_j && memo_live && j > 0 && j != jsplit) {
           ++n_look;
           ++r_look;
           u64 a, b, c;
@@ -714,6 +725,12 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
         }
         __syncthreads();
         if (l == 2 || l == 3) {
+          if (j == jsplit && sub != 0) {
+            // a leaf frame is not shared out: sub-unit 0 takes all of it
+            res_lo = res_hi = res_fp = 0;
+            mode = FINISH;
+            continue;
+          }
           int npre = 0;
           if constexpr (EMIT) {
             // sorted input ids of the chosen vertices: root and stX[0..j)
@@ -877,6 +894,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             res_lo = clo;
             res_hi = chi;
             res_fp = FP ? esym_members(s.mem, np, s.gl, l) : 0;
+            if (j == jsplit && sub != 0) res_lo = res_hi = res_fp = 0;
             __syncthreads();
             mode = FINISH;
             continue;
@@ -891,6 +909,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
               res_lo = clo;
               res_hi = chi;
               res_fp = 0;
+              if (j == jsplit && sub != 0) res_lo = res_hi = 0;
               __syncthreads();
               mode = FINISH;
               continue;
@@ -904,7 +923,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           if (np >= 2 && lhs > rhs) {
             memo_j = true;
           }
-          if (memo_j && j > 0) {
+          if (memo_j && j > 0 && j != jsplit) {
             ++n_look;
             ++r_look;
             u64 a, b, c;
@@ -929,7 +948,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             Q[lane] &= m_lo & m_hi;
           }
         }
-        if (memo_j && memo_live && np >= 2 && j > 0) {
+        if (memo_j && memo_live && np >= 2 && j > 0 && j != jsplit) {
           // resume from the longest memoised proper prefix P & [m_i, inf),
           // m_i the i-th smallest member, i = 1..kMemoProbe, all probed at once
           const int ncut = np - 1 < kMemoProbe ? np - 1 : kMemoProbe;
@@ -952,6 +971,27 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
             }
           }
           if (r_look >= kMemoMinLook && r_hit * kMemoMinRatio < r_look) memo_live = false;
+        }
+        if (j == jsplit) {
+          // this unit's share of frame 1's children: every nsub-th survivor
+          // in ascending order, starting at the sub-th
+          const int cnt = lane < W ? __popcll(Q[lane]) : 0;
+          int incl = cnt;
+          for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+          }
+          if (lane < W) {
+            u64 qw = Q[lane], keep = 0;
+            int pos = incl - cnt;
+            while (qw) {
+              const int b = __ffsll((unsigned long long)qw) - 1;
+              qw &= qw - 1;
+              if (pos % nsub == sub) keep |= 1ull << b;
+              ++pos;
+            }
+            Q[lane] = keep;
+          }
         }
         if (lane == 0) {
           s.stCnt[2 * j] = acc_lo;
@@ -979,7 +1019,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           res_lo = s.stCnt[2 * j];
           res_hi = s.stCnt[2 * j + 1];
           res_fp = s.stFp[j];
-          if (s.stMemo[j] && memo_live && j > 0) {
+          if (s.stMemo[j] && memo_live && j > 0 && j != jsplit) {
             u64 Pr[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) Pr[w] = s.stP[j * W + w];
@@ -1017,7 +1057,7 @@ __global__ __launch_bounds__(64) void k_search(Params p) {
           s.stCnt[2 * j + 1] = hi;
           s.stFp[j] = f;
         }
-        if (s.stMemo[j] && memo_live && j > 0) {
+        if (s.stMemo[j] && memo_live && j > 0 && j != jsplit) {
           // trie node t_i = P & [x, inf) is now complete for l
           memo_put<W>(p, table, (root_tag << 8) | (u64)l, s.stP + j * W, x, lo, hi, f);
           ++n_ins;
@@ -1214,21 +1254,60 @@ int ws_plan(size_t bytes) {
 }
 
 
+// Units per range of depth-1 children, for each width class of one count.
+// forced > 0 sets it for every class.  Else (automatic) a class is split only
+// where its launch would wait on its heaviest unit: a depth-1 subtree costs
+// roughly (d/64)^(k-3), the first child of a root about 2^(k-4) times the
+// mean over its children, and a launch of W waves ideally takes
+// sum(cost) / W; where the heaviest unit exceeds that, each child of a
+// single-child unit is shared by up to kMaxSub units.
+void split_children(const dist_graph* g, int32_t nroots, int k, int cw, int forced, int (&sub_of)[kClasses]) {
+  for (int& x : sub_of) x = 1;
+  if (k < 6) return;
+  if (forced > 0) {
+    for (int& x : sub_of) x = forced < kMaxSub ? forced : kMaxSub;
+    return;
+  }
+  const int cwk = auto_chunk(cw, k);
+  double total[kClasses] = {}, heavy[kClasses] = {};
+  int32_t a = 0;
+  for (const auto& run : g->deg_hist) {
+    if (a >= nroots) break;
+    const int d = run.first;
+    const int32_t cnt = (int32_t)std::min<int64_t>(run.second, (int64_t)nroots - a);
+    a += cnt;
+    const int sl = wslot_of_width(width_of(d));
+    const double child = std::pow((double)d / 64.0, (double)(k - 3));
+    total[sl] += (double)cnt * (double)d * child;
+    if (d > 64 && cwk / d <= 1 && child > heavy[sl]) heavy[sl] = child;
+  }
+  const double waves = 8.0 * (g_ws.cus > 0 ? g_ws.cus : 256);
+  for (int sl = 0; sl < kClasses; ++sl) {
+    if (heavy[sl] <= 0 || total[sl] <= 0) continue;
+    const double r = heavy[sl] * std::ldexp(1.0, k - 4) * waves / total[sl];
+    if (r <= 1.0) continue;
+    int sub = 2;
+    while (sub < kMaxSub && sub < 2.0 * r) sub <<= 1;
+    sub_of[sl] = sub;
+  }
+}
+
 // Appends the work segments of pair `pair` (roots [0, nroots) of g, clique
-// size k) to the five width classes: consecutive roots with the same width
-// and the same number of units per root form one segment.
+// size k) to the width classes: consecutive roots with the same width and the
+// same split into units form one segment.
 void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, bool whole_roots, int min_w,
-                  std::vector<BatchSeg> (&segs)[kClasses], uint64_t (&units)[kClasses], int (&kmax)[kClasses]) {
+                  const int (&sub_of)[kClasses], std::vector<BatchSeg> (&segs)[kClasses],
+                  uint64_t (&units)[kClasses], int (&kmax)[kClasses]) {
   // walks the runs of equal out-degree (roots are in descending out-degree
   // order), so planning costs O(distinct degrees), not O(roots)
   int32_t a = 0;
-  int cur_sl = -1, cur_upr = 0;
+  int cur_sl = -1, cur_upr = 0, cur_sub = 1;
   int32_t seg_a = 0;
   size_t first_seg[kClasses];
   for (int b = 0; b < kClasses; ++b) first_seg[b] = segs[b].size();
   auto flush = [&](int32_t end) {
     if (cur_sl < 0 || end <= seg_a) return;
-    segs[cur_sl].push_back(BatchSeg{(uint32_t)units[cur_sl], pair, seg_a, cur_upr, 0u});
+    segs[cur_sl].push_back(BatchSeg{(uint32_t)units[cur_sl], pair, seg_a, cur_upr, 0u, cur_sub});
     units[cur_sl] += (uint64_t)(end - seg_a) * (uint64_t)cur_upr;
     if (k > kmax[cur_sl]) kmax[cur_sl] = k;
   };
@@ -1239,11 +1318,13 @@ void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, 
     int W = width_of(d);
     if (W < min_w) W = width_of(64 * min_w);  // the narrowest class of at least min_w words
     const int sl = wslot_of_width(W);
-    const int upr = whole_roots ? 1 : units_per_root(d, k, auto_chunk(cw, k));
-    if (sl != cur_sl || upr != cur_upr) {
+    const int sub = (whole_roots || k < 6) ? 1 : sub_of[sl];
+    const int upr = whole_roots ? 1 : units_per_root(d, k, auto_chunk(cw, k)) * sub;
+    if (sl != cur_sl || upr != cur_upr || sub != cur_sub) {
       flush(a);
       cur_sl = sl;
       cur_upr = upr;
+      cur_sub = sub;
       seg_a = a;
     }
     a = b;
@@ -1313,7 +1394,9 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   std::vector<BatchSeg> segs[kClasses];
   uint64_t units64[kClasses] = {};
   int kmax[kClasses] = {};
-  add_segments(g, 0, nroots, base.k, cw, base.soft_only != 0, 1, segs, units64, kmax);
+  int sub_of[kClasses];
+  split_children(g, nroots, base.k, cw, cfg.sub_units, sub_of);
+  add_segments(g, 0, nroots, base.k, cw, base.soft_only != 0, 1, sub_of, segs, units64, kmax);
   std::vector<Bucket> buckets;
   std::vector<uint32_t> units;
   std::vector<size_t> seg_off;
@@ -1753,7 +1836,7 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
       if (rc) return rc;
       {
         BatchGraph bgh{g->dptr, g->dcol, g->orig, g->roots, g->gw, k, 0};
-        BatchSeg sg{0u, 0, b0, 1, (uint32_t)(b1 - b0)};
+        BatchSeg sg{0u, 0, b0, 1, (uint32_t)(b1 - b0), 1};
         memcpy(g_ws.h_plan, &bgh, sizeof(bgh));
         memcpy(g_ws.h_plan + sizeof(BatchGraph), &sg, sizeof(sg));
         DIST_CHECK(hipMemcpyAsync(g_ws.d_plan, g_ws.h_plan, sizeof(BatchGraph) + sizeof(BatchSeg),
@@ -1989,6 +2072,9 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
   uint64_t units64[kTiers][kClasses] = {};
   int kmax[kTiers][kClasses] = {};
   const int min_w = cfg.min_width > 1 ? cfg.min_width : 1;
+  // batches split depth-1 children only on request: their graphs are small
+  int sub_of[kClasses];
+  for (int& x : sub_of) x = cfg.sub_units > 0 ? std::min(cfg.sub_units, kMaxSub) : 1;
   const int cw = cfg.chunk_work;  // 0: automatic per pair's k
   std::vector<int> order(n), tier(n, 0);
   for (int i = 0; i < n; ++i) order[i] = i;
@@ -2029,7 +2115,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     uint64_t* u = units64[t];
     uint64_t before = 0;
     for (int c = 0; c < kClasses; ++c) before += u[c];
-    add_segments(g, i, nroots, k, cw, false, min_w, segs[t], units64[t], kmax[t]);
+    add_segments(g, i, nroots, k, cw, false, min_w, sub_of, segs[t], units64[t], kmax[t]);
     uint64_t after = 0;
     for (int c = 0; c < kClasses; ++c) after += u[c];
     rem_init[i] = (uint32_t)(after - before);

@@ -37,7 +37,8 @@ class Config(ctypes.Structure):
                 ("fingerprint", ctypes.c_int32), ("memo_entries", ctypes.c_int32),
                 ("memo_bytes", ctypes.c_int64), ("deadline_ms", ctypes.c_int64),
                 ("chunk_work", ctypes.c_int32), ("grid_pct", ctypes.c_int32),
-                ("budget_from_pair_start", ctypes.c_int32), ("min_width", ctypes.c_int32)]
+                ("budget_from_pair_start", ctypes.c_int32), ("min_width", ctypes.c_int32),
+                ("sub_units", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

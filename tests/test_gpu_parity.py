@@ -192,3 +192,48 @@ def test_nearly_complete(D, oracle_mod, n, removed, seed):
                 c, f, rc = D.count(G, k, cfg=D.config(fingerprint=0, **cfg))
                 assert c == want[0], (k, order, cfg)
                 assert _gpu(D, g, k, order, **cfg) == want
+
+
+def _planted(n, p, s, seed):
+    """G(n, p) plus one planted clique on s random vertices."""
+    rng = np.random.default_rng(seed)
+    iu, ju = np.triu_indices(n, 1)
+    keep = rng.random(len(iu)) < p
+    a, b = iu[keep], ju[keep]
+    plant = np.sort(rng.choice(n, size=s, replace=False))
+    pi, pj = np.triu_indices(s, 1)
+    a = np.concatenate([a, plant[pi]])
+    b = np.concatenate([b, plant[pj]])
+    e = np.unique(np.stack([a, b], 1), axis=0)
+    return gg.csr_from_edges(n, e[:, 0], e[:, 1], name="G(%d,%.2f)+K%d" % (n, p, s))
+
+
+@pytest.mark.parametrize("sub", [2, 3, 7, 32])
+def test_sub_units(D, oracle_mod, sub):
+    """Depth-1 children shared out among several work units (each takes every
+    sub-th surviving depth-2 child): per-root results equal the oracle's for
+    every split, with and without memoisation, chunking and fingerprints,
+    including complete and nearly complete candidate sets at the split frame."""
+    P61 = (1 << 61) - 1
+    cases = [(gg.gnp(80, 0.5, 3), (6, 7)), (_planted(150, 0.3, 40, 11), (6, 8))]
+    rng = np.random.default_rng(900 + sub)
+    iu, ju = np.triu_indices(60, 1)
+    keep = np.ones(len(iu), bool)
+    keep[rng.choice(len(iu), size=5, replace=False)] = False
+    cases.append((gg.csr_from_edges(60, iu[keep], ju[keep], name="K60-5"), (7, 9)))
+    for g, ks in cases:
+        G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+        for k in ks:
+            want = oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, np.arange(g.n, dtype=np.int32))
+            for cfg in (dict(memo=1), dict(memo=0), dict(memo=2), dict(memo=1, chunk_work=64)):
+                for fp in (1, 0):
+                    print("sub", sub, g.name, k, cfg, fp, flush=True)
+                    per = np.zeros(3 * g.n, np.uint64)
+                    c, f, rc = D.count(G, k, cfg=D.config(sub_units=sub, fingerprint=fp, **cfg), per_root=per)
+                    assert rc == D.OK
+                    got = [int(per[3 * v]) | (int(per[3 * v + 1]) << 64) for v in range(g.n)]
+                    assert got == [w for w, _ in want], (k, cfg, fp)
+                    assert c == sum(w for w, _ in want)
+                    if fp:
+                        assert [int(per[3 * v + 2]) for v in range(g.n)] == [x for _, x in want]
+                        assert f == sum(x for _, x in want) % P61

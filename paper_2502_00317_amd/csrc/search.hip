@@ -399,26 +399,47 @@ __device__ __forceinline__ void wave_sum128(u64& lo, u64& hi) {
   }
 }
 
-// pairs: the e missing edges as local-id pairs (2e entries) in LDS.
+// pairs: the e missing edges as local-id pairs (2e entries) in LDS.  Only
+// |V(S)| varies between terms, so lanes 0..16 first compute the binomials
+// C(|P| - v, l - v) for every possible v; a term is then a lookup.
 __device__ __forceinline__ bool near_complete_count(const uint16_t* pairs, int e, int np, int l, u64& lo, u64& hi) {
   const int lane = lane_id();
-  u64 plo = 0, phi = 0, nlo = 0, nhi = 0;  // positive and negative terms
+  // distinct endpoints: lane t < 2e holds the t-th endpoint; idx numbers the
+  // distinct ones in order of first appearance
+  const int a = lane < 2 * e ? (int)pairs[lane] : -1;
+  int first = lane;
+  for (int t = 2 * e - 1; t >= 0; --t) {
+    const int b = __shfl(a, t);
+    if (t < lane && b == a) first = t;
+  }
+  const u64 firsts = __ballot(lane < 2 * e && first == lane);
+  const int nv = __popcll(firsts);
+  const int idx = __shfl(__popcll(firsts & lanemask_lt()), first);
+  // endpoint masks of the missing edges, 16 bits each, four per word
+  u64 em0 = 0, em1 = 0;
+#pragma unroll
+  for (int i = 0; i < kNearMissing; ++i) {
+    const int i0 = __shfl(idx, 2 * i), i1 = __shfl(idx, 2 * i + 1);
+    const u64 m = i < e ? (u64)((1u << i0) | (1u << i1)) : 0ull;
+    if (i < 4) em0 |= m << (16 * i);
+    else em1 |= m << (16 * (i - 4));
+  }
+  // lane v <= nv: C(np - v, l - v)
+  u64 cvlo = 0, cvhi = 0;
   bool ok = true;
-  for (int S = lane; S < (1 << e); S += kWave) {
-    int ends[2 * kNearMissing];
-    int v = 0;
-    for (int i = 0; i < e; ++i) {
-      if (!((S >> i) & 1)) continue;
-      for (int t = 0; t < 2; ++t) {
-        const int a = pairs[2 * i + t];
-        bool seen = false;
-        for (int q = 0; q < v; ++q) seen = seen || ends[q] == a;
-        if (!seen) ends[v++] = a;
-      }
-    }
-    if (v <= l) {
-      u64 clo, chi;
-      ok = ok && binom128(np - v, l - v, clo, chi);
+  if (lane <= nv && lane <= l) ok = binom128(np - lane, l - lane, cvlo, cvhi);
+  if (__ballot(!ok)) return false;
+  u64 plo = 0, phi = 0, nlo = 0, nhi = 0;  // positive and negative terms
+  const int ns = 1 << e;
+  for (int base = 0; base < ns; base += kWave) {
+    const int S = base + lane;
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < kNearMissing; ++i)
+      if ((S >> i) & 1) m |= (uint32_t)(((i < 4 ? em0 : em1) >> (16 * (i & 3))) & 0xffffull);
+    const int v = __popc(m);
+    const u64 clo = __shfl(cvlo, v), chi = __shfl(cvhi, v);
+    if (S < ns) {
       if (__popc((unsigned)S) & 1) {
         const u64 t = nlo + clo;
         nhi += chi + (t < nlo ? 1ull : 0ull);
@@ -430,7 +451,6 @@ __device__ __forceinline__ bool near_complete_count(const uint16_t* pairs, int e
       }
     }
   }
-  if (__ballot(!ok)) return false;
   wave_sum128(plo, phi);
   wave_sum128(nlo, nhi);
   lo = plo - nlo;

@@ -57,9 +57,11 @@ constexpr int kOutWords = 16;
 constexpr int kMemoProbe = 1;
 // A root stops using its memo table once at least kMemoMinLook lookups
 // found fewer than one hit in kMemoMinRatio (the table is a cache: using it
-// or not never changes a result).
+// or not never changes a result).  Where the closed forms already cover the
+// dense branches, hits mostly save single leaf frames and do not repay the
+// lookups and inserts; one hit in four is about where they break even.
 constexpr int kMemoMinLook = 1024;
-constexpr int kMemoMinRatio = 16;
+constexpr int kMemoMinRatio = 4;
 
 // Batched counting: one entry per (graph, k) pair, and the units of a
 // launch as segments [unit_begin, next unit_begin) of consecutive roots of

@@ -504,8 +504,10 @@ __device__ __forceinline__ int missing_edges(const Lds& s, const u64 (&Pr)[W], i
 
 // ---- the kernel ----------------------------------------------------------------
 
+// Counting kernels of up to 6 words are held to 256 VGPRs, i.e. two waves per
+// SIMD (the register file holds 512 per lane): crossing it halves occupancy.
 template <int W, bool EMIT, bool FP>
-__global__ __launch_bounds__(64) void k_search(Params p) {
+__global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params p) {
   extern __shared__ __align__(16) char smem[];
   const int lane = lane_id();
   int k = p.k;  // batch mode: the largest k of the launch (sizes the stacks)

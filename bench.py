@@ -186,7 +186,70 @@ def summarize_profiles(d):
             lines.append("| %s | %d | %.3f | %.3f |" % (kname, n, ms, ms / max(n, 1)))
         with open(os.path.join(ROOT, "profiles", "k_search_cfg2_kernel_stats.md"), "w") as f:
             f.write("\n".join(lines) + "\n")
+    summarize_issue(d)
     print(json.dumps(out)[:400])
+
+
+def summarize_issue(d):
+    """Instruction issue rates of the search kernels from two rocprofv3 --pmc
+    runs of SQ counters (sq_1, sq_2 under d), against the issue peaks of
+    256 CUs at 2.4 GHz: 4 SIMDs per CU, each issuing one wave64 VALU
+    instruction per 4 cycles (614 G/s, the 39.3 T lane-op/s of the roofline),
+    and one LDS instruction per CU per cycle (614 G/s)."""
+    import csv
+    import glob
+    data = {}
+    for sub in ("sq_1", "sq_2"):
+        f = glob.glob(os.path.join(d, sub, "*counter_collection.csv"))
+        if not f:
+            return
+        for r in csv.DictReader(open(f[0])):
+            name = r["Kernel_Name"]
+            if "k_search<" not in name:
+                continue
+            key = (int(r["Dispatch_Id"]), name.split("k_search<")[1].split(">")[0])
+            e = data.setdefault((sub, key), {"ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    peak = 256 * 4 * 2.4e9 / 4
+    lines = ["# Instruction issue of the search kernels (rocprofv3 --pmc SQ counters), plain count",
+             "# on the Chung-Lu n=1e6 workload, k = 5 (fingerprint), 7 and 9",
+             "",
+             "Commands (repository root, one MI355X; TMPDIR=/tmp), one pass each:",
+             "",
+             "    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_SMEM SQ_INSTS_BRANCH \\",
+             "        SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR GRBM_GUI_ACTIVE --output-format csv -d $PWD/gpurun_out/sq_1 -o run -- \\",
+             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving",
+             "    rocprofv3 --pmc SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT SQ_BUSY_CYCLES SQ_WAVE_CYCLES \\",
+             "        SQ_THREAD_CYCLES_VALU SQ_WAIT_INST_LDS SQ_ACTIVE_INST_ANY GRBM_COUNT --output-format csv \\",
+             "        -d $PWD/gpurun_out/sq_2 -o run -- python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving",
+             "    python3 bench.py --summarize-profiles gpurun_out",
+             "",
+             "Peaks (256 CUs, 2.4 GHz): VALU 614 G wave64 instructions/s (4 SIMDs per CU, one wave64",
+             "instruction per SIMD per 4 cycles = 39.3 T lane-ops/s); LDS 614 G instructions/s (one per CU",
+             "per cycle).  k_search<W, EMIT, FP>: one launch per width class per k.",
+             "Kernel source hash: %s" % kernel_source_hash(),
+             "",
+             "| kernel | k | ms | VALU G/s | VALU % of peak | SALU G/s | LDS G/s | LDS % of peak | bank-conflict cycles / LDS active cycles | VMEM rd+wr M |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    keys = sorted({k for (_, k) in data}, key=lambda x: (int(x[1].split(",")[0]), x[0]))
+    nth = {}
+    for key in keys:
+        w = int(key[1].split(",")[0])
+        kk = (5, 7, 9)[nth.get(w, 0)] if nth.get(w, 0) < 3 else "?"
+        nth[w] = nth.get(w, 0) + 1
+        a = data.get(("sq_1", key))
+        b = data.get(("sq_2", key))
+        if not a or not b:
+            continue
+        sec = a["ns"] / 1e9
+        valu = a.get("SQ_INSTS_VALU", 0) / sec
+        lds = a.get("SQ_INSTS_LDS", 0) / sec
+        conf = b.get("SQ_LDS_BANK_CONFLICT", 0) / max(b.get("SQ_ACTIVE_INST_LDS", 1), 1)
+        lines.append("| k_search<%s> | %s | %.1f | %.1f | %.1f | %.1f | %.1f | %.2f | %.2f | %.1f |" % (
+            key[1], kk, a["ns"] / 1e6, valu / 1e9, 100 * valu / peak, a.get("SQ_INSTS_SALU", 0) / sec / 1e9,
+            lds / 1e9, 100 * lds / peak, conf, (a.get("SQ_INSTS_VMEM_RD", 0) + a.get("SQ_INSTS_VMEM_WR", 0)) / 1e6))
+    with open(os.path.join(ROOT, "profiles", "k_search_cfg2_issue.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def measured_traffic(kernel):

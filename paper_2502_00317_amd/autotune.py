@@ -3,12 +3,13 @@
 Picks, per size bucket of a batch, the switches of dist_count_batch_ex that
 run fastest on the device:
 
-* ``min_width``  -- smallest bitmap width (words of 64 bits: 1, 2, 4, 8)
-  given to a root; larger values merge the small width classes into fewer,
-  wider launches (fewer tails, more LDS per wave);
+* ``min_width``  -- smallest bitmap width (words of 64 bits, one of the
+  library's width classes) given to a root; larger values merge the small
+  width classes into fewer, wider launches (fewer tails, more LDS per wave);
 * ``chunk_work`` -- work-unit size for roots with more than 64
-  out-neighbours (children per unit = chunk_work / d): smaller values split
-  heavy roots across more wavefronts;
+  out-neighbours (children per unit = chunk_work / d; 0 = the library's
+  cost-based sizing): smaller values split heavy roots across more
+  wavefronts;
 * ``memo``       -- memoisation of dense branches on or off.
 
 Every candidate must return exactly the same (count, fingerprint) for every
@@ -28,6 +29,7 @@ DEFAULT_CANDIDATES = [
     dict(min_width=2, chunk_work=512, memo=1),
     dict(min_width=1, chunk_work=128, memo=1),
     dict(min_width=1, chunk_work=512, memo=0),
+    dict(min_width=1, chunk_work=0, memo=1),
 ]
 
 

@@ -115,7 +115,7 @@ struct Params {
   unsigned long long* pair_t0;  // batch: [0] first unit of the batch, [1 + i] first unit of pair i
   u64* pair_host;            // batch: host-mapped {flag, lo, hi, fp, t_first, t_last} per pair
   uint32_t units;            // work units in this bucket
-  int chunk_work;            // children per unit = max(1, chunk_work / d) for d > 64
+  int chunk_work;            // the unit-size switch the host planned with (0 = automatic)
   int32_t drows;             // LDS rows of G_u for this launch (>= every root's out-degree)
   u64* wave_out;
   u64* per_root;
@@ -209,20 +209,29 @@ __device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, c
 }
 
 // Work units per root.  A root with more than 64 out-neighbours is cut into
-// ranges of max(1, chunk_work / d) depth-1 children so that many waves share
-// it (each wave rebuilds G_u in its own LDS); lighter roots stay one unit,
-// which keeps the memo reuse between the children of a root inside one wave.
-// chunk_work 0 = automatic: deeper searches (k >= 9) make each depth-1
-// child heavier, so they get smaller units (256) for balance; else 512.
-__host__ __device__ inline int auto_chunk(int chunk_work, int k) {
-  return chunk_work > 0 ? chunk_work : (k >= 9 ? 256 : 512);
+// ranges of depth-1 children so that many waves share it; every unit
+// rebuilds G_u in its wave's LDS, so a unit should hold enough search to
+// repay that build.  With chunk_work > 0 a range holds max(1, chunk_work / d)
+// children.  Automatic (chunk_work 0): for k <= 6 the same with 512; for
+// deeper searches a depth-1 subtree costs roughly (d/64)^(k-3), and a range
+// holds children worth about kUnitCost of that, so light roots stay whole
+// (one build) while the children of heavy roots become units of their own.
+// (For shallow searches the ranges this gives are too coarse: the few heavy
+// ones then hold the launch.)  Roots of up to 64 stay one unit.
+constexpr double kUnitCost = 512.0;
+
+inline int children_per_unit(int d, int k, int chunk_work) {
+  if (k <= 3 || d <= 64) return d;
+  const double c = chunk_work > 0 ? (double)(chunk_work / d)
+                   : k <= 6       ? (double)(512 / d)
+                                  : kUnitCost / std::pow((double)d / 64.0, (double)(k - 3));
+  if (c < 1.0) return 1;
+  if (c >= (double)d) return d;
+  return (int)c;
 }
 
-__host__ __device__ inline int units_per_root(int d, int k, int chunk_work) {
-  if (k <= 3 || d <= 64) return 1;
-  int c = chunk_work / d;  // depth-1 children per unit
-  if (c < 1) c = 1;
-  if (c >= d) return 1;
+inline int units_per_root(int d, int k, int chunk_work) {
+  const int c = children_per_unit(d, k, chunk_work);
   return (d + c - 1) / c;
 }
 
@@ -355,8 +364,21 @@ __device__ __forceinline__ void div_small(u64& hi, u64& lo, u64 d) {
   lo = ((u64)limb[2] << 32) | limb[3];
 }
 
+// C(n, r) for n <= 1024 and r <= 16, filled once per device by
+// k_fill_binom (entry (0, 0) = 1 marks it filled): a closed form then costs a
+// load instead of r 128-bit multiply-divides.
+constexpr int kBinomN = 1024;
+constexpr int kBinomR = 16;
+__device__ u64 g_binom[(kBinomN + 1) * (kBinomR + 1) * 2];
+
 // C(n, r) as 128 bits; false if it may not fit (then nothing is claimed).
 __device__ __forceinline__ bool binom128(int n, int r, u64& lo, u64& hi) {
+  if (r >= 0 && r <= kBinomR && n >= 0 && n <= kBinomN && g_binom[0] == 1ull) {
+    const u64* e = g_binom + ((size_t)n * (kBinomR + 1) + (size_t)r) * 2;
+    lo = e[0];
+    hi = e[1];
+    return true;
+  }
   lo = 1;
   hi = 0;
   for (int i = 0; i < r; ++i) {
@@ -370,6 +392,28 @@ __device__ __forceinline__ bool binom128(int n, int r, u64& lo, u64& hi) {
     div_small(hi, lo, (u64)(i + 1));
   }
   return true;
+}
+
+// Row n of the table: C(n, r) for r = 0..kBinomR by C(n, r) = C(n, r-1) (n-r+1) / r
+// (exact; C(1024, 16) < 2^117).
+__global__ void k_fill_binom() {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n > kBinomN) return;
+  u64 lo = 1, hi = 0;
+  for (int r = 0; r <= kBinomR; ++r) {
+    if (r > n) {
+      lo = 0;
+      hi = 0;
+    } else if (r > 0) {
+      const u64 m = (u64)(n - r + 1);
+      const u64 plo = lo * m;
+      hi = hi * m + __umul64hi(lo, m);
+      lo = plo;
+      div_small(hi, lo, (u64)r);
+    }
+    g_binom[((size_t)n * (kBinomR + 1) + (size_t)r) * 2] = lo;
+    g_binom[((size_t)n * (kBinomR + 1) + (size_t)r) * 2 + 1] = hi;
+  }
 }
 
 // e_l of the weights of the np members of P (wave-collective): lane j holds
@@ -1199,6 +1243,27 @@ std::recursive_mutex g_ws_mu;  // serialises the calls that use g_ws
 // so entries left in a table by an earlier launch can never match.
 u64 g_tag_next = 1;
 
+// The binomial table of a device is filled once, on a stream of its own,
+// before the first search there (never inside a graph capture).
+int ensure_binom() {
+  static std::mutex mu;
+  static bool done[64] = {};
+  int dev = 0;
+  DIST_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return DIST_OK;  // the kernels then compute binomials
+  std::lock_guard<std::mutex> lock(mu);
+  if (done[dev]) return DIST_OK;
+  hipStream_t st = nullptr;
+  DIST_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  hipLaunchKernelGGL(k_fill_binom, dim3((kBinomN + 1 + 255) / 256), dim3(256), 0, st);
+  const hipError_t e1 = hipGetLastError();
+  const hipError_t e2 = hipStreamSynchronize(st);
+  (void)hipStreamDestroy(st);
+  if (e1 != hipSuccess || e2 != hipSuccess) return DIST_E_DEVICE;
+  done[dev] = true;
+  return DIST_OK;
+}
+
 int ws_ensure(size_t wave_words, size_t memo_bytes) {
   int dev = 0;
   DIST_CHECK(hipGetDevice(&dev));
@@ -1292,7 +1357,6 @@ void split_children(const dist_graph* g, int32_t nroots, int k, int cw, int forc
     for (int& x : sub_of) x = forced < kMaxSub ? forced : kMaxSub;
     return;
   }
-  const int cwk = auto_chunk(cw, k);
   double total[kClasses] = {}, heavy[kClasses] = {};
   int32_t a = 0;
   for (const auto& run : g->deg_hist) {
@@ -1303,7 +1367,7 @@ void split_children(const dist_graph* g, int32_t nroots, int k, int cw, int forc
     const int sl = wslot_of_width(width_of(d));
     const double child = std::pow((double)d / 64.0, (double)(k - 3));
     total[sl] += (double)cnt * (double)d * child;
-    if (d > 64 && cwk / d <= 1 && child > heavy[sl]) heavy[sl] = child;
+    if (children_per_unit(d, k, cw) == 1 && child > heavy[sl]) heavy[sl] = child;
   }
   const double waves = 8.0 * (g_ws.cus > 0 ? g_ws.cus : 256);
   for (int sl = 0; sl < kClasses; ++sl) {
@@ -1343,7 +1407,7 @@ void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, 
     if (W < min_w) W = width_of(64 * min_w);  // the narrowest class of at least min_w words
     const int sl = wslot_of_width(W);
     const int sub = (whole_roots || k < 6) ? 1 : sub_of[sl];
-    const int upr = whole_roots ? 1 : units_per_root(d, k, auto_chunk(cw, k)) * sub;
+    const int upr = whole_roots ? 1 : units_per_root(d, k, cw) * sub;
     if (sl != cur_sl || upr != cur_upr || sub != cur_sub) {
       flush(a);
       cur_sl = sl;
@@ -1414,6 +1478,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   for (int i = 0; i < kOutWords; ++i) totals[i] = 0;
   if (nroots <= 0) return DIST_OK;
   if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
+  if (int rb = ensure_binom()) return rb;
   const int cw = base.chunk_work;  // 0: automatic per k
   std::vector<BatchSeg> segs[kClasses];
   uint64_t units64[kClasses] = {};
@@ -2308,6 +2373,7 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
   if (on_done) use_graph = 0;
   for (int i = 0; i < n; ++i)
     if (!gs[i] || ks[i] < 1 || ks[i] > DIST_K_MAX) return gs[i] ? DIST_E_K : DIST_E_INVALID;
+  if (int rb = ensure_binom()) return rb;
   int dev = 0;
   DIST_CHECK(hipGetDevice(&dev));
   if (use_graph && s == nullptr) {

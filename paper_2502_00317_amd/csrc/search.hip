@@ -546,6 +546,55 @@ __device__ __forceinline__ int missing_edges(const Lds& s, const u64 (&Pr)[W], i
   return base;
 }
 
+// The 3-cliques of G[P] (a leaf frame, l = 3) and their fingerprint sum, with
+// the members of P in s.mem: the edges of G[P] are counted first, so that a
+// complete or nearly complete P takes its closed form; otherwise each member x
+// counts the edges among its forward neighbours P & A[x].  Wave-collective.
+template <int W, bool FP>
+__device__ __forceinline__ void leaf3_count(const Lds& s, const u64 (&Pr)[W], int np, u64& lo, u64& hi, u64& fp,
+                                            u64& wops, u64& bits) {
+  const int lane = lane_id();
+  u64 m = 0;
+  for (int i = lane; i < np; i += kWave) {
+    const int x = s.mem[i];
+    int c = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) c += __popcll(Pr[w] & s.A[x * W + w]);
+    m += (u64)c;
+  }
+  wops += (u64)((np + kWave - 1 - lane) / kWave) * W;
+  m = wave_sum(m);
+  const u64 full = (u64)np * (u64)(np - 1) / 2;
+  u64 clo, chi;
+  if (m == full && binom128(np, 3, clo, chi)) {
+    lo = clo;
+    hi = chi;
+    fp = FP ? esym_members(s.mem, np, s.gl, 3) : 0;
+    return;
+  }
+  u64 c_acc = 0, f_acc = 0;
+  for (int i = lane; i < np; i += kWave) {
+    const int x = s.mem[i];
+    u64 q[W];
+    int c = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      q[w] = Pr[w] & s.A[x * W + w];
+      c += __popcll(q[w]);
+    }
+    wops += W;
+    if (c >= 2 && s.rcap[x] >= 3) {
+      u64 ec = 0, ef = 0;
+      edges_in<W>(q, s.A, s.gl, FP, ec, ef, wops, bits);
+      c_acc += ec;
+      if (FP && ec) f_acc = addp(f_acc, mulp(s.gl[x], ef));
+    }
+  }
+  lo = wave_sum(c_acc);
+  hi = 0;
+  fp = FP ? wave_sum_p(f_acc) : 0;
+}
+
 // ---- the kernel ----------------------------------------------------------------
 
 // Counting kernels of up to 6 words are held to 256 VGPRs, i.e. two waves per
@@ -1016,7 +1065,7 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
             Q[lane] &= m_lo & m_hi;
           }
         }
-        if (memo_j && memo_live && np >= 2 && j > 0 && j != jsplit) {
+        if (memo_j && memo_live && np >= 2 && j > 0 && j != jsplit && (EMIT || l > 4)) {
           // resume from the longest memoised proper prefix P & [m_i, inf),
           // m_i the i-th smallest member, i = 1..kMemoProbe, all probed at once
           const int ncut = np - 1 < kMemoProbe ? np - 1 : kMemoProbe;
@@ -1059,6 +1108,57 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
               ++pos;
             }
             Q[lane] = keep;
+          }
+        }
+        if constexpr (!EMIT) {
+          if (l == 4) {
+            // the children are leaf frames (l = 3): counted here, one after
+            // another, without a frame of their own (no memo entries for them)
+            __syncthreads();
+            while (true) {
+              int x = -1;
+              for (int w = W - 1; w >= 0; --w) {
+                const u64 qw = Q[w];
+                if (qw) {
+                  x = w * 64 + 63 - __clzll((long long)qw);
+                  break;
+                }
+              }
+              if (x < 0) break;
+              __syncthreads();
+              if (lane == 0) Q[x >> 6] &= ~(1ull << (x & 63));
+              u64 Pc[W];
+              int np2 = 0;
+#pragma unroll
+              for (int w = 0; w < W; ++w) {
+                Pc[w] = s.stP[j * W + w] & s.A[x * W + w];
+                const u64 bw = Pc[w];
+                if ((bw >> lane) & 1ull) s.mem[np2 + __popcll(bw & lanemask_lt())] = (uint16_t)(w * 64 + lane);
+                np2 += __popcll(bw);
+              }
+              wops += W;
+              ++n_frames;
+              __syncthreads();
+              if (np2 >= 3) {
+                u64 clo = 0, chi = 0, cfp = 0;
+                leaf3_count<W, FP>(s, Pc, np2, clo, chi, cfp, wops, bits);
+                const u64 nlo = acc_lo + clo;
+                acc_hi += chi + (nlo < acc_lo ? 1ull : 0ull);
+                acc_lo = nlo;
+                if (FP) acc_fp = addp(acc_fp, mulp(s.gl[x], cfp));
+              }
+              __syncthreads();
+            }
+            res_lo = acc_lo;
+            res_hi = acc_hi;
+            res_fp = acc_fp;
+            if (memo_j && memo_live && j > 0 && j != jsplit) {
+              memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+              ++n_ins;
+            }
+            __syncthreads();
+            mode = FINISH;
+            continue;
           }
         }
         if (lane == 0) {

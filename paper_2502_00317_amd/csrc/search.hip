@@ -1065,7 +1065,7 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
             Q[lane] &= m_lo & m_hi;
           }
         }
-        if (memo_j && memo_live && np >= 2 && j > 0 && j != jsplit && (EMIT || l > 4)) {
+        if (memo_j && memo_live && np >= 2 && j > 0 && j != jsplit) {
           // resume from the longest memoised proper prefix P & [m_i, inf),
           // m_i the i-th smallest member, i = 1..kMemoProbe, all probed at once
           const int ncut = np - 1 < kMemoProbe ? np - 1 : kMemoProbe;
@@ -1112,8 +1112,12 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
         }
         if constexpr (!EMIT) {
           if (l == 4) {
-            // the children are leaf frames (l = 3): counted here, one after
-            // another, without a frame of their own (no memo entries for them)
+            // the children are leaf frames (l = 3): counted here, highest
+            // first, without a frame push each.  The memo is used exactly as
+            // by child frames: a child's set is looked up and stored under
+            // l = 3, and after each child the prefix P & [x, inf) under l = 4.
+            const bool memo_c = p.memo == 2 || (p.memo == 1 && memo_j);
+            const u64 ctag = (root_tag << 8) | 3ull;
             __syncthreads();
             while (true) {
               int x = -1;
@@ -1125,30 +1129,67 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
                 }
               }
               if (x < 0) break;
+              ++n_frames;
+              if ((deadline || pair_deadline) && (n_frames & 15) == 0) {
+                const u64 now = wall_clock64();
+                if (deadline && now > deadline) {
+                  if (lane == 0) atomicOr(p.abort_flag, 1);
+                  stop = true;
+                  break;
+                }
+                if (pair_deadline && now > pair_deadline && p.pair_abort) {
+                  if (lane == 0) atomicOr(p.pair_abort + pair, 1);
+                  unit_cancel = true;
+                  break;
+                }
+              }
               __syncthreads();
               if (lane == 0) Q[x >> 6] &= ~(1ull << (x & 63));
-              u64 Pc[W];
-              int np2 = 0;
-#pragma unroll
-              for (int w = 0; w < W; ++w) {
-                Pc[w] = s.stP[j * W + w] & s.A[x * W + w];
-                const u64 bw = Pc[w];
-                if ((bw >> lane) & 1ull) s.mem[np2 + __popcll(bw & lanemask_lt())] = (uint16_t)(w * 64 + lane);
-                np2 += __popcll(bw);
-              }
-              wops += W;
-              ++n_frames;
+              u64* Pn = s.stP + (j + 1) * W;
+              if (lane < W) Pn[lane] = s.stP[j * W + lane] & s.A[x * W + lane];
               __syncthreads();
-              if (np2 >= 3) {
-                u64 clo = 0, chi = 0, cfp = 0;
-                leaf3_count<W, FP>(s, Pc, np2, clo, chi, cfp, wops, bits);
-                const u64 nlo = acc_lo + clo;
-                acc_hi += chi + (nlo < acc_lo ? 1ull : 0ull);
-                acc_lo = nlo;
-                if (FP) acc_fp = addp(acc_fp, mulp(s.gl[x], cfp));
+              u64 clo = 0, chi = 0, cfp = 0;
+              bool got = false;
+              if (memo_c && memo_live) {
+                ++n_look;
+                ++r_look;
+                if (memo_find<W>(p, table, ctag, Pn, nullptr, 1, clo, chi, cfp) >= 0) {
+                  ++n_hit;
+                  ++r_hit;
+                  got = true;
+                }
+                if (r_look >= kMemoMinLook && r_hit * kMemoMinRatio < r_look) memo_live = false;
+              }
+              if (!got) {
+                u64 Pc[W];
+                int np2 = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                  Pc[w] = Pn[w];
+                  const u64 bw = Pc[w];
+                  if ((bw >> lane) & 1ull) s.mem[np2 + __popcll(bw & lanemask_lt())] = (uint16_t)(w * 64 + lane);
+                  np2 += __popcll(bw);
+                }
+                wops += W;
+                __syncthreads();
+                if (np2 >= 3) leaf3_count<W, FP>(s, Pc, np2, clo, chi, cfp, wops, bits);
+                if (memo_c && memo_live) {
+                  memo_put<W>(p, table, ctag, Pn, -1, clo, chi, cfp);
+                  ++n_ins;
+                }
+              }
+              const u64 nlo = acc_lo + clo;
+              acc_hi += chi + (nlo < acc_lo ? 1ull : 0ull);
+              acc_lo = nlo;
+              if (FP) acc_fp = addp(acc_fp, mulp(s.gl[x], cfp));
+              if (memo_j && memo_live && j > 0 && j != jsplit) {
+                // trie node P & [x, inf) is now complete for l = 4
+                memo_put<W>(p, table, tag, s.stP + j * W, x, acc_lo, acc_hi, acc_fp);
+                ++n_ins;
               }
               __syncthreads();
             }
+            if (stop || unit_cancel) break;
             res_lo = acc_lo;
             res_hi = acc_hi;
             res_fp = acc_fp;

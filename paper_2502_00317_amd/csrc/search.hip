@@ -1170,7 +1170,6 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
                   if ((bw >> lane) & 1ull) s.mem[np2 + __popcll(bw & lanemask_lt())] = (uint16_t)(w * 64 + lane);
                   np2 += __popcll(bw);
                 }
-                wops += W;
                 __syncthreads();
                 if (np2 >= 3) leaf3_count<W, FP>(s, Pc, np2, clo, chi, cfp, wops, bits);
                 if (memo_c && memo_live) {

@@ -445,10 +445,12 @@ __device__ __forceinline__ void wave_sum128(u64& lo, u64& hi) {
   }
 }
 
+// Not inlined: its three callers (the leaf counter, leaf frames, and frames
+// with l >= 4) would otherwise push the search kernel past 256 VGPRs.
 // pairs: the e missing edges as local-id pairs (2e entries) in LDS.  Only
 // |V(S)| varies between terms, so lanes 0..16 first compute the binomials
 // C(|P| - v, l - v) for every possible v; a term is then a lookup.
-__device__ __forceinline__ bool near_complete_count(const uint16_t* pairs, int e, int np, int l, u64& lo, u64& hi) {
+__device__ __noinline__ bool near_complete_count(const uint16_t* pairs, int e, int np, int l, u64& lo, u64& hi) {
   const int lane = lane_id();
   // distinct endpoints: lane t < 2e holds the t-th endpoint; idx numbers the
   // distinct ones in order of first appearance
@@ -566,6 +568,17 @@ __device__ __forceinline__ void leaf3_count(const Lds& s, const u64 (&Pr)[W], in
   m = wave_sum(m);
   const u64 full = (u64)np * (u64)(np - 1) / 2;
   u64 clo, chi;
+  if constexpr (!FP) {
+    if (m < full && full - m <= (u64)kNearMissing) {
+      const int e = missing_edges<W>(s, Pr, np, s.pos);
+      if (e == (int)(full - m) && near_complete_count(s.pos, e, np, 3, clo, chi)) {
+        lo = clo;
+        hi = chi;
+        fp = 0;
+        return;
+      }
+    }
+  }
   if (m == full && binom128(np, 3, clo, chi)) {
     lo = clo;
     hi = chi;

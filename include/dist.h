@@ -93,7 +93,7 @@ typedef struct {
                             out-neighbours: such a root is split into ranges of
                             max(1, chunk_work / d) depth-1 children that
                             different wavefronts take; 0 = auto (k <= 6: as
-                            512; deeper: ranges worth about
+                            1024; deeper: ranges worth about
                             512 / (d/64)^(k-3) children, so light roots stay
                             whole and heavy ones split per child) */
   int32_t grid_pct;      /* batches: percent of the full persistent grid a

@@ -212,7 +212,7 @@ __device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, c
 // ranges of depth-1 children so that many waves share it; every unit
 // rebuilds G_u in its wave's LDS, so a unit should hold enough search to
 // repay that build.  With chunk_work > 0 a range holds max(1, chunk_work / d)
-// children.  Automatic (chunk_work 0): for k <= 6 the same with 512; for
+// children.  Automatic (chunk_work 0): for k <= 6 the same with 1024; for
 // deeper searches a depth-1 subtree costs roughly (d/64)^(k-3), and a range
 // holds children worth about kUnitCost of that, so light roots stay whole
 // (one build) while the children of heavy roots become units of their own.
@@ -223,7 +223,7 @@ constexpr double kUnitCost = 512.0;
 inline int children_per_unit(int d, int k, int chunk_work) {
   if (k <= 3 || d <= 64) return d;
   const double c = chunk_work > 0 ? (double)(chunk_work / d)
-                   : k <= 6       ? (double)(512 / d)
+                   : k <= 6       ? (double)(1024 / d)
                                   : kUnitCost / std::pow((double)d / 64.0, (double)(k - 3));
   if (c < 1.0) return 1;
   if (c >= (double)d) return d;

@@ -237,3 +237,38 @@ def test_sub_units(D, oracle_mod, sub):
                     if fp:
                         assert [int(per[3 * v + 2]) for v in range(g.n)] == [x for _, x in want]
                         assert f == sum(x for _, x in want) % P61
+
+
+@pytest.mark.parametrize("n,ks", [(20, (16, 17, 18, 19)), (64, (17, 18, 30)), (200, (17, 20))])
+def test_large_k_closed_forms(D, n, ks):
+    """Complete graphs at k > 16: closed forms whose binomials C(|P|, l) lie
+    beyond the precomputed table (l > 16) and are computed exactly in 128
+    bits, next to ones inside it, against C(n, k) and e_k."""
+    import refdefs as R
+    g = gg.complete(n)
+    for k in ks:
+        want = R.complete_graph_result(n, k)
+        for cfg in (dict(memo=1, prune=1), dict(memo=0, prune=0)):
+            print("K", n, k, cfg, flush=True)
+            assert _gpu(D, g, k, D.ORDER_DEGREE, **cfg) == want
+
+
+@pytest.mark.parametrize("removed,seed", [(2, 0), (5, 1)])
+def test_large_k_nearly_complete(D, oracle_mod, removed, seed):
+    """K_22 minus a few edges at k = 12..20: inclusion-exclusion terms with
+    binomials inside and beyond the table, against the enumerating oracle."""
+    n = 22
+    rng = np.random.default_rng(800 + seed)
+    iu, ju = np.triu_indices(n, 1)
+    keep = np.ones(len(iu), bool)
+    keep[rng.choice(len(iu), size=removed, replace=False)] = False
+    g = gg.csr_from_edges(n, iu[keep], ju[keep], name="K22-%d" % removed)
+    for k in (12, 17, 18, 20):
+        want = oracle_mod.count(g.row_ptr, g.col, k)
+        for fp in (0, 1):
+            print("K22-", removed, k, fp, flush=True)
+            G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+            c, f, rc = D.count(G, k, cfg=D.config(fingerprint=fp))
+            assert c == want[0], (k, fp)
+            if fp:
+                assert f == want[1], k

@@ -5,8 +5,8 @@ Workload: Chung-Lu graph, n = 1,000,000, power-law exponent 2.2, mean
 degree 20, degrees capped at 5,000, plus 200 planted 30-cliques (seed 2;
 synthetic stand-in for the paper's real networks).  One step = the whole
 hot path on the resident CSR: dist_orient (degree order) followed by
-dist_count for every k of --ks (default 5, 7 and 9; the fingerprint is
-computed at k = 5, the other ks are exact counts).
+dist_count for every k of --ks (default 5, 7 and 9), each with its count and
+fingerprint.
 
 Prints one JSON line with the metric, the roofline of the dominant search
 kernel (integer ALU bound) and the CPU oracle timed on a bounded sample of
@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--ks", default="5,7,9")
-    ap.add_argument("--fp-ks", default="5", help="ks whose fingerprint is computed (the rest: exact count only)")
+    ap.add_argument("--fp-ks", default="all",
+                    help="ks whose fingerprint is computed ('all' = every k of --ks; the rest: exact count only)")
     ap.add_argument("--k-dnf", type=int, default=0, help="a further k attempted once under a deadline")
     ap.add_argument("--dnf-deadline-ms", type=int, default=20000)
     ap.add_argument("--order", default="degree", choices=["degree", "degeneracy"])
@@ -315,7 +316,7 @@ def main():
     torch.cuda.init()
     dist.lib()
     ks = [int(x) for x in a.ks.split(",") if x]
-    fp_ks = {int(x) for x in a.fp_ks.split(",") if x}
+    fp_ks = set(ks) if a.fp_ks == "all" else {int(x) for x in a.fp_ks.split(",") if x}
     order = dist.ORDER_DEGREE if a.order == "degree" else dist.ORDER_DEGENERACY
 
     t0 = time.time()

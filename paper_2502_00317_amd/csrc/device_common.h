@@ -23,6 +23,10 @@ __device__ __forceinline__ u64 addp(u64 a, u64 b) {
   return s >= DIST_P61 ? s - DIST_P61 : s;
 }
 
+__device__ __forceinline__ u64 subp(u64 a, u64 b) {
+  return a >= b ? a - b : a + (DIST_P61 - b);
+}
+
 __device__ __forceinline__ u64 mulp(u64 a, u64 b) {
   u64 lo = a * b;
   u64 hi = __umul64hi(a, b);
@@ -41,6 +45,14 @@ __device__ __forceinline__ u64 wave_sum_p(u64 x) {
   return x;
 }
 
+// Lane l's value of v (l uniform); valid in divergent code, since it reads
+// the register directly.
+__device__ __forceinline__ u64 readlane64(u64 v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((u64)hi << 32) | lo;
+}
+
 __device__ __forceinline__ u64 ld_coherent(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -52,6 +64,7 @@ __device__ __forceinline__ u64 ld_coherent(const u64* p) {
 struct Lds {
   u64* A;        // D * W
   u64* gl;       // D (null without fingerprints)
+  u64* wtab;     // W * 256 nibble table of weight sums (fingerprints, W <= kTabMaxW; else null)
   u64* stP;      // (k-1) * W
   u64* stQ;      // (k-1) * W
   u64* stCnt;    // (k-1) * 2
@@ -69,6 +82,13 @@ struct Lds {
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
 
+// Fingerprint weight sums over bitmaps use a table of 16 entries per nibble
+// (2 KB per bitmap word) for widths up to this; wider launches, whose rows
+// already take most of the LDS, sum bit by bit.
+constexpr int kTabMaxW = 6;
+
+__host__ __device__ inline size_t wtab_words(int W, int fp) { return (fp && W <= kTabMaxW) ? (size_t)W * 256 : 0; }
+
 // Rows of a launch: its largest root out-degree rounded up to 16, within
 // the width class.
 __host__ __device__ inline int lds_rows(int W, int dmax) {
@@ -82,7 +102,7 @@ __host__ __device__ inline int lds_rows(int W, int dmax) {
 // fp = 0 leaves out the fingerprint weights (8 D bytes).
 __host__ __device__ inline size_t lds_bytes(int W, int k, int fp, int Drows) {
   size_t D = (size_t)Drows, L = (size_t)(k > 1 ? k - 1 : 1);
-  size_t b = 8 * (D * W + (fp ? D : 0) + 2 * L * W + 3 * L + W);
+  size_t b = 8 * (D * W + (fp ? D : 0) + wtab_words(W, fp) + 2 * L * W + 3 * L + W);
   size_t build = 4 * (3 * D + 1), post = 5 * D;
   b += align8(build > post ? build : post);
   b += align8(3 * L);
@@ -99,6 +119,11 @@ __device__ inline Lds carve(char* base, int k, int fp, int Drows) {
   if (fp) {
     s.gl = p;
     p += D;
+  }
+  s.wtab = nullptr;
+  if (wtab_words(W, fp)) {
+    s.wtab = p;
+    p += wtab_words(W, fp);
   }
   s.stP = p; p += L * W;
   s.stQ = p; p += L * W;
@@ -139,9 +164,59 @@ __device__ __forceinline__ u64 weight_sum(const u64 (&q)[W], const u64* gl, u64&
   return s >= DIST_P61 ? s - DIST_P61 : s;
 }
 
+// The nibble table of a root's weights: tab[16 (16 w + n) + v] = sum of
+// g(64 w + 4 n + b) over the set bits b of v (mod p), for vertices below d.
+template <int W>
+__device__ void build_weight_table(const Lds& s, int d) {
+  for (int e = lane_id(); e < W * 256; e += kWave) {
+    const int base = (e >> 4) * 4, v = e & 15;
+    u64 a = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (((v >> b) & 1) && base + b < d) a += s.gl[base + b];
+    a = (a & DIST_P61) + (a >> 61);
+    s.wtab[e] = a >= DIST_P61 ? a - DIST_P61 : a;
+  }
+  __syncthreads();
+}
+
+// The same sum as weight_sum, sixteen table loads per nonzero word.  Each
+// entry is below p < 2^61 and a folded sum below p + 16, so folding after six,
+// six and four entries keeps every partial sum below 2^64.
+template <int W>
+__device__ __forceinline__ u64 weight_sum_tab(const u64 (&q)[W], const u64* tab, u64& bits_visited) {
+  u64 s = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const u64 x = q[w];
+    if (x) {
+      bits_visited += (u64)__popcll(x);
+      const u64* t = tab + w * 256;
+      u64 a = 0;
+#pragma unroll
+      for (int n = 0; n < 16; ++n) {
+        a += t[n * 16 + (int)((x >> (4 * n)) & 15ull)];
+        if (n == 5 || n == 11) a = (a & DIST_P61) + (a >> 61);
+      }
+      s += (a & DIST_P61) + (a >> 61);
+      s = (s & DIST_P61) + (s >> 61);
+    }
+  }
+  return s >= DIST_P61 ? s - DIST_P61 : s;
+}
+
+// Σ_{z in q} g(z) mod p: by table where the launch has one.
+template <int W>
+__device__ __forceinline__ u64 weight_sum_any(const u64 (&q)[W], const u64* gl, const u64* tab, u64& bits) {
+  if constexpr (W <= kTabMaxW) {
+    if (tab) return weight_sum_tab<W>(q, tab, bits);
+  }
+  return weight_sum<W>(q, gl, bits);
+}
+
 // Edges of G[Y] and their fingerprint sum Σ g(y) g(z) over edges y<z.
 template <int W>
-__device__ __forceinline__ void edges_in(const u64 (&Y)[W], const u64* A, const u64* gl, int fpon,
+__device__ __forceinline__ void edges_in(const u64 (&Y)[W], const u64* A, const u64* gl, const u64* tab, int fpon,
                                          u64& cnt, u64& fp, u64& wops, u64& bits) {
 #pragma unroll
   for (int w = 0; w < W; ++w) {
@@ -159,7 +234,7 @@ __device__ __forceinline__ void edges_in(const u64 (&Y)[W], const u64* A, const 
       }
       wops += W;
       cnt += (u64)c;
-      if (fpon && c) fp = addp(fp, mulp(gl[y], weight_sum<W>(q, gl, bits)));
+      if (fpon && c) fp = addp(fp, mulp(gl[y], weight_sum_any<W>(q, gl, tab, bits)));
     }
   }
 }

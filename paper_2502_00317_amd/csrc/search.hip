@@ -416,9 +416,10 @@ __global__ void k_fill_binom() {
   }
 }
 
-// e_l of the weights of the np members of P (wave-collective): lane j holds
-// e_j while the members are added one at a time.
-__device__ __forceinline__ u64 esym_members(const uint16_t* mem, int np, const u64* gl, int l) {
+// e_j of the weights of the np members of P for j = 0..l (wave-collective):
+// lane j holds e_j while the members are added one at a time.  Used where l
+// exceeds kEsymMaxL.
+__device__ __forceinline__ u64 esym_serial(const uint16_t* mem, int np, const u64* gl, int l) {
   const int lane = lane_id();
   u64 e = lane == 0 ? 1ull : 0ull;
   for (int i = 0; i < np; ++i) {
@@ -426,15 +427,100 @@ __device__ __forceinline__ u64 esym_members(const uint16_t* mem, int np, const u
     const u64 prev = __shfl_up(e, 1);
     if (lane >= 1 && lane <= l) e = addp(e, mulp(prev, g));
   }
-  return __shfl(e, l);
+  return e;
 }
 
-// Nearly complete candidate sets (counts only): if G[P] misses e <= 8 edges,
-// its l-cliques are the l-subsets of P containing none of them; by
-// inclusion-exclusion over the subsets S of the missing edges,
+// The same by Newton's identities: with the power sums p_m = sum_x g(x)^m,
+//   j e_j = sum_{i=1..j} (-1)^(i-1) e_{j-i} p_i,
+// and j is invertible mod the prime p.  Every lane adds the powers of its own
+// members, the wave sums each p_m, and the e_j follow in l^2 / 2 products, so
+// no step waits on the previous member.
+constexpr int kEsymMaxL = 16;
+
+constexpr u64 mulp_host(u64 a, u64 b) { return (u64)((unsigned __int128)a * b % DIST_P61); }
+constexpr u64 powp_host(u64 b, u64 e) {
+  u64 r = 1;
+  while (e) {
+    if (e & 1) r = mulp_host(r, b);
+    b = mulp_host(b, b);
+    e >>= 1;
+  }
+  return r;
+}
+// inverses of 1..kEsymMaxL mod p (Fermat: j^(p-2)), evaluated by the compiler
+struct InvSmall {
+  u64 v[kEsymMaxL + 1];
+};
+constexpr InvSmall make_inv_small() {
+  InvSmall t{};
+  for (int j = 1; j <= kEsymMaxL; ++j) t.v[j] = powp_host((u64)j, DIST_P61 - 2);
+  return t;
+}
+constexpr InvSmall kInvSmall = make_inv_small();
+
+// Not inlined: it would otherwise add to the search kernel's registers.
+// Lane j returns e_j (j <= l), the rest 0.  A lane holds at most W members
+// (np <= 64 W); lane m keeps p_m, lane j keeps e_j, and the products of the
+// identities take their factors from other lanes by readlane.
+template <int W>
+__device__ __noinline__ u64 esym_lanes(const uint16_t* mem, int np, const u64* gl, int l) {
+  if (l > kEsymMaxL) return esym_serial(mem, np, gl, l);
+  const int lane = lane_id();
+  u64 g[W], pw[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    const int i = lane + t * kWave;
+    g[t] = i < np ? gl[mem[i]] : 0ull;
+    pw[t] = g[t];
+  }
+  u64 pl = 0;  // lane m: p_m
+#pragma unroll
+  for (int m = 1; m <= kEsymMaxL; ++m) {
+    if (m <= l) {
+      u64 acc = 0;
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        acc = addp(acc, pw[t]);
+        if (m < l) pw[t] = mulp(pw[t], g[t]);
+      }
+      acc = wave_sum_p(acc);
+      if (lane == m) pl = acc;
+    }
+  }
+  u64 el = lane == 0 ? 1ull : 0ull;  // lane j: e_j
+#pragma unroll
+  for (int j = 1; j <= kEsymMaxL; ++j) {
+    if (j <= l) {
+      u64 pos = 0, neg = 0;
+#pragma unroll
+      for (int i = 1; i <= j; ++i) {
+        const u64 t = mulp(readlane64(el, j - i), readlane64(pl, i));
+        if (i & 1) pos = addp(pos, t);
+        else neg = addp(neg, t);
+      }
+      const u64 ej = mulp(subp(pos, neg), kInvSmall.v[j]);
+      if (lane == j) el = ej;
+    }
+  }
+  return el;
+}
+
+// e_l of the weights of the np members of P (wave-collective).
+template <int W>
+__device__ __forceinline__ u64 esym_members(const uint16_t* mem, int np, const u64* gl, int l) {
+  return __shfl(esym_lanes<W>(mem, np, gl, l), l);
+}
+
+// Nearly complete candidate sets: if G[P] misses e <= 8 edges, its l-cliques
+// are the l-subsets of P containing none of them; by inclusion-exclusion over
+// the subsets S of the missing edges, with V(S) the endpoints of S,
 //   count = sum_S (-1)^|S| C(|P| - |V(S)|, l - |V(S)|),
-// V(S) the endpoints of S.  Lanes take the 2^e subsets in turn.  Exact.
+//   fp    = sum_S (-1)^|S| prod_{v in V(S)} g(v) e_{l-|V(S)|}(g(P \ V(S))),
+// since the l-subsets containing V(S) are V(S) plus an (l - |V(S)|)-subset of
+// the rest.  Lanes take the 2^e subsets in turn.  Exact.
 constexpr int kNearMissing = 8;
+// The fingerprint form keeps l + 1 coefficients per lane: l <= kNearFpL.
+constexpr int kNearFpL = 15;
 
 __device__ __forceinline__ void wave_sum128(u64& lo, u64& hi) {
   for (int off = 32; off > 0; off >>= 1) {
@@ -448,10 +534,16 @@ __device__ __forceinline__ void wave_sum128(u64& lo, u64& hi) {
 // Not inlined: its three callers (the leaf counter, leaf frames, and frames
 // with l >= 4) would otherwise push the search kernel past 256 VGPRs.
 // pairs: the e missing edges as local-id pairs (2e entries) in LDS.  Only
-// |V(S)| varies between terms, so lanes 0..16 first compute the binomials
-// C(|P| - v, l - v) for every possible v; a term is then a lookup.
-__device__ __noinline__ bool near_complete_count(const uint16_t* pairs, int e, int np, int l, u64& lo, u64& hi) {
+// |V(S)| varies between count terms, so lanes 0..16 first compute the
+// binomials C(|P| - v, l - v) for every possible v; a term is then a lookup.
+// With FP, e_{l - v}(P \ V(S)) comes from the coefficients of
+// prod_{x in P} (1 + g(x) t) (mem, gl: the members and their weights) divided
+// by (1 + g(v) t) for each v in V(S): q_0 = 1, q_j = f_j - g(v) q_{j-1}.
+template <int W, bool FP>
+__device__ __noinline__ bool near_complete(const uint16_t* pairs, int e, int np, int l, const uint16_t* mem,
+                                           const u64* gl, u64& lo, u64& hi, u64& fp) {
   const int lane = lane_id();
+  if (FP && l > kNearFpL) return false;
   // distinct endpoints: lane t < 2e holds the t-th endpoint; idx numbers the
   // distinct ones in order of first appearance
   const int a = lane < 2 * e ? (int)pairs[lane] : -1;
@@ -477,7 +569,23 @@ __device__ __noinline__ bool near_complete_count(const uint16_t* pairs, int e, i
   bool ok = true;
   if (lane <= nv && lane <= l) ok = binom128(np - lane, l - lane, cvlo, cvhi);
   if (__ballot(!ok)) return false;
-  u64 plo = 0, phi = 0, nlo = 0, nhi = 0;  // positive and negative terms
+  // fingerprint: lane j holds the coefficient f_j = e_j(g(P)) and lane i the
+  // weight of the i-th distinct endpoint; read back with readlane (uniform
+  // lane numbers), so only the quotient stays in registers per lane
+  u64 ep = 0, gyl = 0;
+  if constexpr (FP) {
+    ep = esym_lanes<W>(mem, np, gl, l);
+    const u64 wt = lane < 2 * e ? gl[a] : 0ull;
+    u64 fb = firsts;
+    for (int i = 0; i < nv; ++i) {
+      const int t = __ffsll((unsigned long long)fb) - 1;
+      fb &= fb - 1;
+      const u64 gi = __shfl(wt, t);
+      if (lane == i) gyl = gi;
+    }
+  }
+  u64 plo = 0, phi = 0, nlo = 0, nhi = 0;  // positive and negative count terms
+  u64 fpos = 0, fneg = 0;                  // and fingerprint terms
   const int ns = 1 << e;
   for (int base = 0; base < ns; base += kWave) {
     const int S = base + lane;
@@ -488,7 +596,8 @@ __device__ __noinline__ bool near_complete_count(const uint16_t* pairs, int e, i
     const int v = __popc(m);
     const u64 clo = __shfl(cvlo, v), chi = __shfl(cvhi, v);
     if (S < ns) {
-      if (__popc((unsigned)S) & 1) {
+      const bool neg = __popc((unsigned)S) & 1;
+      if (neg) {
         const u64 t = nlo + clo;
         nhi += chi + (t < nlo ? 1ull : 0ull);
         nlo = t;
@@ -497,12 +606,38 @@ __device__ __noinline__ bool near_complete_count(const uint16_t* pairs, int e, i
         phi += chi + (t < plo ? 1ull : 0ull);
         plo = t;
       }
+      if constexpr (FP) {
+        if (v <= l) {
+          u64 q[kNearFpL + 1];
+#pragma unroll
+          for (int j = 0; j <= kNearFpL; ++j) q[j] = j <= l ? readlane64(ep, j) : 0ull;
+          u64 gprod = 1;
+#pragma unroll
+          for (int i = 0; i < 2 * kNearMissing; ++i) {
+            if (i < nv && ((m >> i) & 1u)) {
+              const u64 gi = readlane64(gyl, i);
+              gprod = mulp(gprod, gi);
+#pragma unroll
+              for (int j = 1; j <= kNearFpL; ++j)
+                if (j <= l) q[j] = subp(q[j], mulp(gi, q[j - 1]));
+            }
+          }
+          u64 c = 0;
+#pragma unroll
+          for (int j = 0; j <= kNearFpL; ++j)
+            if (j == l - v) c = q[j];
+          const u64 term = mulp(gprod, c);
+          if (neg) fneg = addp(fneg, term);
+          else fpos = addp(fpos, term);
+        }
+      }
     }
   }
   wave_sum128(plo, phi);
   wave_sum128(nlo, nhi);
   lo = plo - nlo;
   hi = phi - nhi - (plo < nlo ? 1ull : 0ull);
+  fp = FP ? subp(wave_sum_p(fpos), wave_sum_p(fneg)) : 0ull;
   return true;
 }
 
@@ -567,22 +702,20 @@ __device__ __forceinline__ void leaf3_count(const Lds& s, const u64 (&Pr)[W], in
   wops += (u64)((np + kWave - 1 - lane) / kWave) * W;
   m = wave_sum(m);
   const u64 full = (u64)np * (u64)(np - 1) / 2;
-  u64 clo, chi;
-  if constexpr (!FP) {
-    if (m < full && full - m <= (u64)kNearMissing) {
-      const int e = missing_edges<W>(s, Pr, np, s.pos);
-      if (e == (int)(full - m) && near_complete_count(s.pos, e, np, 3, clo, chi)) {
-        lo = clo;
-        hi = chi;
-        fp = 0;
-        return;
-      }
+  u64 clo, chi, cfp;
+  if (m < full && full - m <= (u64)kNearMissing) {
+    const int e = missing_edges<W>(s, Pr, np, s.pos);
+    if (e == (int)(full - m) && near_complete<W, FP>(s.pos, e, np, 3, s.mem, s.gl, clo, chi, cfp)) {
+      lo = clo;
+      hi = chi;
+      fp = cfp;
+      return;
     }
   }
   if (m == full && binom128(np, 3, clo, chi)) {
     lo = clo;
     hi = chi;
-    fp = FP ? esym_members(s.mem, np, s.gl, 3) : 0;
+    fp = FP ? esym_members<W>(s.mem, np, s.gl, 3) : 0;
     return;
   }
   u64 c_acc = 0, f_acc = 0;
@@ -598,7 +731,7 @@ __device__ __forceinline__ void leaf3_count(const Lds& s, const u64 (&Pr)[W], in
     wops += W;
     if (c >= 2 && s.rcap[x] >= 3) {
       u64 ec = 0, ef = 0;
-      edges_in<W>(q, s.A, s.gl, FP, ec, ef, wops, bits);
+      edges_in<W>(q, s.A, s.gl, s.wtab, FP, ec, ef, wops, bits);
       c_acc += ec;
       if (FP && ec) f_acc = addp(f_acc, mulp(s.gl[x], ef));
     }
@@ -729,6 +862,7 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
       ++n_builds;
       // ---- 1. G_u in LDS ------------------------------------------------------
       arcs += build_subgraph<W>(s, Gdptr, Gdcol, Ggw, Gorig, oid, beg, d);
+      if (s.wtab) build_weight_table<W>(s, d);
 
       // ---- 2. soft-embedding bound (Algorithm 5) ---------------------------------
       if (p.soft_only) {
@@ -821,7 +955,7 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
           u64 f = 0;
           if (FP) {
             u64 tmpb = 0;
-            f = weight_sum<W>(Pr, s.gl, tmpb);
+            f = weight_sum_any<W>(Pr, s.gl, s.wtab, tmpb);
             bits += (lane == 0) ? tmpb : 0;
           }
           res_lo = c; res_hi = 0; res_fp = f;
@@ -892,14 +1026,15 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
             wops += (u64)((np + kWave - 1 - lane) / kWave) * W;
             m = wave_sum(m);
             u64 clo, chi;
-            if constexpr (!FP) {
+            {
               const u64 full = (u64)np * (u64)(np - 1) / 2;
               if (m < full && full - m <= (u64)kNearMissing) {
                 const int e = missing_edges<W>(s, Pr, np, s.pos);
-                if (e == (int)(full - m) && near_complete_count(s.pos, e, np, 3, clo, chi)) {
+                u64 cfp;
+                if (e == (int)(full - m) && near_complete<W, FP>(s.pos, e, np, 3, s.mem, s.gl, clo, chi, cfp)) {
                   res_lo = clo;
                   res_hi = chi;
-                  res_fp = 0;
+                  res_fp = cfp;
                   if (memo_j && memo_live) {
                     memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
                     ++n_ins;
@@ -913,7 +1048,7 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
             if (m == (u64)np * (u64)(np - 1) / 2 && binom128(np, 3, clo, chi)) {
               res_lo = clo;
               res_hi = chi;
-              res_fp = FP ? esym_members(s.mem, np, s.gl, 3) : 0;
+              res_fp = FP ? esym_members<W>(s.mem, np, s.gl, 3) : 0;
                 if (memo_j && memo_live) {
                 memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
                 ++n_ins;
@@ -942,10 +1077,10 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
               if (l == 2) {
                 c_acc += (u64)c;
                 mine = (u64)c;
-                if (FP && c) f_acc = addp(f_acc, mulp(s.gl[x], weight_sum<W>(q, s.gl, bits)));
+                if (FP && c) f_acc = addp(f_acc, mulp(s.gl[x], weight_sum_any<W>(q, s.gl, s.wtab, bits)));
               } else if (c >= 2 && s.rcap[x] >= 3) {
                 u64 ec = 0, ef = 0;
-                edges_in<W>(q, s.A, s.gl, FP, ec, ef, wops, bits);
+                edges_in<W>(q, s.A, s.gl, s.wtab, FP, ec, ef, wops, bits);
                 c_acc += ec;
                 mine = ec;
                 if (FP && ec) f_acc = addp(f_acc, mulp(s.gl[x], ef));
@@ -1023,23 +1158,23 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
           if (binom128(np, l, clo, chi)) {
             res_lo = clo;
             res_hi = chi;
-            res_fp = FP ? esym_members(s.mem, np, s.gl, l) : 0;
+            res_fp = FP ? esym_members<W>(s.mem, np, s.gl, l) : 0;
             if (j == jsplit && sub != 0) res_lo = res_hi = res_fp = 0;
             __syncthreads();
             mode = FINISH;
             continue;
           }
         }
-        if constexpr (!EMIT && !FP) {
+        if constexpr (!EMIT) {
           const u64 full = (u64)np * (u64)(np - 1) / 2;
           if (j > 0 && m_edges < full && full - m_edges <= (u64)kNearMissing) {
             const int e = missing_edges<W>(s, Pr, np, s.pos);
-            u64 clo, chi;
-            if (e == (int)(full - m_edges) && near_complete_count(s.pos, e, np, l, clo, chi)) {
+            u64 clo, chi, cfp;
+            if (e == (int)(full - m_edges) && near_complete<W, FP>(s.pos, e, np, l, s.mem, s.gl, clo, chi, cfp)) {
               res_lo = clo;
               res_hi = chi;
-              res_fp = 0;
-              if (j == jsplit && sub != 0) res_lo = res_hi = 0;
+              res_fp = cfp;
+              if (j == jsplit && sub != 0) res_lo = res_hi = res_fp = 0;
               __syncthreads();
               mode = FINISH;
               continue;

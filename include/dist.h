@@ -57,6 +57,8 @@ extern "C" {
 #define DIST_E_CANCELLED 6   /* the sink returned nonzero, or the deadline in
                                 dist_config.deadline_ms passed; results partial */
 #define DIST_E_UNSUPPORTED 7 /* a root's out-degree exceeds DIST_MAX_OUTDEG */
+#define DIST_E_SCRATCH 8     /* dist_count_noalloc: the call's launch plan exceeds
+                                DIST_NOALLOC_PLAN_SEGS segments */
 
 #define DIST_K_MAX 64
 #define DIST_MAX_OUTDEG 1024  /* widest per-root subgraph (16 words per bitmap row) */
@@ -186,6 +188,30 @@ int dist_count(const dist_graph* g, int k, void* hip_stream, dist_result* out);
  * input vertex v (zero for vertices that are not roots). */
 int dist_count_ex(const dist_graph* g, int k, const dist_config* cfg,
                   uint64_t* per_root, void* hip_stream, dist_result* out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dist_count
+ * that allocates nothing.  It calls no hipMalloc, hipFree, pinned-memory or
+ * other allocating routine; everything the kernels need beyond the graph and
+ * *out (unit cursors, abort flag, per-wave results of up to
+ * DIST_NOALLOC_WAVES resident waves -- a larger grid is clamped -- and the
+ * launch plan of up to DIST_NOALLOC_PLAN_SEGS segments) lives in one static
+ * device block of 0.55 MB per GPU, held until the process ends.  The
+ * memo table is not used (cfg->memo is ignored: it is a cache and changes no
+ * result) and there is no per-root output; every other switch of cfg (NULL =
+ * the graph's) applies.  Results and statuses are those of dist_count_ex
+ * with the same switches; the device time is not measured (the kernel_ms of
+ * dist_stats_get is 0).  Every call on a GPU shares that GPU's block, which
+ * keeps the last call's contents (each call clears what must start at zero):
+ * two calls overlapping on one GPU would race on it, so the library makes
+ * its calls from several host threads take turns (each returns only after
+ * its work on the stream is done).  Returns DIST_E_SCRATCH if the plan would
+ * not fit (for one graph it always fits: its segments are at most its
+ * distinct out-degrees, <= DIST_MAX_OUTDEG). */
+#define DIST_NOALLOC_WAVES 4096
+#define DIST_NOALLOC_PLAN_SEGS 1024
+int dist_count_noalloc(const dist_graph* g, int k, const dist_config* cfg,
+                       void* hip_stream, dist_result* out);
 
 /* List the k-cliques of g (Definition "k-clique listing"): every clique is
  * delivered once to sink as k ascending input ids, in chunks; the order of

@@ -59,6 +59,7 @@ const char* dist_strerror(int status) {
     case DIST_E_OVERFLOW: return "count exceeds 64 bits (128-bit result is exact)";
     case DIST_E_CANCELLED: return "cancelled (sink stop or deadline)";
     case DIST_E_UNSUPPORTED: return "root out-degree or k beyond the supported range";
+    case DIST_E_SCRATCH: return "the call needs more than the fixed scratch of dist_count_noalloc holds";
     default: return "unknown status";
   }
 }
@@ -144,6 +145,22 @@ int dist_count_ex(const dist_graph* g, int k, const dist_config* cfg, uint64_t* 
 
 int dist_count(const dist_graph* g, int k, void* hip_stream, dist_result* out) {
   return dist_count_ex(g, k, nullptr, nullptr, hip_stream, out);
+}
+
+int dist_count_noalloc(const dist_graph* g, int k, const dist_config* cfg, void* hip_stream, dist_result* out) {
+  if (!g || !out) return DIST_E_INVALID;
+  if (!valid_k(k)) return DIST_E_K;
+  SearchLaunch L;
+  L.g = g;
+  L.k = k;
+  L.cfg = cfg ? *cfg : g->cfg;
+  L.cfg.memo = 0;
+  L.stream = (hipStream_t)hip_stream;
+  L.per_root = nullptr;
+  dist_stats st{};
+  int rc = search_count(L, out, &st, true);
+  g->stats = st;
+  return rc;
 }
 
 int dist_list(const dist_graph* g, int k, dist_sink sink, void* user, void* hip_stream, dist_result* out) {

@@ -49,7 +49,9 @@ struct SearchLaunch {
   u64* per_root;       // device, 3 per input id, or null
   hipStream_t stream;
 };
-int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st);
+// no_alloc: the form behind dist_count_noalloc (no per-root output, no memo,
+// every buffer in the library's static scratch block).
+int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st, bool no_alloc = false);
 int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out,
                            hipStream_t s);
 

@@ -1671,8 +1671,9 @@ void split_children(const dist_graph* g, int32_t nroots, int k, int cw, int forc
 // Appends the work segments of pair `pair` (roots [0, nroots) of g, clique
 // size k) to the width classes: consecutive roots with the same width and the
 // same split into units form one segment.
+template <class SegList>
 void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, bool whole_roots, int min_w,
-                  const int (&sub_of)[kClasses], std::vector<BatchSeg> (&segs)[kClasses],
+                  const int (&sub_of)[kClasses], SegList (&segs)[kClasses],
                   uint64_t (&units)[kClasses], int (&kmax)[kClasses]) {
   // walks the runs of equal out-degree (roots are in descending out-degree
   // order), so planning costs O(distinct degrees), not O(roots)
@@ -1761,43 +1762,118 @@ std::vector<Bucket> make_buckets(const dist_graph* g, int32_t nroots) {
 }
 
 
+// Segments of one graph's count: consecutive roots of equal out-degree fall
+// into one segment, so a class holds at most as many segments as there are
+// out-degrees (<= DIST_MAX_OUTDEG), and so does the whole plan.  A list of
+// fixed capacity over static storage (calls hold g_ws_mu).
+constexpr size_t kPlanSegs = DIST_MAX_OUTDEG;
+struct SegList {
+  BatchSeg* p = nullptr;
+  size_t n = 0, cap = 0;
+  void push_back(const BatchSeg& x) {
+    if (n < cap) p[n] = x;
+    ++n;
+  }
+  size_t size() const { return n < cap ? n : cap; }
+  bool overflow() const { return n > cap; }
+  BatchSeg& operator[](size_t i) { return p[i]; }
+  const BatchSeg& operator[](size_t i) const { return p[i]; }
+};
+BatchSeg g_seg_store[kClasses][kPlanSegs];
+
+// ---- scratch of the no-allocation entry point -------------------------------
+// One fixed block of device memory per GPU holds everything a count needs
+// beyond its inputs and outputs: the unit cursors and the abort flag, the
+// per-wave results of up to kScratchWaves resident waves (a larger grid is
+// clamped: the kernels are persistent) and the launch plan (graph descriptor
+// and up to kPlanSegs segments).  Its host-side mirrors are static too.
+constexpr int kScratchWaves = 4096;
+constexpr size_t kScratchHead = 64;  // words: cursors (words 0..31), abort flag (32..39)
+constexpr size_t kScratchPlanBytes = sizeof(BatchGraph) + sizeof(BatchSeg) * (kPlanSegs + 1);
+constexpr size_t kScratchWords = kScratchHead + (size_t)kScratchWaves * kOutWords + (kScratchPlanBytes + 7) / 8;
+static_assert(kScratchWaves == DIST_NOALLOC_WAVES && kPlanSegs == DIST_NOALLOC_PLAN_SEGS, "dist.h limits");
+static __device__ __align__(256) u64 scratch[kScratchWords];
+u64 g_scratch_host_out[(size_t)kScratchWaves * kOutWords];
+u64 g_scratch_host_plan[(kScratchPlanBytes + 7) / 8];
+
+// The device address of scratch on the current device, looked up once per
+// device with that device current (each GPU holds its own copy).
+int scratch_base(u64** out) {
+  static std::mutex mu;
+  static u64* base[64] = {};
+  int dev = 0;
+  DIST_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return DIST_E_DEVICE;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!base[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return DIST_E_DEVICE;
+    base[dev] = (u64*)ptr;
+  }
+  *out = base[dev];
+  return DIST_OK;
+}
+
+// ensure_binom without a stream of its own: the fill is queued on s, ahead of
+// the searches of the same call.
+int ensure_binom_on(hipStream_t s) {
+  static bool done[64] = {};
+  int dev = 0;
+  DIST_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return DIST_OK;
+  if (done[dev]) return DIST_OK;
+  hipLaunchKernelGGL(k_fill_binom, dim3((kBinomN + 1 + 255) / 256), dim3(256), 0, s);
+  DIST_CHECK(hipGetLastError());
+  DIST_CHECK(hipStreamSynchronize(s));
+  done[dev] = true;
+  return DIST_OK;
+}
+
+// fixed != null: the no-allocation form -- every device buffer is a region of
+// the scratch block at `fixed`, host copies go through static buffers, no
+// memo table (it is a cache and changes no result) and no timing events.
 int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_config& cfg, hipStream_t s,
-                u64* totals /* 16 */, double* ms_out, dist_stats* bst = nullptr) {
+                u64* totals /* 16 */, double* ms_out, dist_stats* bst = nullptr, u64* fixed = nullptr) {
   for (int i = 0; i < kOutWords; ++i) totals[i] = 0;
   if (nroots <= 0) return DIST_OK;
   if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
-  if (int rb = ensure_binom()) return rb;
+  if (int rb = fixed ? ensure_binom_on(s) : ensure_binom()) return rb;
   const int cw = base.chunk_work;  // 0: automatic per k
-  std::vector<BatchSeg> segs[kClasses];
+  SegList segs[kClasses];
+  for (int sl = 0; sl < kClasses; ++sl) segs[sl] = SegList{g_seg_store[sl], 0, kPlanSegs};
   uint64_t units64[kClasses] = {};
   int kmax[kClasses] = {};
   int sub_of[kClasses];
   split_children(g, nroots, base.k, cw, cfg.sub_units, sub_of);
   add_segments(g, 0, nroots, base.k, cw, base.soft_only != 0, 1, sub_of, segs, units64, kmax);
-  std::vector<Bucket> buckets;
-  std::vector<uint32_t> units;
-  std::vector<size_t> seg_off;
+  Bucket buckets[kClasses];
+  uint32_t units[kClasses];
+  size_t seg_off[kClasses];
+  size_t nbk = 0;
   size_t nseg_total = 0;
   for (int sl = 0; sl < kClasses; ++sl) {
+    if (segs[sl].overflow()) return DIST_E_UNSUPPORTED;
     if (units64[sl] == 0) continue;
     if (units64[sl] >= 0xffffffffull) return DIST_E_UNSUPPORTED;
     // roots are in descending out-degree order: a class's first root is its widest
-    buckets.push_back(Bucket{kSlotWidth[sl], 0, 0, lds_rows(kSlotWidth[sl], g->root_deg[segs[sl][0].a])});
-    units.push_back((uint32_t)units64[sl]);
-    seg_off.push_back(nseg_total);
+    buckets[nbk] = Bucket{kSlotWidth[sl], 0, 0, lds_rows(kSlotWidth[sl], g->root_deg[segs[sl][0].a])};
+    units[nbk] = (uint32_t)units64[sl];
+    seg_off[nbk] = nseg_total;
+    ++nbk;
     nseg_total += segs[sl].size();
   }
+  if (fixed && nseg_total > kPlanSegs) return DIST_E_SCRATCH;
   {
     int dev = 0, maxlds = 0;
     DIST_CHECK(hipGetDevice(&dev));
     DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    for (auto& b : buckets)
-      if (lds_bytes(b.W, base.k, base.fingerprint, b.D) > (size_t)maxlds) return DIST_E_UNSUPPORTED;
+    for (size_t b = 0; b < nbk; ++b)
+      if (lds_bytes(buckets[b].W, base.k, base.fingerprint, buckets[b].D) > (size_t)maxlds) return DIST_E_UNSUPPORTED;
   }
   // grids and memo sizing
   int maxgrid = 0;
-  std::vector<int> grids(buckets.size());
-  for (size_t b = 0; b < buckets.size(); ++b) {
+  int grids[kClasses];
+  for (size_t b = 0; b < nbk; ++b) {
     int W = buckets[b].W;
     size_t lds = lds_bytes(W, base.k, base.fingerprint, buckets[b].D);
     int occ = 1;
@@ -1807,17 +1883,18 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     int64_t grid = (int64_t)occ * cus;
     int64_t cnt = units[b];
     if (grid > cnt) grid = cnt;
+    if (fixed && grid > kScratchWaves) grid = kScratchWaves;
     if (grid < 1) grid = 1;
     grids[b] = (int)grid;
     if (grids[b] > maxgrid) maxgrid = grids[b];
   }
-  bool want_memo = cfg.memo != 0 && base.k >= 4 && !base.soft_only;
+  bool want_memo = cfg.memo != 0 && base.k >= 4 && !base.soft_only && !fixed;
   size_t memo_total = 0;
   u64 entries = 0;
   if (want_memo) {
     size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)16 << 30);
     int maxW = 1;
-    for (auto& b : buckets) maxW = b.W > maxW ? b.W : maxW;
+    for (size_t b = 0; b < nbk; ++b) maxW = buckets[b].W > maxW ? buckets[b].W : maxW;
     size_t es = (size_t)(maxW + 4) * 8;
     if (cfg.memo_entries > 0) {
       entries = 1;
@@ -1828,32 +1905,57 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     }
     memo_total = entries * es * (size_t)maxgrid;
   }
-  int rc = ws_ensure((size_t)maxgrid * kOutWords, memo_total);
-  if (rc) return rc;
-  // device plan: the graph descriptor, then the segments of every class
+  // device and host buffers: the library's workspace, or regions of scratch
+  unsigned* cursor;
+  int* abort_flag;
+  u64* wave_out;
+  u64* host_out;
+  char* d_plan;
+  char* h_plan;
   const size_t plan_bytes = sizeof(BatchGraph) + sizeof(BatchSeg) * (nseg_total + 1);
-  rc = ws_plan(plan_bytes);
-  if (rc) return rc;
+  int rc = DIST_OK;
+  if (fixed) {
+    cursor = (unsigned*)fixed;
+    abort_flag = (int*)(fixed + 32);
+    wave_out = fixed + kScratchHead;
+    d_plan = (char*)(fixed + kScratchHead + (size_t)kScratchWaves * kOutWords);
+    host_out = g_scratch_host_out;
+    h_plan = (char*)g_scratch_host_plan;
+  } else {
+    rc = ws_ensure((size_t)maxgrid * kOutWords, memo_total);
+    if (rc) return rc;
+    rc = ws_plan(plan_bytes);
+    if (rc) return rc;
+    cursor = g_ws.cursor;
+    abort_flag = g_ws.abort_flag;
+    wave_out = g_ws.wave_out;
+    host_out = g_ws.host_out;
+    d_plan = g_ws.d_plan;
+    h_plan = g_ws.h_plan;
+  }
+  // device plan: the graph descriptor, then the segments of every class
   {
     BatchGraph bgh{g->dptr, g->dcol, g->orig, g->roots, g->gw, base.k, 0};
-    memcpy(g_ws.h_plan, &bgh, sizeof(bgh));
-    BatchSeg* hs = (BatchSeg*)(g_ws.h_plan + sizeof(BatchGraph));
+    memcpy(h_plan, &bgh, sizeof(bgh));
+    BatchSeg* hs = (BatchSeg*)(h_plan + sizeof(BatchGraph));
     size_t o = 0;
     for (int sl = 0; sl < kClasses; ++sl)
-      for (const BatchSeg& x : segs[sl]) hs[o++] = x;
-    DIST_CHECK(hipMemcpyAsync(g_ws.d_plan, g_ws.h_plan, plan_bytes, hipMemcpyHostToDevice, s));
+      for (size_t i = 0; i < segs[sl].size(); ++i) hs[o++] = segs[sl][i];
+    DIST_CHECK(hipMemcpyAsync(d_plan, h_plan, plan_bytes, hipMemcpyHostToDevice, s));
   }
-  const BatchGraph* d_bg = (const BatchGraph*)g_ws.d_plan;
-  const BatchSeg* d_segs = (const BatchSeg*)(g_ws.d_plan + sizeof(BatchGraph));
+  const BatchGraph* d_bg = (const BatchGraph*)d_plan;
+  const BatchSeg* d_segs = (const BatchSeg*)(d_plan + sizeof(BatchGraph));
 
-  hipEvent_t e0, e1, kb0, kb1;
-  DIST_CHECK(hipEventCreate(&e0));
-  DIST_CHECK(hipEventCreate(&e1));
-  DIST_CHECK(hipEventCreate(&kb0));
-  DIST_CHECK(hipEventCreate(&kb1));
+  hipEvent_t e0 = nullptr, e1 = nullptr, kb0 = nullptr, kb1 = nullptr;
+  if (!fixed) {
+    DIST_CHECK(hipEventCreate(&e0));
+    DIST_CHECK(hipEventCreate(&e1));
+    DIST_CHECK(hipEventCreate(&kb0));
+    DIST_CHECK(hipEventCreate(&kb1));
+  }
   double kernel_ms = 0;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, g_ws.cursor, 64);
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)g_ws.abort_flag, 16);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, cursor, 64);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)abort_flag, 16);
   u64 deadline = 0;
   if (cfg.deadline_ms > 0) {
     // wall_clock64 runs at a fixed rate: query it
@@ -1861,8 +1963,8 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     DIST_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, g_ws.device));
     deadline = (u64)cfg.deadline_ms * (u64)rate_khz;  // relative; made absolute on the device
   }
-  DIST_CHECK(hipEventRecord(e0, s));
-  for (size_t b = 0; b < buckets.size(); ++b) {
+  if (!fixed) DIST_CHECK(hipEventRecord(e0, s));
+  for (size_t b = 0; b < nbk; ++b) {
     Params prm = base;
     prm.root_deg = g->d_root_deg;
     prm.chunk_work = cw;
@@ -1871,9 +1973,9 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     prm.segs = d_segs + seg_off[b];
     prm.nsegs = (int32_t)segs[wslot_of_width(buckets[b].W)].size();
     prm.pair_out = nullptr;
-    prm.cursor = g_ws.cursor + b;  // one counter per bucket (zeroed above; <= 6 buckets)
-    prm.wave_out = g_ws.wave_out;
-    prm.abort_flag = g_ws.abort_flag;
+    prm.cursor = cursor + b;  // one counter per bucket (zeroed above; <= 8 buckets)
+    prm.wave_out = wave_out;
+    prm.abort_flag = abort_flag;
     prm.memo_base = want_memo ? g_ws.memo : nullptr;
     prm.memo_mask = want_memo ? entries - 1 : 0;
     // root tags are unit indices of this launch: reserve the whole range
@@ -1883,20 +1985,20 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     g_tag_next += (u64)units[b] + 1;
     size_t lds = lds_bytes(buckets[b].W, base.k, base.fingerprint, buckets[b].D);
     prm.drows = buckets[b].D;
-    hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grids[b] * kOutWords);
-    DIST_CHECK(hipEventRecord(kb0, s));
+    hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, wave_out, (u64)grids[b] * kOutWords);
+    if (!fixed) DIST_CHECK(hipEventRecord(kb0, s));
     rc = with_width(buckets[b].W, [&](auto w) { return launch_bucket<decltype(w)::value>(prm, grids[b], lds, s); });
     if (rc) break;
-    DIST_CHECK(hipEventRecord(kb1, s));
-    DIST_CHECK(hipMemcpyAsync(g_ws.host_out, g_ws.wave_out, (size_t)grids[b] * kOutWords * sizeof(u64),
+    if (!fixed) DIST_CHECK(hipEventRecord(kb1, s));
+    DIST_CHECK(hipMemcpyAsync(host_out, wave_out, (size_t)grids[b] * kOutWords * sizeof(u64),
                               hipMemcpyDeviceToHost, s));
     DIST_CHECK(hipStreamSynchronize(s));
     float kms = 0;
-    DIST_CHECK(hipEventElapsedTime(&kms, kb0, kb1));
+    if (!fixed) DIST_CHECK(hipEventElapsedTime(&kms, kb0, kb1));
     kernel_ms += kms;
     u64 bw = 0, bb = 0, br = 0, ba = 0;
     for (int w = 0; w < grids[b]; ++w) {
-      const u64* o = g_ws.host_out + (size_t)w * kOutWords;
+      const u64* o = host_out + (size_t)w * kOutWords;
       br += o[3];
       bw += o[6];
       bb += o[7];
@@ -1911,7 +2013,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
       bst->bucket_arcs[sl] += ba;
     }
     for (int w = 0; w < grids[b]; ++w) {
-      const u64* o = g_ws.host_out + (size_t)w * kOutWords;
+      const u64* o = host_out + (size_t)w * kOutWords;
       u64 lo = totals[0] + o[0];
       totals[1] += o[1] + (lo < totals[0] ? 1 : 0);
       totals[0] = lo;
@@ -1923,15 +2025,16 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     }
     if (totals[12]) break;
   }
-  DIST_CHECK(hipEventRecord(e1, s));
-  DIST_CHECK(hipEventSynchronize(e1));
-  float ms = 0;
-  DIST_CHECK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(kb0);
-  (void)hipEventDestroy(kb1);
-  (void)ms;
+  if (!fixed) {
+    DIST_CHECK(hipEventRecord(e1, s));
+    DIST_CHECK(hipEventSynchronize(e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(kb0);
+    (void)hipEventDestroy(kb1);
+  } else {
+    DIST_CHECK(hipStreamSynchronize(s));
+  }
   if (ms_out) *ms_out = kernel_ms;
   if (rc) return rc;
   return totals[12] ? DIST_E_CANCELLED : DIST_OK;
@@ -1939,7 +2042,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
 
 }  // namespace
 
-int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st) {
+int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st, bool no_alloc) {
   std::lock_guard<std::recursive_mutex> lock(g_ws_mu);
   const dist_graph* g = L.g;
   const int k = L.k;
@@ -1947,14 +2050,26 @@ int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st) {
   dist_stats stats{};
   hipStream_t s = L.stream;
   int rc = DIST_OK;
+  u64* fixed = nullptr;
+  if (no_alloc) {
+    if (L.per_root) return DIST_E_INVALID;
+    rc = scratch_base(&fixed);
+    if (rc) return rc;
+  }
   if (k == 1) {
     res.count_lo = (u64)g->n;
     if (L.cfg.fingerprint && g->n > 0) {
-      int r2 = ws_ensure(kOutWords, 0);
-      if (r2) return r2;
-      hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, g_ws.wave_out, (u64)1);
-      hipLaunchKernelGGL(k_sum_weights, dim3(256), dim3(256), 0, s, g->gw, g->n, g_ws.wave_out);
-      DIST_CHECK(hipMemcpyAsync(&res.fp, g_ws.wave_out, sizeof(u64), hipMemcpyDeviceToHost, s));
+      u64* acc = nullptr;
+      if (fixed) {
+        acc = fixed + kScratchHead;
+      } else {
+        int r2 = ws_ensure(kOutWords, 0);
+        if (r2) return r2;
+        acc = g_ws.wave_out;
+      }
+      hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, acc, (u64)1);
+      hipLaunchKernelGGL(k_sum_weights, dim3(256), dim3(256), 0, s, g->gw, g->n, acc);
+      DIST_CHECK(hipMemcpyAsync(&res.fp, acc, sizeof(u64), hipMemcpyDeviceToHost, s));
       DIST_CHECK(hipStreamSynchronize(s));
     }
     if (L.per_root) {
@@ -1998,7 +2113,7 @@ int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st) {
   prm.per_root = L.per_root;
   u64 tot[kOutWords];
   double ms = 0;
-  rc = run_buckets(g, prm, nroots, L.cfg, s, tot, &ms, &stats);
+  rc = run_buckets(g, prm, nroots, L.cfg, s, tot, &ms, &stats, fixed);
   res.count_lo = tot[0];
   res.count_hi = tot[1];
   res.fp = L.cfg.fingerprint ? tot[2] : 0;

@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdist.so")
 
-OK, E_INVALID, E_K, E_NOMEM, E_DEVICE, E_OVERFLOW, E_CANCELLED, E_UNSUPPORTED = range(8)
+OK, E_INVALID, E_K, E_NOMEM, E_DEVICE, E_OVERFLOW, E_CANCELLED, E_UNSUPPORTED, E_SCRATCH = range(9)
 WIDTHS = (1, 2, 3, 4, 5, 6, 8, 16)   # DIST_WIDTHS: bitmap width classes (words)
 WIDTH_CLASSES = len(WIDTHS)
 ORDER_DEGREE, ORDER_DEGENERACY = 0, 1
@@ -105,6 +105,8 @@ def _load():
     lib.dist_count_ex.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Config), vp, vp,
                                   ctypes.POINTER(Result)]
     lib.dist_count_ex.restype = ctypes.c_int
+    lib.dist_count_noalloc.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Config), vp, ctypes.POINTER(Result)]
+    lib.dist_count_noalloc.restype = ctypes.c_int
     lib.dist_list.argtypes = [vp, ctypes.c_int, SINK, vp, vp, ctypes.POINTER(Result)]
     lib.dist_list.restype = ctypes.c_int
     lib.dist_count_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
@@ -255,6 +257,17 @@ def count(g: Graph, k: int, cfg: Config | None = None, per_root=None, stream=Non
                                    pr, _stream_ptr(stream), ctypes.byref(res))
     if rc not in (OK, E_OVERFLOW) or (rc == E_OVERFLOW and not allow_overflow):
         _check(rc, "dist_count")
+    return res.count, int(res.fp), rc
+
+
+def count_noalloc(g: Graph, k: int, cfg: Config | None = None, stream=None, allow_overflow=True):
+    """dist_count_noalloc: (count, fp, status) without any device allocation
+    (static scratch; no memo, no per-root output)."""
+    res = Result()
+    rc = _load().dist_count_noalloc(g.handle, int(k), ctypes.byref(cfg) if cfg is not None else None,
+                                    _stream_ptr(stream), ctypes.byref(res))
+    if rc not in (OK, E_OVERFLOW) or (rc == E_OVERFLOW and not allow_overflow):
+        _check(rc, "dist_count_noalloc")
     return res.count, int(res.fp), rc
 
 

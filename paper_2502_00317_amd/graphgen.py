@@ -356,32 +356,49 @@ def _spec_graph_arrays(spec):
     return g.row_ptr, g.col
 
 
-def spec_graphs(specs, workers: int = 0):
-    """spec_graph for every spec, in spawned worker processes."""
+def _gpu_in_use() -> bool:
+    """True if this process may hold a GPU context (torch initialised it, or
+    the library's binding is loaded)."""
+    import sys
+    t = sys.modules.get("torch")
+    if t is not None and t.cuda.is_initialized():
+        return True
+    d = sys.modules.get("paper_2502_00317_amd.dist")
+    return d is not None and getattr(d, "_lib", None) is not None
+
+
+def _map_procs(fn, items, workers: int, chunksize: int):
+    """fn over items in worker processes.  A process that holds no GPU
+    context forks its workers (no exec, no helper process left behind);
+    one that may hold a GPU context spawns them instead.  The pool is closed
+    and joined, so every worker ends normally rather than by a signal.
+    Results do not depend on the pool."""
     import multiprocessing as mp
     import os
     if workers <= 0:
         workers = min(16, os.cpu_count() or 1)
-    if workers == 1 or len(specs) < 4:
-        return [spec_graph(s) for s in specs]
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(workers) as pool:
-        arrays = pool.map(_spec_graph_arrays, specs, chunksize=1)
+    if workers == 1 or len(items) < 4:
+        return [fn(x) for x in items]
+    ctx = mp.get_context("spawn" if _gpu_in_use() else "fork")
+    pool = ctx.Pool(workers)
+    try:
+        out = pool.map(fn, items, chunksize=chunksize)
+    finally:
+        pool.close()
+        pool.join()
+    return out
+
+
+def spec_graphs(specs, workers: int = 0):
+    """spec_graph for every spec, in worker processes."""
+    arrays = _map_procs(_spec_graph_arrays, specs, workers, 1)
     return [Graph(rp, col, name="spec#%d" % s["i"]) for (rp, col), s in zip(arrays, specs)]
 
 
 def batch_graphs(specs, workers: int = 0):
-    """batch_graph for every spec, in worker processes (spawned, so the
-    caller may hold a GPU context).  Each graph depends only on its spec."""
-    import multiprocessing as mp
-    import os
-    if workers <= 0:
-        workers = min(16, os.cpu_count() or 1)
-    if workers == 1 or len(specs) < 8:
-        return [batch_graph(s) for s in specs]
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(workers) as pool:
-        arrays = pool.map(_batch_graph_arrays, specs, chunksize=8)
+    """batch_graph for every spec, in worker processes.  Each graph depends
+    only on its spec."""
+    arrays = _map_procs(_batch_graph_arrays, specs, workers, 8)
     return [Graph(rp, col, name="batch#%d" % s["i"]) for (rp, col), s in zip(arrays, specs)]
 
 

@@ -1,17 +1,19 @@
 """Parity at full size, in the launch configuration the benchmark times.
 
 The one-large-graph workload (Chung-Lu n = 10^6, exponent 2.2, mean degree
-20, cap 5,000, 200 planted K30) has ~5e16 9-cliques: the oracle cannot
-enumerate them, but it can recount single roots.  Each test runs the whole
-graph on the GPU with per-root output, checks that the per-root results add
-up to the total of the plain call (the benchmark's call, no per-root
-output), and compares seeded samples of roots one by one: roots whose
+20, cap 5,000, 200 planted K30) has ~5e16 9-cliques: the enumerating oracle
+cannot list them, but its pivot-based counter totals every root in under a
+minute (tests/golden/cfg2_totals.json, written by make_cfg2_totals.py from
+the oracle alone).  Each test compares the benchmark's call (count and
+fingerprint) with that total, runs the whole graph again with per-root
+output, checks that the per-root results add up to it, and compares seeded
+samples of roots one by one: roots whose
 search the enumerating oracle finishes quickly (C(d+, k-1) below a bound),
 and the dense core (the heaviest roots and a sample of roots with d+ >= 64)
 through the oracle's pivot-based counter.
 
-The batched workload (4,096 graphs) is checked on a seeded sample of pairs
-and on the 30 heaviest pairs through the pivot-based counter, and on the
+The batched workload (4,096 graphs) is checked on every pair against the
+oracle's per-pair results (tests/golden/cfg4_totals.json), and on the
 smallest sampled graphs through the enumerating oracle."""
 import math
 
@@ -57,13 +59,24 @@ def _sample_roots(outd, k, bound, n_uniform, n_heavy, seed):
     return np.array(sorted(pick), dtype=np.int32)
 
 
-@pytest.mark.parametrize("k,fp,bound", [(5, 1, 2e7), (7, 0, 2e6), (9, 0, 2e6)])
+def _golden_totals():
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cfg2_totals.json")))
+
+
+@pytest.mark.parametrize("k,fp,bound", [(5, 1, 2e7), (7, 1, 2e6), (9, 1, 2e6)])
 def test_large_graph_sampled_roots(D, oracle_mod, big, k, fp, bound):
     g, G, outd = big
     cfg = D.config(fingerprint=fp)
     print("full-size k=%d fp=%d" % (k, fp), flush=True)
     total, tfp, rc = D.count(G, k, cfg=cfg)          # the benchmark's call
     assert rc == D.OK
+    # the whole-graph total and fingerprint, against the oracle's (every root
+    # through the pivot-based counter; tests/golden/make_cfg2_totals.py)
+    gold = _golden_totals()
+    assert (gold["n"], gold["m"]) == (g.n, g.m)
+    assert (total, tfp) == (int(gold["results"][str(k)]["count"]), int(gold["results"][str(k)]["fp"]))
     per = np.zeros(3 * g.n, np.uint64)
     total2, tfp2, rc2 = D.count(G, k, cfg=cfg, per_root=per)
     assert (total2, tfp2, rc2) == (total, tfp, rc)
@@ -99,38 +112,45 @@ def test_large_graph_sampled_roots(D, oracle_mod, big, k, fp, bound):
         sum(c for c, _ in want), float(total)), flush=True)
 
 
-def test_batched_workload_sampled_pairs(D, oracle_mod):
-    """Pairs of the full 4,096-pair batch, graph-captured as the benchmark
-    runs it, against the oracle."""
+def test_batched_workload_every_pair(D, oracle_mod):
+    """Every pair of the full 4,096-pair batch, graph-captured as the
+    benchmark runs it, against the oracle: the digest of the per-pair
+    (count, fp) list, their sums and the first 256 pairs verbatim, written by
+    tests/golden/make_cfg4_totals.py from the oracle's pivot-based counter;
+    the 40 smallest graphs of a seeded sample also against the enumerating
+    oracle."""
+    import json
+    import os
+    sys_path = os.path.join(os.path.dirname(__file__), "golden")
+    gold = json.load(open(os.path.join(sys_path, "cfg4_totals.json")))
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_cfg4_totals", os.path.join(sys_path, "make_cfg4_totals.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
     specs = gg.batch_specs()
     graphs = gg.batch_graphs(specs)
     ks = [s["k"] for s in specs]
+    assert (len(specs), sum(g.m for g in graphs)) == (gold["pairs"], gold["edges"])
     G = [D.orient(g.row_ptr, g.col) for g in graphs]
     res, rc, ms = D.count_batch(G, ks, cfg=D.config(), use_graph=True)
     assert rc in (D.OK, D.E_OVERFLOW)
     P61 = (1 << 61) - 1
-
-    def pivot_total(i):
-        g = graphs[i]
-        per = oracle_mod.pivot_count_roots(g.row_ptr, g.col, ks[i], np.arange(g.n, dtype=np.int32))
-        return sum(c for c, _ in per), sum(f for _, f in per) % P61
-
-    # a uniform seeded sample of 300 pairs and the 30 heaviest (largest
-    # planted cliques for their k), every root of each graph, through the
-    # pivot-based reference; the 40 smallest sampled graphs also through the
-    # enumerating oracle
+    print("batched: %d pairs in %.1f ms" % (len(res), ms), flush=True)
+    for i, (c, f) in enumerate(gold["first"]):
+        assert res[i] == (int(c), int(f)), i
+    assert str(sum(c for c, _ in res)) == gold["sum_count"]
+    assert str(sum(f for _, f in res) % P61) == gold["sum_fp"]
+    assert mk.pair_digest(res) == gold["sha256"]
     rng = np.random.default_rng(44)
     sample = sorted(rng.choice(len(specs), size=300, replace=False).tolist())
-    heavy = sorted(range(len(specs)), key=lambda i: -sum(math.comb(p, ks[i]) for p in specs[i]["plants"]))[:30]
-    print("batched: %d sampled + %d heaviest pairs" % (len(sample), len(heavy)), flush=True)
-    for i in sorted(set(sample) | set(heavy)):
-        assert res[i] == pivot_total(i), i
     for i in sorted(sample, key=lambda i: specs[i]["n"])[:40]:
         g = graphs[i]
         assert res[i] == oracle_mod.count(g.row_ptr, g.col, ks[i]), i
     # a replay of the captured launch gives the same results for every pair
     res2, rc2, _ = D.count_batch(G, ks, cfg=D.config(), use_graph=True)
     assert res2 == res
+    for Gi in G:
+        Gi.free()
 
 
 def test_dense_core_rmat_orientation_and_budget(D):

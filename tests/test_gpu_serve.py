@@ -1,6 +1,6 @@
 """Serving on the GPU: continuous batching over two streams; every query's
-result in the mix equals its result alone; a query past its budget is
-stopped without stopping the rest of its batch."""
+result in the mix equals its result alone and the oracle's; a query past its
+budget is stopped without stopping the rest of its batch."""
 import numpy as np
 import pytest
 
@@ -48,6 +48,21 @@ def test_served_equals_alone(D, oracle_mod):
     assert s["completed"] == len(qs), [q.status for q in qs if q.status != "ok"]
     assert len(srv.batches) < len(qs)  # queries were batched
     print("moved to the bulk lane:", srv.demoted, flush=True)
+    P61 = (1 << 61) - 1
+    oracle_of = {}
+
+    def pool_oracle(gi, k):
+        # k <= 6 by enumeration, larger k by the pivot-based counter over
+        # every root (pinned against enumeration); both are the oracle's
+        if (gi, k) not in oracle_of:
+            g = pool[gi]
+            if k <= 6:
+                oracle_of[gi, k] = oracle_mod.count(g.row_ptr, g.col, k)
+            else:
+                per = oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, np.arange(g.n, dtype=np.int32))
+                oracle_of[gi, k] = (sum(c for c, _ in per), sum(f for _, f in per) % P61)
+        return oracle_of[gi, k]
+
     for q in qs:
         if q.adhoc is not None:
             G = D.orient(q.adhoc[0], q.adhoc[1])
@@ -56,8 +71,7 @@ def test_served_equals_alone(D, oracle_mod):
             G.free()
         else:
             alone = D.count(handles[q.graph], q.k)[:2]
-            g = pool[q.graph]
-            want = oracle_mod.count(g.row_ptr, g.col, q.k) if q.k <= 6 else alone
+            want = pool_oracle(q.graph, q.k)
         assert (q.count, q.fp) == alone == want, q.qid
 
 

@@ -635,6 +635,7 @@ def run_serving(a, dist, torch, inputs, log):
              ("plain", dict(slots=1, plain=True), [100], [{}])]
     modes = [m for m in modes if m[0] in a.serve_modes.split(",")]
     ans = {}
+    lat = {}
     for name, kw, pcts, scfg in modes:
         be = DeviceBackend(slots=kw["slots"], grid_pcts=pcts, slot_cfgs=scfg)
         srv = Server(be, handles, mem_limit=mem_limit, pool_bytes=pool_bytes, **kw)
@@ -654,19 +655,25 @@ def run_serving(a, dist, torch, inputs, log):
                          "moved_to_bulk": srv.demoted, "routed_to_bulk": srv.routed_bulk,
                          "heavy_keys": len(srv.heavy), "shed": srv.shed, "shed_frac": srv.shed_frac})
         ans[name] = {(q.qid): (q.count, q.fp) for q in qs if q.status in ("ok", "overflow")}
+        lat[name] = {q.qid: q.latency for q in qs if q.status in ("ok", "overflow")}
         if a.serve_trace:
             with open(a.serve_trace + "." + name + ".json", "w") as f:
                 json.dump({"batches": srv.batches,
                            "queries": [[q.qid, q.graph, q.k, q.lane, q.moves, q.status, q.t_arrival, q.t_start,
                                         q.t_done, q.slot, q.batch_size] for q in qs]}, f)
-        log("serving[%s]: p50 %.1f ms p99 %.1f ms, %d/%d completed, %d DNF, %.3g cliques/s" % (
-            name, summ["p50_ms"], summ["p99_ms"], summ["completed"], summ["queries"], summ["dnf"],
-            summ["cliques_per_s"]))
+        log("serving[%s]: p50 %.1f ms p99 %.1f ms (unfinished at their budget), %d/%d completed, %d DNF, "
+            "%d shed, %.3g cliques/s" % (name, summ["p50_ms"], summ["p99_ms"], summ["completed"], summ["queries"],
+                                         summ["dnf"], summ["shed"], summ["cliques_per_s"]))
         out[name] = summ
     if "served" in ans and "plain" in ans:
         both = set(ans["served"]) & set(ans["plain"])
         out["same_results_where_both_completed"] = all(ans["served"][i] == ans["plain"][i] for i in both)
         out["compared"] = len(both)
+        if both:
+            # latency percentiles of the two modes over the same queries
+            out["both_completed"] = {m: {"p50_ms": float(np.percentile([lat[m][i] for i in both], 50) * 1e3),
+                                         "p99_ms": float(np.percentile([lat[m][i] for i in both], 99) * 1e3)}
+                                     for m in ("served", "plain")}
     for h in handles.values():
         h.free()
     return out

@@ -260,3 +260,25 @@ def test_shed_queries_known_to_exceed_budget(oracle_mod):
     assert second[0].status == "dnf" and second[0].lane == "shed" and srv.shed == 1
     assert second[0].latency < 0.05
     assert second[1].status == "ok"
+
+
+def test_summary_charges_unfinished_queries_their_budget():
+    """Percentiles count every query: a DNF or shed query at its latency
+    budget, so dropping work cannot improve p50/p99; the completed-only
+    figures are reported beside them."""
+    qs = []
+    for i in range(100):
+        q = Query(qid=i, k=4, t_arrival=0.0, graph=0, deadline_ms=2000)
+        if i < 90:
+            q.status, q.t_done, q.count = "ok", 0.010, 1
+        else:
+            q.status = "dnf"
+            if i >= 95:
+                q.lane = "shed"
+        qs.append(q)
+    s = summarize(qs, 1.0)
+    assert s["completed"] == 90 and s["dnf"] == 10 and s["shed"] == 5
+    assert s["dnf_rate"] == 0.1
+    assert abs(s["p50_ms"] - 10.0) < 1e-6
+    assert abs(s["p99_ms"] - 2000.0) < 1e-6          # the unfinished tail, at its budget
+    assert abs(s["p99_completed_ms"] - 10.0) < 1e-6

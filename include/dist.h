@@ -76,6 +76,8 @@ typedef struct dist_graph dist_graph;
 #define DIST_ORDER_DEGREE 0      /* (degree, id) ascending */
 #define DIST_ORDER_DEGENERACY 1  /* bulk minimum-degree peeling: (round, id) ascending;
                                     every out-degree is at most the degeneracy */
+#define DIST_ORDER_INPUT 2       /* the caller's numbering: id ascending (an order
+                                    computed elsewhere, e.g. the worked example's) */
 
 /* Switches of the search.  All of them leave count and fp unchanged (the
  * paper's Theorem 1, Lemma 1 and Theorem 2); they only change the work. */
@@ -113,6 +115,13 @@ typedef struct {
                             sub_units-th surviving depth-2 child (results do
                             not depend on it); 0 = auto (more for wide roots
                             at large k, up to 32); larger values count as 32 */
+  int32_t trie_nodes;    /* listing: nodes of the Induced Subgraph Trie per
+                            wavefront (< 2^24); 0 = auto (32,768).  A frame
+                            whose string does not fit lists without the trie
+                            (results do not depend on it) */
+  int64_t list_bytes;    /* listing: device record buffer in bytes; 0 = auto
+                            (512 MiB).  Roots are listed in batches whose
+                            records fit it; one root's records must fit */
 } dist_config;
 
 typedef struct {
@@ -165,7 +174,8 @@ void dist_config_init(dist_config* cfg);
  * row_ptr: int32[n+1], col: int32[nnz]; host or device memory (detected);
  * the rows must be strictly increasing, symmetric, without self-loops.
  * nnz = row_ptr[n] = 2|E|.  The input is copied; the caller keeps
- * ownership.  order_mode: DIST_ORDER_DEGREE or DIST_ORDER_DEGENERACY.
+ * ownership.  order_mode: DIST_ORDER_DEGREE, DIST_ORDER_DEGENERACY or
+ * DIST_ORDER_INPUT.
  * cfg: switches stored with the graph (NULL = defaults).  On success *out
  * owns a device-resident DAG (ranks, out-lists sorted by rank, per-vertex
  * fingerprint weights, roots sorted by out-degree descending) until
@@ -216,9 +226,53 @@ int dist_count_noalloc(const dist_graph* g, int k, const dist_config* cfg,
 /* List the k-cliques of g (Definition "k-clique listing"): every clique is
  * delivered once to sink as k ascending input ids, in chunks; the order of
  * cliques is unspecified.  *out receives the count and fp of the cliques
- * delivered.  Returns DIST_E_CANCELLED if sink stopped the run. */
+ * delivered.  Returns DIST_E_CANCELLED if sink stopped the run.
+ *
+ * The search is Algorithm 2's Listing; a branch whose subgraph satisfies
+ * criterion (1) of Section IV (and still needs at least 4 vertices) runs as
+ * Algorithm 3's ListingDense on a per-root Induced Subgraph Trie: the
+ * identifying string of each dense subgraph is inserted, its path nodes get
+ * l-child and l-sibling links and Marked[l], and an l-memoised node's
+ * cliques are retrieved by Algorithm 4's ListingIST instead of being
+ * recomputed.  cfg->memo (dist_list_ex) selects: 1 criterion (1), 2 every
+ * branch that still needs >= 2 vertices, 0 no trie (Listing only).  Counters
+ * of the last run (dist_stats_get): memo_lookups = ListingDense frames,
+ * memo_inserts = trie nodes created, memo_hits = retrievals from l-memoised
+ * nodes, leaf_bits = cliques delivered by retrieval. */
 int dist_list(const dist_graph* g, int k, dist_sink sink, void* user,
               void* hip_stream, dist_result* out);
+
+/* dist_list with per-call switches (cfg NULL = the graph's) and flags:
+ * DIST_LIST_DEVICE_ROWS hands sink device pointers (rows in device memory,
+ * valid during the call) instead of copying them to the host first. */
+#define DIST_LIST_DEVICE_ROWS 1
+int dist_list_ex(const dist_graph* g, int k, const dist_config* cfg, int flags,
+                 dist_sink sink, void* user, void* hip_stream,
+                 dist_result* out);
+
+/* Inspection of the Induced Subgraph Trie (Section IV, Definitions of the
+ * l-child and l-sibling links, Algorithms 3 and 4) for one root: lists the
+ * k-cliques whose minimum vertex under g's order is input vertex `root`
+ * (k >= 3) with switches cfg, then runs ListingIST(t, ret_l, {root}) for the
+ * trie node t whose vertex set is ret_set (a bitmap over the root's local
+ * ids, 16 words; NULL or empty: no retrieval; ret_l must be k - 1, so that
+ * the retrieved cliques are k-cliques).  Outputs (host memory):
+ * local_ids[i] (i < *d, capacity DIST_MAX_OUTDEG): input id of local vertex
+ * i (the i-th out-neighbour of root in g's order); *n_nodes trie nodes
+ * (node 0 is the trie's root), at most cap + 1; per node t: sets[16 t ..]
+ * its vertex set over local ids, marked[t] bit l = Marked[l], lc[k t + l]
+ * and ls[k t + l] its l-child and l-sibling links (node ids; valid where
+ * Marked[l]); rows (may be NULL; room for rows_cap records): the root's
+ * *n_rows cliques followed by the *n_ret cliques of the retrieval, k
+ * ascending input ids each.  Errors: DIST_E_INVALID, DIST_E_UNSUPPORTED (trie or rows beyond the
+ * capacities), DIST_E_DEVICE. */
+int dist_ist_inspect(const dist_graph* g, int k, int32_t root,
+                     const dist_config* cfg, const uint64_t* ret_set, int ret_l,
+                     int32_t cap, int32_t* local_ids, int32_t* d,
+                     uint64_t* sets, uint64_t* marked, uint32_t* lc,
+                     uint32_t* ls, int32_t* n_nodes, int32_t* rows,
+                     int64_t rows_cap, int64_t* n_rows, int64_t* n_ret,
+                     void* hip_stream);
 
 /* Count many (graph, k) pairs in one persistent launch per bitmap width
  * class (at most five launches for the whole batch).  gs[i], ks[i] for

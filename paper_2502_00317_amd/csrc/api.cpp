@@ -70,7 +70,8 @@ int dist_orient(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t n
   *out = nullptr;
   if (n < 0 || nnz < 0 || nnz >= ((int64_t)1 << 31) || !row_ptr || (nnz > 0 && !col))
     return DIST_E_INVALID;
-  if (order_mode != DIST_ORDER_DEGREE && order_mode != DIST_ORDER_DEGENERACY) return DIST_E_INVALID;
+  if (order_mode != DIST_ORDER_DEGREE && order_mode != DIST_ORDER_DEGENERACY && order_mode != DIST_ORDER_INPUT)
+    return DIST_E_INVALID;
   hipStream_t s = (hipStream_t)hip_stream;
   dist_graph* g = new (std::nothrow) dist_graph();
   if (!g) return DIST_E_NOMEM;
@@ -166,7 +167,31 @@ int dist_count_noalloc(const dist_graph* g, int k, const dist_config* cfg, void*
 int dist_list(const dist_graph* g, int k, dist_sink sink, void* user, void* hip_stream, dist_result* out) {
   if (!g || !out || !sink) return DIST_E_INVALID;
   if (!valid_k(k)) return DIST_E_K;
-  return search_list(g, k, g->cfg, sink, user, (hipStream_t)hip_stream, out);
+  dist_stats st{};
+  int rc = search_list(g, k, g->cfg, sink, user, 0, (hipStream_t)hip_stream, out, &st);
+  g->stats = st;
+  return rc;
+}
+
+int dist_list_ex(const dist_graph* g, int k, const dist_config* cfg, int flags, dist_sink sink, void* user,
+                 void* hip_stream, dist_result* out) {
+  if (!g || !out || !sink) return DIST_E_INVALID;
+  if (!valid_k(k)) return DIST_E_K;
+  dist_stats st{};
+  int rc = search_list(g, k, cfg ? *cfg : g->cfg, sink, user, flags, (hipStream_t)hip_stream, out, &st);
+  g->stats = st;
+  return rc;
+}
+
+int dist_ist_inspect(const dist_graph* g, int k, int32_t root, const dist_config* cfg, const uint64_t* ret_set,
+                     int ret_l, int32_t cap, int32_t* local_ids, int32_t* d, uint64_t* sets, uint64_t* marked,
+                     uint32_t* lc, uint32_t* ls, int32_t* n_nodes, int32_t* rows, int64_t rows_cap,
+                     int64_t* n_rows, int64_t* n_ret, void* hip_stream) {
+  if (!g || !local_ids || !d || !sets || !marked || !lc || !ls || !n_nodes || !n_rows || !n_ret)
+    return DIST_E_INVALID;
+  if (!valid_k(k)) return DIST_E_K;
+  return search_ist_inspect(g, k, root, cfg ? *cfg : g->cfg, ret_set, ret_l, cap, local_ids, d, sets, marked, lc, ls,
+                            n_nodes, rows, rows_cap, n_rows, n_ret, (hipStream_t)hip_stream);
 }
 
 int dist_count_batch_ex(const dist_graph* const* gs, const int* ks, int n, const dist_config* cfg, int use_graph,

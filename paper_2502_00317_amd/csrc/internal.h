@@ -65,9 +65,13 @@ double estimate_cost(const dist_graph* g, int k);
 
 void batch_forget(const dist_graph* g);  // drop a cached batch plan that uses g
 
-// ---- listing -----------------------------------------------------------
-int search_list(const dist_graph* g, int k, const dist_config& cfg,
-                dist_sink sink, void* user, hipStream_t s, dist_result* out);
+// ---- listing (the Induced Subgraph Trie: ist.hip) -------------------------
+int search_list(const dist_graph* g, int k, const dist_config& cfg, dist_sink sink, void* user, int flags,
+                hipStream_t s, dist_result* out, dist_stats* st = nullptr);
+int search_ist_inspect(const dist_graph* g, int k, int32_t root_id, const dist_config& cfg, const uint64_t* ret_set,
+                       int ret_l, int32_t cap, int32_t* local_ids, int32_t* d_out, uint64_t* sets, uint64_t* marked,
+                       uint32_t* lc, uint32_t* ls, int32_t* n_nodes, int32_t* rows, int64_t rows_cap,
+                       int64_t* n_rows, int64_t* n_ret, hipStream_t s);
 
 // ---- memory: block cache (frees never wait for the device) ---------------
 int dev_alloc(void** p, size_t bytes);   // device memory of the current device

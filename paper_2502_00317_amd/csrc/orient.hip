@@ -557,6 +557,9 @@ int orient_build(const int32_t* rp, const int32_t* col, int32_t n, int64_t nnz, 
   if (order_mode == DIST_ORDER_DEGREE) {
     hipLaunchKernelGGL(k_degree_keys, dim3(gridn), dim3(T), 0, s, rp, n, key);
     g->order_bound = 0;
+  } else if (order_mode == DIST_ORDER_INPUT) {
+    hipLaunchKernelGGL(k_iota, dim3(gridn), dim3(T), 0, s, (int32_t*)key, n);  // key = id
+    g->order_bound = 0;
   } else {
     int32_t *degc, *round_of, *fa, *fb, *cnts;
     TRY(sc.get(&degc, nn));
@@ -639,7 +642,7 @@ int orient_build(const int32_t* rp, const int32_t* col, int32_t n, int64_t nnz, 
   DIST_CHECK(hipMemcpyAsync(hflags, dmax, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   DIST_CHECK(hipStreamSynchronize(s));
   g->max_outdeg = hflags[0];
-  if (order_mode == DIST_ORDER_DEGREE) g->order_bound = g->max_outdeg;
+  if (order_mode != DIST_ORDER_DEGENERACY) g->order_bound = g->max_outdeg;
   hipLaunchKernelGGL(k_root_keys, dim3(gridn), dim3(T), 0, s, outdeg, n, g->max_outdeg, key);
   hipLaunchKernelGGL(k_iota, dim3(gridn), dim3(T), 0, s, g->roots, n);
   TRY(radix_sort(key, g->roots, ktmp, vtmp, counts, n, bits_for((uint32_t)g->max_outdeg), s));

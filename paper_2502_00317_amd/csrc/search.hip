@@ -38,6 +38,7 @@
 // Every quantity is an integer; the result is exact (u128 count, fp mod
 // 2^61 - 1) and independent of scheduling.
 #include "device_common.h"
+#include "ist.h"
 
 #include <string.h>
 
@@ -2160,8 +2161,14 @@ int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out, hipStre
 // ---- listing driver ------------------------------------------------------------
 namespace {
 
-constexpr size_t kListBufBytes = (size_t)512 << 20;    // device record buffer
+u64 addp_host(u64 a, u64 b) {
+  const u64 t = a + b;
+  return t >= DIST_P61 ? t - DIST_P61 : t;
+}
+
+constexpr size_t kListBufBytes = (size_t)512 << 20;    // device record buffer (default)
 constexpr size_t kListStageBytes = (size_t)64 << 20;   // pinned host staging
+constexpr uint32_t kTrieNodes = 1u << 15;               // trie nodes per wave (default)
 
 __global__ void k_gather_counts(const u64* per_root, const int32_t* orig, const int32_t* roots, int32_t nroots,
                                 u64* out, int* wide) {
@@ -2172,32 +2179,6 @@ __global__ void k_gather_counts(const u64* per_root, const int32_t* orig, const 
     out[i] = o[0];
     if (o[1]) atomicOr(wide, 1);
   }
-}
-
-template <int W>
-int launch_list(Params prm, int grid, size_t lds, hipStream_t s) {
-  if (prm.fingerprint) {
-    DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((k_search<W, true, true>), dim3(grid), dim3(64), lds, s, prm);
-  } else {
-    DIST_CHECK(hipFuncSetAttribute((const void*)k_search<W, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((k_search<W, true, false>), dim3(grid), dim3(64), lds, s, prm);
-  }
-  DIST_CHECK(hipGetLastError());
-  return DIST_OK;
-}
-
-template <int W>
-int occupancy_list(size_t lds, bool fp) {
-  int nb = 0;
-  hipError_t e = fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, true, true>, 64, lds)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, true, false>, 64, lds);
-  if (e != hipSuccess) return 1;
-  return nb > 0 ? nb : 1;
-}
-
-size_t list_lds_bytes(int W, int k, int fp, int D) {
-  return lds_bytes(W, k, fp, D) + align8(4 * (size_t)D) + align8(4 * (size_t)(k + 1));
 }
 
 // Freed blocks are reused at once, so a buffer is released only after the
@@ -2225,25 +2206,93 @@ struct HostBuf {
   }
 };
 
+u64 g_ist_epoch = 1;  // trie epochs: unique over the life of the process
+
+// Clears the hash slots of every wave's trie region (blocks = waves), so no
+// stale word of reused memory can pass for a slot of a live epoch.
+__global__ void k_zero_trie_hash(char* base, u64 stride, u64 hash_off, u64 hslots) {
+  u64* h = (u64*)(base + (u64)blockIdx.x * stride + hash_off);
+  for (u64 i = threadIdx.x; i < hslots; i += blockDim.x) h[i] = 0;
+}
+
+// Largest listing grid: the per-wave output words of the workspace.
+constexpr int kListMaxWaves = 2048;
+
 }  // namespace
 
-int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink sink, void* user, hipStream_t s,
-                dist_result* out) {
+// One launch of the trie listing kernel over roots [b0, b1) of g with their
+// record offsets and counts (device arrays indexed from b0); see ist.hip.
+// With inspect, one root and one retrieval (ret_*) and the wave's totals in
+// wave_host.
+static int list_launch(const dist_graph* g, int k, const dist_config& cfg, int W, int drows, int32_t b0, int32_t b1,
+                       const u64* d_off, const u64* d_cnt, int32_t* d_out, int grid, char* trie, u64 stride,
+                       uint32_t node_cap, u64 hslots, size_t lds, hipStream_t s, u64* wave_host, int* err_host,
+                       const IstParams* extra) {
+  IstParams prm{};
+  if (extra) prm = *extra;
+  prm.dptr = g->dptr;
+  prm.dcol = g->dcol;
+  prm.orig = g->orig;
+  prm.roots = g->roots;
+  prm.gw = g->gw;
+  prm.k = k;
+  prm.prune = cfg.prune;
+  prm.memo = cfg.memo;
+  prm.fingerprint = cfg.fingerprint;
+  prm.root_begin = b0;
+  prm.nroots = b1 - b0;
+  prm.cursor = g_ws.cursor;
+  prm.rec_off = d_off;
+  prm.rec_cnt = d_cnt;
+  prm.out = d_out;
+  prm.drows = drows;
+  prm.trie = trie;
+  prm.trie_stride = stride;
+  prm.node_cap = node_cap;
+  prm.hmask = hslots - 1;
+  prm.epoch_base = g_ist_epoch;
+  g_ist_epoch += (u64)(b1 - b0) + 1;
+  prm.wave_out = g_ws.wave_out;
+  prm.err = g_ws.abort_flag;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, g_ws.cursor, 64);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)g_ws.abort_flag, 16);
+  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grid * kOutWords);
+  int rc = ist_list_launch(W, prm, grid, lds, s);
+  if (rc) return rc;
+  DIST_CHECK(hipMemcpyAsync(wave_host, g_ws.wave_out, (size_t)grid * kOutWords * sizeof(u64), hipMemcpyDeviceToHost,
+                            s));
+  DIST_CHECK(hipMemcpyAsync(err_host, g_ws.abort_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipStreamSynchronize(s));
+  return DIST_OK;
+}
+
+int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink sink, void* user, int flags,
+                hipStream_t s, dist_result* out, dist_stats* st_out) {
   std::lock_guard<std::recursive_mutex> lock(g_ws_mu);
   dist_result res{0, 0, 0};
   dist_config cfg = cfg_in;
+  dist_stats st{};
   *out = res;
+  const bool dev_rows = (flags & DIST_LIST_DEVICE_ROWS) != 0;
   if (k == 1) {
     // every vertex is a 1-clique
     SearchLaunch L{g, 1, cfg, nullptr, s};
-    dist_stats st{};
-    int rc = search_count(L, &res, &st);
+    dist_stats st1{};
+    int rc = search_count(L, &res, &st1);
     if (rc) return rc;
     std::vector<int32_t> ids(1 << 20);
+    DevBuf dids(s);
+    if (dev_rows && dev_alloc(&dids.p, sizeof(int32_t) * ids.size())) return DIST_E_NOMEM;
     for (int32_t a = 0; a < g->n; a += (int32_t)ids.size()) {
       int32_t c = g->n - a < (int32_t)ids.size() ? g->n - a : (int32_t)ids.size();
       for (int32_t i = 0; i < c; ++i) ids[i] = a + i;
-      if (sink(ids.data(), (uint64_t)c, 1, user)) {
+      const int32_t* rows = ids.data();
+      if (dev_rows) {
+        DIST_CHECK(hipMemcpyAsync(dids.p, ids.data(), sizeof(int32_t) * c, hipMemcpyHostToDevice, s));
+        DIST_CHECK(hipStreamSynchronize(s));
+        rows = (const int32_t*)dids.p;
+      }
+      if (sink(rows, (uint64_t)c, 1, user)) {
         *out = res;
         return DIST_E_CANCELLED;
       }
@@ -2259,22 +2308,27 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
   const int32_t nroots = lo;
   if (nroots == 0) {
     *out = res;
+    if (st_out) *st_out = st;
     return DIST_OK;
   }
   if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
   // 1. per-root clique counts (count kernel), gathered in root order
-  DevBuf per(s), cnts(s), wide(s);
+  DevBuf per(s), cnts(s), offs(s), wide(s);
   if (dev_alloc(&per.p, sizeof(u64) * 3 * ((size_t)g->n + 1))) return DIST_E_NOMEM;
   if (dev_alloc(&cnts.p, sizeof(u64) * (size_t)nroots)) return DIST_E_NOMEM;
+  if (dev_alloc(&offs.p, sizeof(u64) * (size_t)nroots)) return DIST_E_NOMEM;
   if (dev_alloc(&wide.p, 64)) return DIST_E_NOMEM;
   {
-    SearchLaunch L{g, k, cfg, (u64*)per.p, s};
+    dist_config cc = cfg;
+    cc.fingerprint = 0;
+    cc.deadline_ms = 0;
+    SearchLaunch L{g, k, cc, (u64*)per.p, s};
     dist_result tmp;
-    dist_stats st{};
-    int rc = search_count(L, &tmp, &st);
+    dist_stats st1{};
+    int rc = search_count(L, &tmp, &st1);
     if (rc != DIST_OK && rc != DIST_E_OVERFLOW) return rc;
   }
-  DIST_CHECK(hipMemsetAsync(wide.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)wide.p, 16);
   hipLaunchKernelGGL(k_gather_counts, dim3(256), dim3(256), 0, s, (const u64*)per.p, g->orig, g->roots, nroots,
                      (u64*)cnts.p, (int*)wide.p);
   std::vector<u64> rc_host(nroots);
@@ -2286,129 +2340,227 @@ int search_list(const dist_graph* g, int k, const dist_config& cfg_in, dist_sink
   const u64 rec_bytes = 4ull * (u64)k;
   u64 total = 0;
   for (u64 c : rc_host) total += c;
-  u64 cap = kListBufBytes / rec_bytes;
+  const size_t buf_bytes = cfg.list_bytes > 0 ? (size_t)cfg.list_bytes : kListBufBytes;
+  u64 cap = buf_bytes / rec_bytes;
+  if (cap == 0) return DIST_E_UNSUPPORTED;
   for (u64 c : rc_host)
     if (c > cap) return DIST_E_UNSUPPORTED;  // one root's output exceeds the buffer
   if (total < cap) cap = total > 0 ? total : 1;
-  // 2. buffers
-  DevBuf obuf(s), ocur(s);
+  // 2. buffers: records, host staging, per-wave tries
+  DevBuf obuf(s), trie(s);
   HostBuf stage(s);
   if (dev_alloc(&obuf.p, cap * rec_bytes)) return DIST_E_NOMEM;
-  if (dev_alloc(&ocur.p, 64)) return DIST_E_NOMEM;
-  size_t stage_bytes = cap * rec_bytes < kListStageBytes ? cap * rec_bytes : kListStageBytes;
-  stage_bytes = stage_bytes / rec_bytes * rec_bytes;
-  if (stage_bytes == 0) stage_bytes = rec_bytes;
-  if (pinned_alloc(&stage.p, stage_bytes) != DIST_OK) return DIST_E_NOMEM;
+  size_t stage_bytes = 0;
+  if (!dev_rows) {
+    stage_bytes = cap * rec_bytes < kListStageBytes ? cap * rec_bytes : kListStageBytes;
+    stage_bytes = stage_bytes / rec_bytes * rec_bytes;
+    if (stage_bytes == 0) stage_bytes = rec_bytes;
+    if (pinned_alloc(&stage.p, stage_bytes) != DIST_OK) return DIST_E_NOMEM;
+  }
   std::vector<Bucket> buckets = make_buckets(g, nroots);
-  int rc = ws_ensure(16 * kOutWords, 0);
-  if (rc) return rc;
   int maxlds = 0;
+  DIST_CHECK(hipGetDevice(&g_ws.device));
   DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, g_ws.device));
+  int cus = 0;
+  DIST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g_ws.device));
+  const bool use_trie = cfg.memo != 0;
+  uint32_t node_cap = cfg.trie_nodes > 0 ? (uint32_t)std::min<int64_t>(cfg.trie_nodes, (1 << 24) - 1) : kTrieNodes;
+  if (!use_trie) node_cap = 1;
+  u64 hslots = 1;
+  while (hslots < 2ull * node_cap) hslots <<= 1;
+  // grids and the trie region (the largest any bucket needs)
+  std::vector<int> grids(buckets.size());
+  size_t trie_bytes = 0;
+  for (size_t b = 0; b < buckets.size(); ++b) {
+    const size_t lds = ist_lds_bytes(buckets[b].W, k, cfg.fingerprint, buckets[b].D);
+    if (lds > (size_t)maxlds) return DIST_E_UNSUPPORTED;
+    int64_t grid = (int64_t)ist_occupancy(buckets[b].W, lds) * cus;
+    if (grid > kListMaxWaves) grid = kListMaxWaves;
+    if (grid > buckets[b].end - buckets[b].begin) grid = buckets[b].end - buckets[b].begin;
+    if (grid < 1) grid = 1;
+    grids[b] = (int)grid;
+    const IstLayout L = ist_layout(buckets[b].W, k, node_cap, hslots, buckets[b].D);
+    trie_bytes = std::max(trie_bytes, (size_t)grid * L.total);
+  }
+  if (dev_alloc(&trie.p, trie_bytes)) return DIST_E_NOMEM;
+  int rc = ws_ensure(kListMaxWaves * kOutWords, 0);
+  if (rc) return rc;
+  std::vector<u64> offs_h(nroots);
   u64 tot_lo = 0, tot_hi = 0, tot_fp = 0;
   bool cancelled = false;
-  for (auto& bk : buckets) {
+  for (size_t bi = 0; bi < buckets.size() && !cancelled; ++bi) {
+    const Bucket& bk = buckets[bi];
     const int W = bk.W;
-    const size_t lds = list_lds_bytes(W, k, cfg.fingerprint, bk.D);
-    if (lds > (size_t)maxlds) return DIST_E_UNSUPPORTED;
-    int occ = 1;
-    occ = with_width(W, [&](auto w) { return occupancy_list<decltype(w)::value>(lds, cfg.fingerprint != 0); });
-    const int cus = g_ws.cus > 0 ? g_ws.cus : 256;
+    const size_t lds = ist_lds_bytes(W, k, cfg.fingerprint, bk.D);
+    const IstLayout L = ist_layout(W, k, node_cap, hslots, bk.D);
     int32_t b0 = bk.begin;
     while (b0 < bk.end && !cancelled) {
-      // batch [b0, b1): total records within the buffer
+      // batch [b0, b1): records within the buffer, each root at its offset
       u64 sum = 0;
       int32_t b1 = b0;
-      while (b1 < bk.end && sum + rc_host[b1] <= cap) sum += rc_host[b1++];
-      int64_t grid = (int64_t)occ * cus;
-      if (grid > b1 - b0) grid = b1 - b0;
-      if (grid < 1) grid = 1;
-      rc = ws_ensure((size_t)grid * kOutWords, 0);
-      if (rc) return rc;
-      rc = ws_plan(sizeof(BatchGraph) + 2 * sizeof(BatchSeg));
-      if (rc) return rc;
-      {
-        BatchGraph bgh{g->dptr, g->dcol, g->orig, g->roots, g->gw, k, 0};
-        BatchSeg sg{0u, 0, b0, 1, (uint32_t)(b1 - b0), 1};
-        memcpy(g_ws.h_plan, &bgh, sizeof(bgh));
-        memcpy(g_ws.h_plan + sizeof(BatchGraph), &sg, sizeof(sg));
-        DIST_CHECK(hipMemcpyAsync(g_ws.d_plan, g_ws.h_plan, sizeof(BatchGraph) + sizeof(BatchSeg),
-                                  hipMemcpyHostToDevice, s));
+      while (b1 < bk.end && sum + rc_host[b1] <= cap) {
+        offs_h[b1] = sum;
+        sum += rc_host[b1++];
       }
-      Params prm{};
-      prm.bg = (const BatchGraph*)g_ws.d_plan;
-      prm.segs = (const BatchSeg*)(g_ws.d_plan + sizeof(BatchGraph));
-      prm.nsegs = 1;
-      prm.pair_out = nullptr;
-      prm.k = k;
-      prm.drows = bk.D;
-      prm.prune = cfg.prune;
-      prm.memo = 0;
-      prm.fingerprint = cfg.fingerprint;
-      prm.soft_only = 0;
-      prm.cursor = g_ws.cursor;
-      prm.root_deg = g->d_root_deg;
-      prm.units = (uint32_t)(b1 - b0);
-      prm.chunk_work = 1 << 30;
-      prm.wave_out = g_ws.wave_out;
-      prm.per_root = nullptr;
-      prm.memo_base = nullptr;
-      prm.memo_mask = 0;
-      prm.tag_base = 0;
-      prm.deadline = 0;
-      prm.abort_flag = g_ws.abort_flag;
-      prm.out = (int32_t*)obuf.p;
-      prm.out_cap = cap;
-      prm.out_cursor = (unsigned long long*)ocur.p;
-      prm.out_overflow = (int*)((char*)ocur.p + 8);
-      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, g_ws.cursor, 64);
-      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)g_ws.abort_flag, 16);
-      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)ocur.p, 16);
-      hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grid * kOutWords);
-      rc = with_width(W, [&](auto w) { return launch_list<decltype(w)::value>(prm, (int)grid, lds, s); });
+      DIST_CHECK(hipMemcpyAsync((u64*)offs.p + b0, offs_h.data() + b0, sizeof(u64) * (size_t)(b1 - b0),
+                                hipMemcpyHostToDevice, s));
+      const int grid = std::min<int>(grids[bi], b1 - b0);
+      if (use_trie)
+        hipLaunchKernelGGL(k_zero_trie_hash, dim3(grid), dim3(256), 0, s, (char*)trie.p, (u64)L.total, (u64)L.hash,
+                           hslots);
+      std::vector<u64> wh((size_t)grid * kOutWords);
+      int err = 0;
+      rc = list_launch(g, k, cfg, W, bk.D, b0, b1, (const u64*)offs.p + b0, (const u64*)cnts.p + b0,
+                       (int32_t*)obuf.p, grid, (char*)trie.p, L.total, node_cap, hslots, lds, s, wh.data(), &err,
+                       nullptr);
       if (rc) return rc;
-      u64 hc[2] = {0, 0};
-      DIST_CHECK(hipMemcpyAsync(hc, ocur.p, 16, hipMemcpyDeviceToHost, s));
-      DIST_CHECK(hipMemcpyAsync(g_ws.host_out, g_ws.wave_out, (size_t)grid * kOutWords * sizeof(u64),
-                                hipMemcpyDeviceToHost, s));
-      DIST_CHECK(hipStreamSynchronize(s));
-      if ((hc[1] & 0xffffffffull) != 0 || hc[0] != sum) return DIST_E_DEVICE;  // slots disagree with the counts
-      u64 b_lo = 0, b_hi = 0, b_fp = 0;
+      if (err) return DIST_E_DEVICE;  // records disagree with the counts
+      u64 b_cnt = 0, b_fp = 0;
       for (int w = 0; w < grid; ++w) {
-        const u64* o = g_ws.host_out + (size_t)w * kOutWords;
-        u64 nl = b_lo + o[0];
-        b_hi += o[1] + (nl < b_lo ? 1 : 0);
-        b_lo = nl;
-        u64 f = b_fp + o[2];
-        b_fp = f >= DIST_P61 ? f - DIST_P61 : f;
+        const u64* o = wh.data() + (size_t)w * kOutWords;
+        b_cnt += o[0];
+        b_fp = addp_host(b_fp, o[2]);
+        st.roots += o[3];
+        st.roots_pruned += o[4];
+        st.frames += o[5];
+        st.memo_inserts += o[7];   // trie nodes created
+        st.memo_lookups += o[6];   // ListingDense frames
+        st.memo_hits += o[9];      // retrievals from l-memoised nodes
+        st.leaf_bits += o[10];     // cliques delivered by retrieval
       }
-      // 3. hand the records to the sink in staging-sized pieces
-      const u64 per_stage = stage_bytes / rec_bytes;
-      for (u64 a = 0; a < hc[0]; a += per_stage) {
-        u64 c = hc[0] - a < per_stage ? hc[0] - a : per_stage;
-        DIST_CHECK(hipMemcpyAsync(stage.p, (char*)obuf.p + a * rec_bytes, c * rec_bytes, hipMemcpyDeviceToHost, s));
-        DIST_CHECK(hipStreamSynchronize(s));
-        if (sink((const int32_t*)stage.p, c, k, user)) {
-          cancelled = true;
-          break;
+      if (b_cnt != sum) return DIST_E_DEVICE;
+      // 3. hand the records to the sink
+      if (dev_rows) {
+        if (sum && sink((const int32_t*)obuf.p, sum, k, user)) cancelled = true;
+      } else {
+        const u64 per_stage = stage_bytes / rec_bytes;
+        for (u64 a = 0; a < sum; a += per_stage) {
+          u64 c = sum - a < per_stage ? sum - a : per_stage;
+          DIST_CHECK(hipMemcpyAsync(stage.p, (char*)obuf.p + a * rec_bytes, c * rec_bytes, hipMemcpyDeviceToHost,
+                                    s));
+          DIST_CHECK(hipStreamSynchronize(s));
+          if (sink((const int32_t*)stage.p, c, k, user)) {
+            cancelled = true;
+            break;
+          }
         }
       }
       if (!cancelled) {
-        u64 nl = tot_lo + b_lo;
-        tot_hi += b_hi + (nl < tot_lo ? 1 : 0);
+        u64 nl = tot_lo + b_cnt;
+        tot_hi += (nl < tot_lo ? 1 : 0);
         tot_lo = nl;
-        u64 f = tot_fp + b_fp;
-        tot_fp = f >= DIST_P61 ? f - DIST_P61 : f;
+        tot_fp = addp_host(tot_fp, b_fp);
       }
       b0 = b1;
     }
-    if (cancelled) break;
   }
   res.count_lo = tot_lo;
   res.count_hi = tot_hi;
   res.fp = cfg.fingerprint ? tot_fp : 0;
   *out = res;
+  if (st_out) *st_out = st;
   if (cancelled) return DIST_E_CANCELLED;
   return res.count_hi ? DIST_E_OVERFLOW : DIST_OK;
+}
+
+// The trie of one root (inspection; see dist_ist_inspect).
+int search_ist_inspect(const dist_graph* g, int k, int32_t root_id, const dist_config& cfg, const uint64_t* ret_set,
+                       int ret_l, int32_t cap, int32_t* local_ids, int32_t* d_out, uint64_t* sets, uint64_t* marked,
+                       uint32_t* lc, uint32_t* ls, int32_t* n_nodes, int32_t* rows, int64_t rows_cap,
+                       int64_t* n_rows, int64_t* n_ret, hipStream_t s) {
+  std::lock_guard<std::recursive_mutex> lock(g_ws_mu);
+  if (root_id < 0 || root_id >= g->n || k < 3 || cap < 1) return DIST_E_INVALID;
+  if (ret_set && ret_l != k - 1) return DIST_E_INVALID;  // retrieved records are k-cliques
+  // the root's rank, out-degree and clique count
+  int32_t r = 0;
+  DIST_CHECK(hipMemcpy(&r, g->rank + root_id, sizeof(int32_t), hipMemcpyDeviceToHost));
+  int32_t pr[2];
+  DIST_CHECK(hipMemcpy(pr, g->dptr + r, 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+  const int d = pr[1] - pr[0];
+  *d_out = d;
+  if (d > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
+  std::vector<int32_t> nb(d);
+  std::vector<int32_t> orig_all;
+  if (d) DIST_CHECK(hipMemcpy(nb.data(), g->dcol + pr[0], sizeof(int32_t) * d, hipMemcpyDeviceToHost));
+  for (int i = 0; i < d; ++i) DIST_CHECK(hipMemcpy(local_ids + i, g->orig + nb[i], sizeof(int32_t), hipMemcpyDeviceToHost));
+  DevBuf per(s), dr(s), doff(s), dcnt(s), obuf(s), trie(s);
+  if (dev_alloc(&per.p, sizeof(u64) * 3 * ((size_t)g->n + 1))) return DIST_E_NOMEM;
+  {
+    dist_config cc = cfg;
+    cc.fingerprint = 0;
+    SearchLaunch L{g, k, cc, (u64*)per.p, s};
+    dist_result tmp;
+    dist_stats st1{};
+    int rc = search_count(L, &tmp, &st1);
+    if (rc != DIST_OK && rc != DIST_E_OVERFLOW) return rc;
+  }
+  u64 rcnt[3];
+  DIST_CHECK(hipMemcpy(rcnt, (u64*)per.p + 3 * (size_t)root_id, sizeof(rcnt), hipMemcpyDeviceToHost));
+  if (rcnt[1]) return DIST_E_UNSUPPORTED;
+  // rows holds rows_cap records in all: the root's, then the retrieval's
+  if (rows && (rows_cap < 0 || (u64)rows_cap < rcnt[0])) return DIST_E_UNSUPPORTED;
+  const u64 ret_cap = rows ? (u64)rows_cap - rcnt[0] : 0;
+  const u64 total_rows = rcnt[0] + ret_cap;
+  if (dev_alloc(&dr.p, sizeof(int32_t) * 2)) return DIST_E_NOMEM;
+  if (dev_alloc(&doff.p, sizeof(u64))) return DIST_E_NOMEM;
+  if (dev_alloc(&dcnt.p, sizeof(u64))) return DIST_E_NOMEM;
+  if (dev_alloc(&obuf.p, 4ull * k * std::max<u64>(total_rows, 1))) return DIST_E_NOMEM;
+  const int W = width_of(d < 1 ? 1 : d);
+  const int D = lds_rows(W, d < 1 ? 1 : d);
+  const uint32_t node_cap = (uint32_t)cap + 1;
+  u64 hslots = 1;
+  while (hslots < 2ull * node_cap) hslots <<= 1;
+  const IstLayout L = ist_layout(W, k, node_cap, hslots, D);
+  if (dev_alloc(&trie.p, L.total)) return DIST_E_NOMEM;
+  hipLaunchKernelGGL(k_zero_trie_hash, dim3(1), dim3(256), 0, s, (char*)trie.p, (u64)L.total, (u64)L.hash, hslots);
+  const u64 zero = 0;
+  DIST_CHECK(hipMemcpy(dr.p, &r, sizeof(int32_t), hipMemcpyHostToDevice));
+  DIST_CHECK(hipMemcpy(doff.p, &zero, sizeof(u64), hipMemcpyHostToDevice));
+  DIST_CHECK(hipMemcpy(dcnt.p, &rcnt[0], sizeof(u64), hipMemcpyHostToDevice));
+  int rc = ws_ensure(16 * kOutWords, 0);
+  if (rc) return rc;
+  IstParams extra{};
+  extra.inspect = 1;
+  extra.ret_l = ret_l;
+  for (int w = 0; w < 16; ++w) extra.ret_key[w] = ret_set ? ret_set[w] : 0;
+  extra.ret_off = rcnt[0];
+  extra.ret_cap = ret_cap;
+  // a plan whose roots array is the single root
+  dist_graph one = *g;
+  one.roots = (int32_t*)dr.p;
+  u64 wh[kOutWords];
+  int err = 0;
+  const size_t lds = ist_lds_bytes(W, k, cfg.fingerprint, D);
+  rc = list_launch(&one, k, cfg, W, D, 0, 1, (const u64*)doff.p, (const u64*)dcnt.p, (int32_t*)obuf.p, 1,
+                   (char*)trie.p, L.total, node_cap, hslots, lds, s, wh, &err, &extra);
+  if (rc) return rc;
+  if (err || wh[14]) return DIST_E_DEVICE;
+  const u64 nn = wh[11];
+  *n_nodes = (int32_t)nn;
+  *n_rows = (int64_t)rcnt[0];
+  *n_ret = (int64_t)wh[13];
+  if (nn > (u64)cap + 1) return DIST_E_UNSUPPORTED;
+  std::vector<u64> keys(nn * W), mk(nn);
+  std::vector<uint32_t> lcv(nn * k), lsv(nn * k);
+  char* base = (char*)trie.p;
+  DIST_CHECK(hipMemcpy(keys.data(), base + L.keys, sizeof(u64) * nn * W, hipMemcpyDeviceToHost));
+  DIST_CHECK(hipMemcpy(mk.data(), base + L.marked, sizeof(u64) * nn, hipMemcpyDeviceToHost));
+  DIST_CHECK(hipMemcpy(lcv.data(), base + L.lc, sizeof(uint32_t) * nn * k, hipMemcpyDeviceToHost));
+  DIST_CHECK(hipMemcpy(lsv.data(), base + L.ls, sizeof(uint32_t) * nn * k, hipMemcpyDeviceToHost));
+  for (u64 t = 0; t < nn; ++t) {
+    for (int w = 0; w < 16; ++w) sets[t * 16 + w] = (t > 0 && w < W) ? keys[t * W + w] : 0;
+    marked[t] = t > 0 ? mk[t] : ~0ull;
+    for (int l = 0; l < k; ++l) {
+      lc[t * k + l] = t > 0 ? lcv[t * k + l] : 0;
+      ls[t * k + l] = t > 0 ? lsv[t * k + l] : 0;
+    }
+  }
+  if (rows) {
+    const u64 nr = rcnt[0] + wh[13];
+    if (nr > (u64)rows_cap) return DIST_E_UNSUPPORTED;
+    DIST_CHECK(hipMemcpy(rows, obuf.p, 4ull * k * nr, hipMemcpyDeviceToHost));
+  }
+  return DIST_OK;
 }
 
 // ---- batched counting ----------------------------------------------------------

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libdist.so")
 OK, E_INVALID, E_K, E_NOMEM, E_DEVICE, E_OVERFLOW, E_CANCELLED, E_UNSUPPORTED, E_SCRATCH = range(9)
 WIDTHS = (1, 2, 3, 4, 5, 6, 8, 16)   # DIST_WIDTHS: bitmap width classes (words)
 WIDTH_CLASSES = len(WIDTHS)
-ORDER_DEGREE, ORDER_DEGENERACY = 0, 1
+ORDER_DEGREE, ORDER_DEGENERACY, ORDER_INPUT = 0, 1, 2
 K_MAX = 64
 P61 = (1 << 61) - 1
 
@@ -38,7 +38,8 @@ class Config(ctypes.Structure):
                 ("memo_bytes", ctypes.c_int64), ("deadline_ms", ctypes.c_int64),
                 ("chunk_work", ctypes.c_int32), ("grid_pct", ctypes.c_int32),
                 ("budget_from_pair_start", ctypes.c_int32), ("min_width", ctypes.c_int32),
-                ("sub_units", ctypes.c_int32)]
+                ("sub_units", ctypes.c_int32), ("trie_nodes", ctypes.c_int32),
+                ("list_bytes", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):
@@ -109,6 +110,14 @@ def _load():
     lib.dist_count_noalloc.restype = ctypes.c_int
     lib.dist_list.argtypes = [vp, ctypes.c_int, SINK, vp, vp, ctypes.POINTER(Result)]
     lib.dist_list.restype = ctypes.c_int
+    lib.dist_list_ex.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Config), ctypes.c_int, SINK, vp, vp,
+                                 ctypes.POINTER(Result)]
+    lib.dist_list_ex.restype = ctypes.c_int
+    lib.dist_ist_inspect.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(Config), vp, ctypes.c_int,
+                                     ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32), vp, vp, vp, vp,
+                                     ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), vp]
+    lib.dist_ist_inspect.restype = ctypes.c_int
     lib.dist_count_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
                                      ctypes.c_int, vp, ctypes.POINTER(Result)]
     lib.dist_count_batch.restype = ctypes.c_int
@@ -348,13 +357,21 @@ def estimate_cost(g: Graph, k: int) -> float:
     return v.value
 
 
-def list_cliques(g: Graph, k: int, sink=None, stream=None):
-    """dist_list.  With sink=None returns (rows array (N, k) int32, count, fp,
-    status); otherwise calls sink(np.ndarray (n, k)) per chunk and returns
+LIST_DEVICE_ROWS = 1
+
+
+def list_cliques(g: Graph, k: int, sink=None, stream=None, cfg: Config | None = None, device_rows=False,
+                 raw_sink=None):
+    """dist_list / dist_list_ex.  With sink=None (and no raw_sink) returns
+    (rows array (N, k) int32, count, fp, status); otherwise calls
+    sink(np.ndarray (n, k)) per chunk, or raw_sink(ptr, n, k) with the
+    library's pointer (a device pointer with device_rows), and returns
     (None, count, fp, status)."""
     chunks = []
 
     def _cb(ptr, n, kk, user):
+        if raw_sink is not None:
+            return int(bool(raw_sink(ctypes.cast(ptr, ctypes.c_void_p).value, int(n), kk)))
         arr = np.ctypeslib.as_array(ptr, shape=(int(n) * kk,)).reshape(int(n), kk).copy()
         if sink is None:
             chunks.append(arr)
@@ -363,13 +380,60 @@ def list_cliques(g: Graph, k: int, sink=None, stream=None):
 
     cb = SINK(_cb)
     res = Result()
-    rc = _load().dist_list(g.handle, int(k), cb, None, _stream_ptr(stream), ctypes.byref(res))
+    if cfg is None and not device_rows:
+        rc = _load().dist_list(g.handle, int(k), cb, None, _stream_ptr(stream), ctypes.byref(res))
+    else:
+        rc = _load().dist_list_ex(g.handle, int(k), ctypes.byref(cfg) if cfg is not None else None,
+                                  LIST_DEVICE_ROWS if device_rows else 0, cb, None, _stream_ptr(stream),
+                                  ctypes.byref(res))
     if rc not in (OK, E_OVERFLOW, E_CANCELLED):
         _check(rc, "dist_list")
     rows = None
-    if sink is None:
+    if sink is None and raw_sink is None:
         rows = np.concatenate(chunks) if chunks else np.zeros((0, k), np.int32)
     return rows, res.count, int(res.fp), rc
+
+
+def ist_inspect(g: Graph, k: int, root: int, cfg: Config | None = None, ret_set=None, ret_l: int = 0,
+                cap: int = 1 << 14, rows_cap: int = 1 << 16, stream=None):
+    """dist_ist_inspect: the Induced Subgraph Trie built while listing the
+    k-cliques of one root, and one ListingIST retrieval.  Returns a dict with
+    local_ids, nodes (list of frozensets of input ids; node 0 the root),
+    marked (list of int bit masks), lc / ls (lists of per-l node ids), rows
+    (the root's cliques) and retrieved (the retrieval's cliques)."""
+    local = np.zeros(1024, np.int32)
+    d = ctypes.c_int32(0)
+    sets = np.zeros((cap + 1) * 16, np.uint64)
+    marked = np.zeros(cap + 1, np.uint64)
+    lc = np.zeros((cap + 1) * k, np.uint32)
+    ls = np.zeros((cap + 1) * k, np.uint32)
+    nn = ctypes.c_int32(0)
+    rows = np.zeros(max(rows_cap, 1) * k, np.int32)
+    nr = ctypes.c_int64(0)
+    nret = ctypes.c_int64(0)
+    rs = None
+    if ret_set is not None:
+        rs = np.zeros(16, np.uint64)
+        rs[: len(ret_set)] = np.asarray(ret_set, np.uint64)
+    rc = _load().dist_ist_inspect(
+        g.handle, int(k), int(root), ctypes.byref(cfg) if cfg is not None else None,
+        ctypes.c_void_p(rs.ctypes.data) if rs is not None else None, int(ret_l), int(cap),
+        ctypes.c_void_p(local.ctypes.data), ctypes.byref(d), ctypes.c_void_p(sets.ctypes.data),
+        ctypes.c_void_p(marked.ctypes.data), ctypes.c_void_p(lc.ctypes.data), ctypes.c_void_p(ls.ctypes.data),
+        ctypes.byref(nn), ctypes.c_void_p(rows.ctypes.data), int(rows_cap), ctypes.byref(nr), ctypes.byref(nret),
+        _stream_ptr(stream))
+    _check(rc, "dist_ist_inspect")
+    n = nn.value
+    ids = local[: d.value]
+    nodes = []
+    for t in range(n):
+        bits = sets[t * 16:(t + 1) * 16]
+        mem = [int(ids[w * 64 + b]) for w in range(16) for b in range(64) if (int(bits[w]) >> b) & 1]
+        nodes.append(frozenset(mem))
+    r = rows[: (nr.value + nret.value) * k].reshape(-1, k)
+    return {"local_ids": ids.copy(), "nodes": nodes, "marked": [int(m) for m in marked[:n]],
+            "lc": lc[: n * k].reshape(n, k).copy(), "ls": ls[: n * k].reshape(n, k).copy(),
+            "rows": r[: nr.value].copy(), "retrieved": r[nr.value:].copy()}
 
 
 def root_soft_embed(g: Graph, cap: int, stream=None) -> np.ndarray:

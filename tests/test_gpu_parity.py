@@ -37,7 +37,7 @@ def _gpu(D, g, k, order, **cfg):
 
 def test_fig2_all_k(D, oracle_mod):
     g = gg.fig2()
-    for order in (D.ORDER_DEGREE, D.ORDER_DEGENERACY):
+    for order in (D.ORDER_DEGREE, D.ORDER_DEGENERACY, D.ORDER_INPUT):
         for k in range(1, 8):
             want = oracle_mod.count(g.row_ptr, g.col, k)
             for cfg in CONFIGS:

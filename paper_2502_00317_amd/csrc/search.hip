@@ -36,7 +36,8 @@
 //      cnt(t, l) = cnt(L^C_t(l), l - 1) + cnt(L^S_t(l), l).
 //
 // Every quantity is an integer; the result is exact (u128 count, fp mod
-// 2^61 - 1) and independent of scheduling.
+// 2^61 - 1) and independent of scheduling.  Listing (records of cliques)
+// runs in ist.hip on the linked trie of Algorithms 3 and 4.
 #include "device_common.h"
 #include "ist.h"
 
@@ -101,10 +102,6 @@ struct Params {
   int soft_only;    // 1: only compute r_{G'}(u) (capped at k) into soft_out
   int32_t* soft_out;
   unsigned* cursor;
-  int32_t* out;              // listing: records of k input ids
-  u64 out_cap;               // records that fit in out
-  unsigned long long* out_cursor;
-  int* out_overflow;
   const int32_t* root_deg;   // out-degree of roots[i]
   const BatchGraph* bg;      // batch mode (null: one graph, the fields above)
   const BatchSeg* segs;
@@ -238,49 +235,6 @@ inline int units_per_root(int d, int k, int chunk_work) {
 
 // At most this many units share one range of depth-1 children (k >= 6).
 constexpr int kMaxSub = 32;
-
-// ---- listing: record slots and sorted records ----------------------------------
-
-// Wave-collective: reserve cnt record slots for every lane; returns the
-// lane's first slot, or ~0 if the batch would overflow the buffer (then
-// nothing is written and the host reports the error).
-__device__ u64 reserve_records(const Params& p, u64 cnt) {
-  const int lane = lane_id();
-  u64 incl = cnt;
-  for (int off = 1; off < kWave; off <<= 1) {
-    u64 o = __shfl_up(incl, off);
-    if (lane >= off) incl += o;
-  }
-  u64 total = __shfl(incl, kWave - 1);
-  u64 base = 0;
-  if (lane == 0 && total) base = atomicAdd(p.out_cursor, (unsigned long long)total);
-  base = __shfl(base, 0);
-  bool ok = base + total <= p.out_cap;
-  if (!ok && lane == 0 && total) atomicOr(p.out_overflow, 1);
-  return ok ? base + incl - cnt : ~0ull;
-}
-
-// Writes the clique pre[0..np) u {a, b, c}[0..nl) (pre sorted ascending,
-// leaf ids distinct from it) as one ascending record.
-__device__ __forceinline__ void write_record(int32_t* dst, const int32_t* pre, int np, int nl, int32_t a,
-                                             int32_t b, int32_t c) {
-  // slot of a value = #smaller prefix ids + #smaller leaf ids
-  int32_t lv[3] = {a, b, c};
-#pragma unroll
-  for (int t = 0; t < 3; ++t) {
-    if (t >= nl) break;
-    int32_t v = lv[t];
-    int pos = 0;
-    for (int q = 0; q < np; ++q) pos += pre[q] < v;
-    pos += (nl > 0 && a < v) + (nl > 1 && b < v) + (nl > 2 && c < v);
-    dst[pos] = v;
-  }
-  for (int q = 0; q < np; ++q) {
-    int32_t v = pre[q];
-    int pos = q + (nl > 0 && a < v) + (nl > 1 && b < v) + (nl > 2 && c < v);
-    dst[pos] = v;
-  }
-}
 
 // (hi * 2^64 + lo) mod p, p = 2^61 - 1 (2^64 = 8 mod p).
 __device__ __forceinline__ u64 fold_p(u64 hi, u64 lo) {
@@ -746,15 +700,12 @@ __device__ __forceinline__ void leaf3_count(const Lds& s, const u64 (&Pr)[W], in
 
 // Counting kernels of up to 6 words are held to 256 VGPRs, i.e. two waves per
 // SIMD (the register file holds 512 per lane): crossing it halves occupancy.
-template <int W, bool EMIT, bool FP>
-__global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params p) {
+template <int W, bool FP>
+__global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
   extern __shared__ __align__(16) char smem[];
   const int lane = lane_id();
   int k = p.k;  // batch mode: the largest k of the launch (sizes the stacks)
   const Lds s = carve<W>(smem, p.k, FP, p.drows);
-  // listing only: input ids of the local vertices and the sorted prefix
-  int32_t* const oid = EMIT ? (int32_t*)(smem + lds_bytes(W, p.k, FP, p.drows)) : nullptr;
-  int32_t* const pre = EMIT ? oid + p.drows : nullptr;
   const int ES = W + 4;
   u64* table = p.memo_base ? p.memo_base + (u64)blockIdx.x * (p.memo_mask + 1) * ES : nullptr;
 
@@ -862,7 +813,7 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
       d = Gdptr[r + 1] - beg;  // <= 64 * W by the host's bucketing
       ++n_builds;
       // ---- 1. G_u in LDS ------------------------------------------------------
-      arcs += build_subgraph<W>(s, Gdptr, Gdcol, Ggw, Gorig, oid, beg, d);
+      arcs += build_subgraph<W>(s, Gdptr, Gdcol, Ggw, Gorig, nullptr, beg, d);
       if (s.wtab) build_weight_table<W>(s, d);
 
       // ---- 2. soft-embedding bound (Algorithm 5) ---------------------------------
@@ -938,21 +889,6 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
           u64 c = 0;
 #pragma unroll
           for (int w = 0; w < W; ++w) c += __popcll(Pr[w]);
-          if constexpr (EMIT) {
-            // only at k = 2: records {root, x}
-            const int32_t rid = Gorig[r];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-              bool in = (Pr[w] >> lane) & 1ull;
-              u64 slot = reserve_records(p, in ? 1 : 0);
-              if (in && slot != ~0ull) {
-                int32_t xid = oid[w * 64 + lane];
-                int32_t* dst = p.out + slot * 2;
-                dst[0] = rid < xid ? rid : xid;
-                dst[1] = rid < xid ? xid : rid;
-              }
-            }
-          }
           u64 f = 0;
           if (FP) {
             u64 tmpb = 0;
@@ -996,25 +932,7 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
             mode = FINISH;
             continue;
           }
-          int npre = 0;
-          if constexpr (EMIT) {
-            // sorted input ids of the chosen vertices: root and stX[0..j)
-            npre = j + 1;
-            if (lane == 0) {
-              pre[0] = Gorig[r];
-              for (int t = 0; t < j; ++t) {
-                int32_t v = oid[s.stX[t]];
-                int q = t + 1;
-                while (q > 0 && pre[q - 1] > v) {
-                  pre[q] = pre[q - 1];
-                  --q;
-                }
-                pre[q] = v;
-              }
-            }
-            __syncthreads();
-          }
-          if (!EMIT && l == 3 && j > 0) {
+          if (l == 3 && j > 0) {
             // edges of G[P] first: a complete P needs no leaf search
             u64 m = 0;
             for (int i = lane; i < np; i += kWave) {
@@ -1067,7 +985,6 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
             if (j == 0 && (x < x_lo || x >= x_hi)) act = false;
             u64 q[W];
             int c = 0;
-            u64 mine = 0;
             if (act) {
 #pragma unroll
               for (int w = 0; w < W; ++w) {
@@ -1077,54 +994,12 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
               wops += W;
               if (l == 2) {
                 c_acc += (u64)c;
-                mine = (u64)c;
                 if (FP && c) f_acc = addp(f_acc, mulp(s.gl[x], weight_sum_any<W>(q, s.gl, s.wtab, bits)));
               } else if (c >= 2 && s.rcap[x] >= 3) {
                 u64 ec = 0, ef = 0;
                 edges_in<W>(q, s.A, s.gl, s.wtab, FP, ec, ef, wops, bits);
                 c_acc += ec;
-                mine = ec;
                 if (FP && ec) f_acc = addp(f_acc, mulp(s.gl[x], ef));
-              }
-            }
-            if constexpr (EMIT) {
-              u64 slot = reserve_records(p, mine);
-              if (mine && slot != ~0ull) {
-                int32_t* dst = p.out + slot * (u64)k;
-                const int32_t xid = oid[x];
-                if (l == 2) {
-#pragma unroll
-                  for (int w = 0; w < W; ++w) {
-                    u64 b = q[w];
-                    while (b) {
-                      int t = __ffsll((unsigned long long)b) - 1;
-                      b &= b - 1;
-                      write_record(dst, pre, npre, 2, xid, oid[w * 64 + t], 0);
-                      dst += k;
-                    }
-                  }
-                } else {
-#pragma unroll
-                  for (int w = 0; w < W; ++w) {
-                    u64 b = q[w];
-                    while (b) {
-                      int t = __ffsll((unsigned long long)b) - 1;
-                      b &= b - 1;
-                      int y = w * 64 + t;
-                      const int32_t yid = oid[y];
-#pragma unroll
-                      for (int v = 0; v < W; ++v) {
-                        u64 bz = q[v] & s.A[y * W + v];
-                        while (bz) {
-                          int tz = __ffsll((unsigned long long)bz) - 1;
-                          bz &= bz - 1;
-                          write_record(dst, pre, npre, 3, xid, yid, oid[v * 64 + tz]);
-                          dst += k;
-                        }
-                      }
-                    }
-                  }
-                }
               }
             }
           }
@@ -1154,7 +1029,7 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
           if (c >= l - 1 && s.rcap[x] >= l) atomicOr(&Q[x >> 6], 1ull << (x & 63));
         }
         m_edges = wave_sum(m_edges);
-        if (!EMIT && j > 0 && m_edges == (u64)np * (u64)(np - 1) / 2) {
+        if (j > 0 && m_edges == (u64)np * (u64)(np - 1) / 2) {
           u64 clo, chi;
           if (binom128(np, l, clo, chi)) {
             res_lo = clo;
@@ -1166,7 +1041,7 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
             continue;
           }
         }
-        if constexpr (!EMIT) {
+        {
           const u64 full = (u64)np * (u64)(np - 1) / 2;
           if (j > 0 && m_edges < full && full - m_edges <= (u64)kNearMissing) {
             const int e = missing_edges<W>(s, Pr, np, s.pos);
@@ -1259,7 +1134,7 @@ __global__ __launch_bounds__(64, (W <= 6 && !EMIT ? 2 : 1)) void k_search(Params
             Q[lane] = keep;
           }
         }
-        if constexpr (!EMIT) {
+        {
           if (l == 4) {
             // the children are leaf frames (l = 3): counted here, highest
             // first, without a frame push each.  The memo is used exactly as
@@ -1716,14 +1591,14 @@ void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, 
 // fingerprints runs a kernel without their registers.
 template <int W>
 const void* search_kernel(bool fp) {
-  return fp ? (const void*)k_search<W, false, true> : (const void*)k_search<W, false, false>;
+  return fp ? (const void*)k_search<W, true> : (const void*)k_search<W, false>;
 }
 
 template <int W>
 int occupancy_blocks(size_t lds, bool fp) {
   int nb = 0;
-  hipError_t e = fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, false, true>, 64, lds)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, false, false>, 64, lds);
+  hipError_t e = fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, true>, 64, lds)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_search<W, false>, 64, lds);
   if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
@@ -1734,9 +1609,9 @@ int launch_bucket(Params prm, int grid, size_t lds, hipStream_t s, bool set_attr
   if (set_attr)
     DIST_CHECK(hipFuncSetAttribute(search_kernel<W>(fp), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (fp)
-    hipLaunchKernelGGL((k_search<W, false, true>), dim3(grid), dim3(64), lds, s, prm);
+    hipLaunchKernelGGL((k_search<W, true>), dim3(grid), dim3(64), lds, s, prm);
   else
-    hipLaunchKernelGGL((k_search<W, false, false>), dim3(grid), dim3(64), lds, s, prm);
+    hipLaunchKernelGGL((k_search<W, false>), dim3(grid), dim3(64), lds, s, prm);
   DIST_CHECK(hipGetLastError());
   return DIST_OK;
 }

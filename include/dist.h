@@ -199,6 +199,27 @@ int dist_count(const dist_graph* g, int k, void* hip_stream, dist_result* out);
 int dist_count_ex(const dist_graph* g, int k, const dist_config* cfg,
                   uint64_t* per_root, void* hip_stream, dist_result* out);
 
+/* Every clique size at once, by pivoting (the exact pivot-based counter the
+ * paper cites among related work, Section II-B: Jain and Seshadhri, "The
+ * Power of Pivoting for Exact Clique Counting").  For each root u the
+ * cliques of G[N+(u)] are represented once each in a tree of (held, pivot)
+ * vertex sets; a leaf with held set H (u included) and pivot set Q holds,
+ * for every k, C(|Q|, k - |H|) k-cliques with fingerprint sum
+ * prod_{v in H} g(v) * e_{k-|H|}(g(Q)).  No clique is enumerated, so dense
+ * cores count in time near their tree size rather than their clique count.
+ * out[k] (host memory, kmax + 1 entries) receives the count and fp of the
+ * k-cliques for k = 0 .. kmax (out[0] = 0, out[1] = n, out[2] = |E|);
+ * 1 <= kmax <= DIST_ALL_K_MAX (so every C(|Q|, j) is exact in 128 bits).  per_root (optional, host or device, 3 * n
+ * words) receives, for k = per_root_k (2 .. kmax), each root's count and fp
+ * as in dist_count_ex.  cfg (NULL = the graph's): fingerprint and
+ * deadline_ms apply.  Returns DIST_OK, DIST_E_OVERFLOW (some count >= 2^64;
+ * results exact), DIST_E_CANCELLED (deadline; results partial), DIST_E_K,
+ * DIST_E_UNSUPPORTED, DIST_E_NOMEM or DIST_E_DEVICE. */
+#define DIST_ALL_K_MAX 16
+int dist_count_all(const dist_graph* g, int kmax, const dist_config* cfg,
+                   uint64_t* per_root, int per_root_k, void* hip_stream,
+                   dist_result* out);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): dist_count
  * that allocates nothing.  It calls no hipMalloc, hipFree, pinned-memory or

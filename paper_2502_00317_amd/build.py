@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdist.so")
-SOURCES = ["api.cpp", "memcache.cpp", "orient.hip", "search.hip", "ist.hip"]
+SOURCES = ["api.cpp", "memcache.cpp", "orient.hip", "search.hip", "ist.hip", "pivot.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -164,6 +164,35 @@ int dist_count_noalloc(const dist_graph* g, int k, const dist_config* cfg, void*
   return rc;
 }
 
+int dist_count_all(const dist_graph* g, int kmax, const dist_config* cfg, uint64_t* per_root, int per_root_k,
+                   void* hip_stream, dist_result* out) {
+  if (!g || !out) return DIST_E_INVALID;
+  if (kmax < 1 || kmax > DIST_ALL_K_MAX) return DIST_E_K;
+  if (per_root && (per_root_k < 2 || per_root_k > kmax)) return DIST_E_K;
+  hipStream_t s = (hipStream_t)hip_stream;
+  u64* own = nullptr;
+  u64* pr = nullptr;
+  const bool host_pr = per_root && !is_device_ptr(per_root);
+  if (per_root) {
+    if (host_pr) {
+      if (dev_alloc((void**)&own, sizeof(u64) * 3 * ((size_t)g->n + 1))) return DIST_E_NOMEM;
+      pr = own;
+    } else {
+      pr = (u64*)per_root;
+    }
+  }
+  dist_stats st{};
+  int rc = search_count_all(g, kmax, cfg ? *cfg : g->cfg, pr, per_root_k, s, out, &st);
+  g->stats = st;
+  if (host_pr) {
+    if (hipMemcpyAsync(per_root, own, sizeof(u64) * 3 * (size_t)g->n, hipMemcpyDeviceToHost, s) != hipSuccess)
+      rc = rc ? rc : DIST_E_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) rc = rc ? rc : DIST_E_DEVICE;
+    dev_free(own);
+  }
+  return rc;
+}
+
 int dist_list(const dist_graph* g, int k, dist_sink sink, void* user, void* hip_stream, dist_result* out) {
   if (!g || !out || !sink) return DIST_E_INVALID;
   if (!valid_k(k)) return DIST_E_K;

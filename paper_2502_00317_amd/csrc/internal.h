@@ -65,6 +65,10 @@ double estimate_cost(const dist_graph* g, int k);
 
 void batch_forget(const dist_graph* g);  // drop a cached batch plan that uses g
 
+// ---- every k at once, by pivoting (pivot.hip) ------------------------------
+int search_count_all(const dist_graph* g, int kmax, const dist_config& cfg, u64* per_root, int per_root_k,
+                     hipStream_t s, dist_result* out, dist_stats* st);
+
 // ---- listing (the Induced Subgraph Trie: ist.hip) -------------------------
 int search_list(const dist_graph* g, int k, const dist_config& cfg, dist_sink sink, void* user, int flags,
                 hipStream_t s, dist_result* out, dist_stats* st = nullptr);

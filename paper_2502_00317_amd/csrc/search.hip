@@ -40,6 +40,7 @@
 // runs in ist.hip on the linked trie of Algorithms 3 and 4.
 #include "device_common.h"
 #include "ist.h"
+#include "pivot.h"
 
 #include <string.h>
 
@@ -2436,6 +2437,156 @@ int search_ist_inspect(const dist_graph* g, int k, int32_t root_id, const dist_c
     DIST_CHECK(hipMemcpy(rows, obuf.p, 4ull * k * nr, hipMemcpyDeviceToHost));
   }
   return DIST_OK;
+}
+
+// ---- pivot-based counting, every k at once (pivot.hip) ---------------------------
+
+// The device address of the binomial table, filled first if needed.
+static int binom_table(const u64** out) {
+  if (int rc = ensure_binom()) return rc;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_binom)) != hipSuccess || !ptr) return DIST_E_DEVICE;
+  *out = (const u64*)ptr;
+  return DIST_OK;
+}
+
+int search_count_all(const dist_graph* g, int kmax, const dist_config& cfg, u64* per_root, int per_root_k,
+                     hipStream_t s, dist_result* out, dist_stats* st_out) {
+  std::lock_guard<std::recursive_mutex> lock(g_ws_mu);
+  constexpr int kPivWords = 256;   // per-wave output words of the pivot kernel
+  constexpr int kPivMaxWaves = 2048;
+  for (int k = 0; k <= kmax; ++k) out[k] = dist_result{0, 0, 0};
+  dist_stats st{};
+  const bool fp = cfg.fingerprint != 0;
+  int rc = ws_ensure((size_t)kPivMaxWaves * kPivWords, 0);
+  if (rc) return rc;
+  if (per_root && g->n > 0) hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, per_root, (u64)3 * g->n);
+  // k = 1: every vertex
+  if (kmax >= 1) {
+    out[1].count_lo = (u64)g->n;
+    if (fp && g->n > 0) {
+      hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, g_ws.wave_out, (u64)1);
+      hipLaunchKernelGGL(k_sum_weights, dim3(256), dim3(256), 0, s, g->gw, g->n, g_ws.wave_out);
+      DIST_CHECK(hipMemcpyAsync(&out[1].fp, g_ws.wave_out, sizeof(u64), hipMemcpyDeviceToHost, s));
+      DIST_CHECK(hipStreamSynchronize(s));
+    }
+  }
+  if (kmax < 2) {
+    if (st_out) *st_out = st;
+    return DIST_OK;
+  }
+  // roots with at least one out-neighbour (a prefix of the sorted roots)
+  int32_t lo = 0, hi = g->n;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) / 2;
+    if (g->root_deg[mid] >= 1) lo = mid + 1; else hi = mid;
+  }
+  const int32_t nroots = lo;
+  if (nroots == 0) {
+    if (st_out) *st_out = st;
+    return DIST_OK;
+  }
+  if (g->root_deg[0] > DIST_MAX_OUTDEG) return DIST_E_UNSUPPORTED;
+  const u64* binom = nullptr;
+  rc = binom_table(&binom);
+  if (rc) return rc;
+  std::vector<Bucket> buckets = make_buckets(g, nroots);
+  int maxlds = 0, cus = 0;
+  DIST_CHECK(hipGetDevice(&g_ws.device));
+  DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, g_ws.device));
+  DIST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g_ws.device));
+  std::vector<int> grids(buckets.size());
+  size_t stack_words = 0;
+  for (size_t b = 0; b < buckets.size(); ++b) {
+    const size_t lds = pivot_lds_bytes(buckets[b].W, cfg.fingerprint, buckets[b].D);
+    if (lds > (size_t)maxlds) return DIST_E_UNSUPPORTED;
+    int64_t grid = (int64_t)pivot_occupancy(buckets[b].W, lds) * cus;
+    if (grid > kPivMaxWaves) grid = kPivMaxWaves;
+    if (grid > buckets[b].end - buckets[b].begin) grid = buckets[b].end - buckets[b].begin;
+    if (grid < 1) grid = 1;
+    grids[b] = (int)grid;
+    stack_words = std::max(stack_words, (size_t)grid * pivot_stack_words(buckets[b].W, kmax, buckets[b].D));
+  }
+  DevBuf stack(s);
+  if (dev_alloc(&stack.p, stack_words * sizeof(u64))) return DIST_E_NOMEM;
+  u64 deadline = 0;
+  if (cfg.deadline_ms > 0) {
+    int rate_khz = 0;
+    DIST_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, g_ws.device));
+    deadline = (u64)cfg.deadline_ms * (u64)rate_khz;
+  }
+  hipEvent_t e0, e1;
+  DIST_CHECK(hipEventCreate(&e0));
+  DIST_CHECK(hipEventCreate(&e1));
+  std::vector<u64> wh((size_t)kPivMaxWaves * kPivWords);
+  std::vector<u64> c_lo(kmax + 1, 0), c_hi(kmax + 1, 0), c_fp(kmax + 1, 0);
+  bool aborted = false;
+  double kernel_ms = 0;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (unsigned*)g_ws.abort_flag, 16);
+  for (size_t b = 0; b < buckets.size() && !aborted; ++b) {
+    const Bucket& bk = buckets[b];
+    PivParams prm{};
+    prm.dptr = g->dptr;
+    prm.dcol = g->dcol;
+    prm.orig = g->orig;
+    prm.roots = g->roots + bk.begin;
+    prm.gw = g->gw;
+    prm.kmax = kmax;
+    prm.fingerprint = cfg.fingerprint;
+    prm.nroots = bk.end - bk.begin;
+    prm.drows = bk.D;
+    prm.cursor = g_ws.cursor;
+    prm.stack = (u64*)stack.p;
+    prm.binom = binom;
+    prm.wave_out = g_ws.wave_out;
+    prm.abort_flag = g_ws.abort_flag;
+    prm.deadline = deadline;
+    prm.per_root = per_root;
+    prm.per_root_k = per_root ? per_root_k : -1;
+    const size_t lds = pivot_lds_bytes(bk.W, cfg.fingerprint, bk.D);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, g_ws.cursor, 64);
+    hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grids[b] * kPivWords);
+    DIST_CHECK(hipEventRecord(e0, s));
+    rc = pivot_launch(bk.W, prm, grids[b], lds, s);
+    if (rc) break;
+    DIST_CHECK(hipEventRecord(e1, s));
+    DIST_CHECK(hipMemcpyAsync(wh.data(), g_ws.wave_out, (size_t)grids[b] * kPivWords * sizeof(u64),
+                              hipMemcpyDeviceToHost, s));
+    DIST_CHECK(hipStreamSynchronize(s));
+    float kms = 0;
+    DIST_CHECK(hipEventElapsedTime(&kms, e0, e1));
+    kernel_ms += kms;
+    st.bucket_ms[wslot(bk.W)] += kms;
+    for (int w = 0; w < grids[b]; ++w) {
+      const u64* o = wh.data() + (size_t)w * kPivWords;
+      for (int k = 2; k <= kmax; ++k) {
+        const u64 nl = c_lo[k] + o[3 * k];
+        c_hi[k] += o[3 * k + 1] + (nl < c_lo[k] ? 1 : 0);
+        c_lo[k] = nl;
+        c_fp[k] = addp_host(c_fp[k], o[3 * k + 2]);
+      }
+      st.frames += o[192];
+      st.leaf_bits += o[193];
+      st.roots += o[194];
+      st.subgraph_arcs += o[195];
+      st.bucket_roots[wslot(bk.W)] += o[194];
+      if (o[196]) aborted = true;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  st.kernel_ms = kernel_ms;
+  if (st_out) *st_out = st;
+  if (rc) return rc;
+  bool wide = false;
+  for (int k = 2; k <= kmax; ++k) {
+    out[k].count_lo = c_lo[k];
+    out[k].count_hi = c_hi[k];
+    out[k].fp = fp ? c_fp[k] : 0;
+    wide = wide || c_hi[k] != 0;
+  }
+  if (aborted) return DIST_E_CANCELLED;
+  return wide ? DIST_E_OVERFLOW : DIST_OK;
 }
 
 // ---- batched counting ----------------------------------------------------------

@@ -110,6 +110,9 @@ def _load():
     lib.dist_count_noalloc.restype = ctypes.c_int
     lib.dist_list.argtypes = [vp, ctypes.c_int, SINK, vp, vp, ctypes.POINTER(Result)]
     lib.dist_list.restype = ctypes.c_int
+    lib.dist_count_all.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Config), vp, ctypes.c_int, vp,
+                                   ctypes.POINTER(Result)]
+    lib.dist_count_all.restype = ctypes.c_int
     lib.dist_list_ex.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Config), ctypes.c_int, SINK, vp, vp,
                                  ctypes.POINTER(Result)]
     lib.dist_list_ex.restype = ctypes.c_int
@@ -267,6 +270,24 @@ def count(g: Graph, k: int, cfg: Config | None = None, per_root=None, stream=Non
     if rc not in (OK, E_OVERFLOW) or (rc == E_OVERFLOW and not allow_overflow):
         _check(rc, "dist_count")
     return res.count, int(res.fp), rc
+
+
+ALL_K_MAX = 16
+
+
+def count_all(g: Graph, kmax: int, cfg: Config | None = None, per_root=None, per_root_k: int = 0, stream=None):
+    """dist_count_all: [(count, fp) for k = 0 .. kmax] by pivoting, and the
+    status.  per_root: optional 3*n uint64 (NumPy or torch device tensor),
+    filled per input id for k = per_root_k."""
+    out = (Result * (int(kmax) + 1))()
+    pr, keep = (None, None)
+    if per_root is not None:
+        pr, keep = _ptr(per_root, np.uint64)
+    rc = _load().dist_count_all(g.handle, int(kmax), ctypes.byref(cfg) if cfg is not None else None, pr,
+                                int(per_root_k), _stream_ptr(stream), out)
+    if rc not in (OK, E_OVERFLOW, E_CANCELLED):
+        _check(rc, "dist_count_all")
+    return [(r.count, int(r.fp)) for r in out], rc
 
 
 def count_noalloc(g: Graph, k: int, cfg: Config | None = None, stream=None, allow_overflow=True):

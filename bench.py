@@ -6,7 +6,9 @@ degree 20, degrees capped at 5,000, plus 200 planted 30-cliques (seed 2;
 synthetic stand-in for the paper's real networks).  One step = the whole
 hot path on the resident CSR: dist_orient (degree order) followed by
 dist_count for every k of --ks (default 5, 7 and 9), each with its count and
-fingerprint.
+fingerprint.  Untimed legs beside it: pivot-based counting of every k in one
+pass, listing on the Induced Subgraph Trie, the dense-core R-MAT graph under
+a deadline, the batched workload and serving.
 
 Prints one JSON line with the metric, the roofline of the dominant search
 kernel (integer ALU bound) and the CPU oracle timed on a bounded sample of
@@ -68,6 +70,10 @@ def parse():
                     help="turn rocprofv3 CSVs under DIR into the summaries under profiles/")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (calibrates rocprofv3 FETCH/WRITE_SIZE)")
+    ap.add_argument("--no-listing", action="store_true", help="skip the listing section")
+    ap.add_argument("--no-pivot", action="store_true", help="skip the pivot-based all-k section")
+    ap.add_argument("--no-cfg3", action="store_true", help="skip the dense-core R-MAT attempt")
+    ap.add_argument("--cfg3-deadline-ms", type=int, default=5000)
     ap.add_argument("--out", default="")
     return ap.parse_args()
 
@@ -491,6 +497,15 @@ def main():
         log("oracle on 1 thread: %.3g k-cliques/s; pivot reference on %d threads: %.3g k-cliques/s" % (
             c1 / s1, threads, c1 / sp))
 
+    pivot = None
+    if not a.no_pivot:
+        pivot = run_pivot(a, dist, torch, G, g, results, log)
+    listing = None
+    if not a.no_listing:
+        listing = run_listing(a, dist, torch, log)
+    cfg3 = None
+    if not a.no_cfg3:
+        cfg3 = run_cfg3(a, dist, torch, log)
     batched = None
     if batch_graphs is not None:
         batched = run_batched(a, dist, torch, batch_specs, batch_graphs, log)
@@ -518,13 +533,19 @@ def main():
         "per_k": [{"k": k, "count": results[k][0], "fp": results[k][1], "fingerprint": k in fp_ks,
                    "ms": float(np.median(per_k[k]["ms"])),
                    "kernel_ms": float(np.median(per_k[k]["kernel_ms"])),
-                   "cliques_per_s": results[k][0] / (np.median(per_k[k]["ms"]) / 1e3)} for k in ks],
+                   "cliques_per_s": results[k][0] / (np.median(per_k[k]["ms"]) / 1e3),
+                   "memo": {x: per_k[k]["stats"]["memo_" + x] for x in ("lookups", "hits", "inserts")},
+                   "frames": per_k[k]["stats"]["frames"], "leaf_bits": per_k[k]["stats"]["leaf_bits"]}
+                  for k in ks],
         "orient_ms": float(np.median(orient_ms)),
         "k_dnf": dnf,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cpu_context": cpu_context,
         "parity_sampled_roots": parity,
+        "pivot_all_k": pivot,
+        "listing": listing,
+        "dense_core_rmat": cfg3,
         "batched": batched,
         "serving": serving,
         "gen_s": gen_s,
@@ -534,6 +555,106 @@ def main():
     if a.out:
         with open(a.out, "w") as f:
             f.write(s + "\n")
+
+
+def run_pivot(a, dist, torch, G, g, results, log):
+    """Pivot-based counting of every clique size in one pass (dist_count_all,
+    k <= 9) on the same oriented graph: not part of the timed step; its
+    totals must equal the search's at every k the step measured."""
+    kmax = max(9, max(results))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res, rc = dist.count_all(G, kmax)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    st = G.stats()
+    same = all(res[k] == results[k] for k in results)
+    log("pivot all-k (k <= %d): %.0f ms, tree nodes %d, same as the search: %s" % (kmax, dt * 1e3, st.frames, same))
+    return {"workload": "Chung-Lu n=%d (the step's graph), every k <= %d in one pass" % (g.n, kmax),
+            "ms": dt * 1e3, "kernel_ms": st.kernel_ms, "tree_nodes": st.frames, "leaves": st.leaf_bits,
+            "counts": {str(k): [str(res[k][0]), str(res[k][1])] for k in range(kmax + 1)},
+            "same_as_search": same, "status": rc}
+
+
+def run_listing(a, dist, torch, log):
+    """Listing (dist_list_ex, rows left in device memory and handed to a
+    counting sink) on the small Chung-Lu graph (n = 10^4, 20 planted
+    12-cliques): k = 4 (criterion (1) never holds: plain Listing) and k = 6
+    with the Induced Subgraph Trie under criterion (1) and forced on every
+    branch, against plain Listing.  Output-write roofline: 4k bytes per
+    clique against the 8 TB/s of HBM."""
+    import numpy as np
+    from paper_2502_00317_amd import graphgen as gg
+    g = gg.small_powerlaw()
+    G = dist.orient(g.row_ptr, g.col)
+    out = {"workload": "listing: Chung-Lu n=10,000, exponent 2.5, mean degree 8, cap 200, +20 planted K12, seed 1",
+           "legs": []}
+    for k, memo in ((4, 1), (6, 0), (6, 1), (6, 2)):
+        times = []
+        for _ in range(max(1, min(a.steps, 5))):
+            seen = [0]
+
+            def sink(ptr, n, kk):
+                seen[0] += n
+                return 0
+
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, cnt, fp, rc = dist.list_cliques(G, k, cfg=dist.config(memo=memo), device_rows=True, raw_sink=sink)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            assert seen[0] == cnt and rc == dist.OK
+        st = G.stats()
+        sec = float(np.median(times))
+        gbs = cnt * 4 * k / sec / 1e9
+        leg = {"k": k, "memo": memo, "cliques": cnt, "fp": fp, "ms": sec * 1e3, "cliques_per_s": cnt / sec,
+               "bytes_written": cnt * 4 * k, "write_GBps": gbs, "write_frac_of_8TBps": gbs / 8000.0,
+               "dense_frames": st.memo_lookups, "trie_nodes": st.memo_inserts, "retrievals": st.memo_hits,
+               "retrieved_cliques": st.leaf_bits, "frames": st.frames}
+        out["legs"].append(leg)
+        log("listing k=%d memo=%d: %d cliques in %.2f ms (%.3g/s, %.2f GB/s written), %d retrieved" % (
+            k, memo, cnt, sec * 1e3, cnt / sec, gbs, st.leaf_bits))
+    G.free()
+    return out
+
+
+def run_cfg3(a, dist, torch, log):
+    """The dense-core stress graph (R-MAT scale 22, edge factor 16, 10 planted
+    60-cliques): orientation, then k = 6 and 8 by the search and every k <= 12
+    by pivoting, each under a deadline; a count that does not finish is
+    reported as DNF."""
+    from paper_2502_00317_amd import graphgen as gg
+    t = time.time()
+    g = gg.dense_core_rmat()
+    gen_s = time.time() - t
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    G = dist.orient(g.row_ptr, g.col, order=dist.ORDER_DEGENERACY)
+    torch.cuda.synchronize()
+    orient_ms = (time.perf_counter() - t) * 1e3
+    info = G.info()
+    out = {"workload": "R-MAT scale 22, ef 16, (0.57,0.19,0.19,0.05), +10 planted K60, seed 3",
+           "n": g.n, "m": g.m, "gen_s": gen_s, "orient_ms": orient_ms, "degeneracy": info.order_bound,
+           "max_outdeg": info.max_outdeg, "deadline_ms": a.cfg3_deadline_ms, "search": {}, "pivot": None}
+    for k in (6, 8):
+        try:
+            c, f, rc = dist.count(G, k, cfg=dist.config(deadline_ms=a.cfg3_deadline_ms))
+            out["search"][str(k)] = {"status": "finished", "count": str(c), "fp": str(f)}
+        except dist.DistError as e:
+            st = G.stats()
+            out["search"][str(k)] = {"status": "DNF" if e.status == dist.E_CANCELLED else "error %d" % e.status,
+                                     "roots_done": st.roots}
+        log("dense-core R-MAT search k=%d: %s" % (k, out["search"][str(k)]["status"]))
+    res, rc = dist.count_all(G, 12, cfg=dist.config(deadline_ms=a.cfg3_deadline_ms))
+    st = G.stats()
+    out["pivot"] = {"kmax": 12, "status": {dist.OK: "finished", dist.E_OVERFLOW: "finished (k=12 >= 2^64)",
+                                           dist.E_CANCELLED: "DNF"}.get(rc, "error %d" % rc),
+                    "roots_done": st.roots, "tree_nodes": st.frames}
+    if rc in (dist.OK, dist.E_OVERFLOW):
+        out["pivot"]["counts"] = {str(k): [str(res[k][0]), str(res[k][1])] for k in range(13)}
+    log("dense-core R-MAT pivot k<=12: %s" % out["pivot"]["status"])
+    G.free()
+    return out
 
 
 def run_batched(a, dist, torch, specs, graphs, log):

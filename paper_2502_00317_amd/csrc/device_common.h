@@ -35,22 +35,48 @@ __device__ __forceinline__ u64 mulp(u64 a, u64 b) {
   return r >= DIST_P61 ? r - DIST_P61 : r;
 }
 
-__device__ __forceinline__ u64 wave_sum(u64 x) {
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-  return x;
-}
-
-__device__ __forceinline__ u64 wave_sum_p(u64 x) {
-  for (int off = 32; off > 0; off >>= 1) x = addp(x, __shfl_xor(x, off));
-  return x;
-}
-
 // Lane l's value of v (l uniform); valid in divergent code, since it reads
 // the register directly.
 __device__ __forceinline__ u64 readlane64(u64 v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
   return ((u64)hi << 32) | lo;
+}
+
+// A 64-bit value moved across lanes by a DPP pattern (lanes the pattern or
+// the row mask leaves out receive 0).  Patterns: quad_perm [1,0,3,2] (0xB1)
+// and [2,3,0,1] (0x4E), row_half_mirror (0x141), row_mirror (0x140),
+// row_bcast:15 (0x142) and row_bcast:31 (0x143).
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ u64 dpp64(u64 v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, false);
+  return ((u64)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Wave sums (every lane active): pairs, quads, half-rows and rows by DPP
+// within each row of 16 lanes, then rows 0+1 and 2+3 by broadcasting lane 15
+// of a row into the next, and the two halves by broadcasting lane 31; lane 63
+// ends with the total, read back for every lane.  Each step is a VALU move
+// rather than a round trip through the LDS crossbar.
+__device__ __forceinline__ u64 wave_sum(u64 x) {
+  x += dpp64<0xB1>(x);
+  x += dpp64<0x4E>(x);
+  x += dpp64<0x141>(x);
+  x += dpp64<0x140>(x);
+  x += dpp64<0x142, 0xA>(x);
+  x += dpp64<0x143, 0xC>(x);
+  return readlane64(x, 63);
+}
+
+__device__ __forceinline__ u64 wave_sum_p(u64 x) {
+  x = addp(x, dpp64<0xB1>(x));
+  x = addp(x, dpp64<0x4E>(x));
+  x = addp(x, dpp64<0x141>(x));
+  x = addp(x, dpp64<0x140>(x));
+  x = addp(x, dpp64<0x142, 0xA>(x));
+  x = addp(x, dpp64<0x143, 0xC>(x));
+  return readlane64(x, 63);
 }
 
 __device__ __forceinline__ u64 ld_coherent(const u64* p) {

@@ -1033,10 +1033,12 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
         if (j > 0 && m_edges == (u64)np * (u64)(np - 1) / 2) {
           u64 clo, chi;
           if (binom128(np, l, clo, chi)) {
-            res_lo = clo;
-            res_hi = chi;
-            res_fp = FP ? esym_members<W>(s.mem, np, s.gl, l) : 0;
-            if (j == jsplit && sub != 0) res_lo = res_hi = res_fp = 0;
+            // at a shared split frame the closed form is sub-unit 0's: the
+            // others skip it (and its fingerprint) entirely
+            const bool mine = !(j == jsplit && sub != 0);
+            res_lo = mine ? clo : 0;
+            res_hi = mine ? chi : 0;
+            res_fp = (FP && mine) ? esym_members<W>(s.mem, np, s.gl, l) : 0;
             __syncthreads();
             mode = FINISH;
             continue;
@@ -1044,6 +1046,15 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
         }
         {
           const u64 full = (u64)np * (u64)(np - 1) / 2;
+          if (j > 0 && j == jsplit && sub != 0 && m_edges < full && full - m_edges <= (u64)kNearMissing &&
+              np <= kBinomN && l <= kBinomR && (!FP || l <= kNearFpL)) {
+            // a nearly complete split frame whose closed form surely applies
+            // (every binomial comes from the table): sub-unit 0's
+            res_lo = res_hi = res_fp = 0;
+            __syncthreads();
+            mode = FINISH;
+            continue;
+          }
           if (j > 0 && m_edges < full && full - m_edges <= (u64)kNearMissing) {
             const int e = missing_edges<W>(s, Pr, np, s.pos);
             u64 clo, chi, cfp;

@@ -35,6 +35,14 @@ __device__ __forceinline__ u64 mulp(u64 a, u64 b) {
   return r >= DIST_P61 ? r - DIST_P61 : r;
 }
 
+// The LDS address space of a pointer into the workgroup's LDS: a function
+// that is not inlined sees its array arguments as generic pointers and would
+// otherwise read them with flat loads.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(3))) T* as_lds(const T* p) {
+  return (const __attribute__((address_space(3))) T*)p;
+}
+
 // Lane l's value of v (l uniform); valid in divergent code, since it reads
 // the register directly.
 __device__ __forceinline__ u64 readlane64(u64 v, int l) {

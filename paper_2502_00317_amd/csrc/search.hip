@@ -375,7 +375,9 @@ __global__ void k_fill_binom() {
 // e_j of the weights of the np members of P for j = 0..l (wave-collective):
 // lane j holds e_j while the members are added one at a time.  Used where l
 // exceeds kEsymMaxL.
-__device__ __forceinline__ u64 esym_serial(const uint16_t* mem, int np, const u64* gl, int l) {
+__device__ __forceinline__ u64 esym_serial(const uint16_t* mem_, int np, const u64* gl_, int l) {
+  const auto* mem = as_lds(mem_);
+  const auto* gl = as_lds(gl_);
   const int lane = lane_id();
   u64 e = lane == 0 ? 1ull : 0ull;
   for (int i = 0; i < np; ++i) {
@@ -413,14 +415,22 @@ constexpr InvSmall make_inv_small() {
   return t;
 }
 constexpr InvSmall kInvSmall = make_inv_small();
+// the same, in constant memory for a loop index
+__constant__ u64 c_inv_small[kEsymMaxL + 1] = {
+    kInvSmall.v[0],  kInvSmall.v[1],  kInvSmall.v[2],  kInvSmall.v[3],  kInvSmall.v[4],  kInvSmall.v[5],
+    kInvSmall.v[6],  kInvSmall.v[7],  kInvSmall.v[8],  kInvSmall.v[9],  kInvSmall.v[10], kInvSmall.v[11],
+    kInvSmall.v[12], kInvSmall.v[13], kInvSmall.v[14], kInvSmall.v[15], kInvSmall.v[16]};
 
-// Not inlined: it would otherwise add to the search kernel's registers.
-// Lane j returns e_j (j <= l), the rest 0.  A lane holds at most W members
-// (np <= 64 W); lane m keeps p_m, lane j keeps e_j, and the products of the
-// identities take their factors from other lanes by readlane.
+// Not inlined, and its loops are not unrolled: it is called at most search
+// frames, so it has to stay small in the instruction cache.  Lane j returns
+// e_j (j <= l), the rest 0.  A lane holds at most W members (np <= 64 W);
+// lane m keeps p_m, lane j keeps e_j, and the products of the identities take
+// their factors from other lanes by readlane (uniform loop indices).
 template <int W>
-__device__ __noinline__ u64 esym_lanes(const uint16_t* mem, int np, const u64* gl, int l) {
-  if (l > kEsymMaxL) return esym_serial(mem, np, gl, l);
+__device__ __noinline__ u64 esym_lanes(const uint16_t* mem_, int np, const u64* gl_, int l) {
+  if (l > kEsymMaxL) return esym_serial(mem_, np, gl_, l);
+  const auto* mem = as_lds(mem_);
+  const auto* gl = as_lds(gl_);
   const int lane = lane_id();
   u64 g[W], pw[W];
 #pragma unroll
@@ -429,34 +439,34 @@ __device__ __noinline__ u64 esym_lanes(const uint16_t* mem, int np, const u64* g
     g[t] = i < np ? gl[mem[i]] : 0ull;
     pw[t] = g[t];
   }
-  u64 pl = 0;  // lane m: p_m
+  const int nt = (np + kWave - 1) / kWave;  // slots in use (uniform)
+  u64 pl = 0;                               // lane m: p_m
+#pragma unroll 1
+  for (int m = 1; m <= l; ++m) {
+    u64 acc = pw[0];
+    pw[0] = mulp(pw[0], g[0]);
 #pragma unroll
-  for (int m = 1; m <= kEsymMaxL; ++m) {
-    if (m <= l) {
-      u64 acc = 0;
-#pragma unroll
-      for (int t = 0; t < W; ++t) {
+    for (int t = 1; t < W; ++t) {
+      if (t < nt) {
         acc = addp(acc, pw[t]);
-        if (m < l) pw[t] = mulp(pw[t], g[t]);
+        pw[t] = mulp(pw[t], g[t]);
       }
-      acc = wave_sum_p(acc);
-      if (lane == m) pl = acc;
     }
+    acc = wave_sum_p(acc);
+    if (lane == m) pl = acc;
   }
   u64 el = lane == 0 ? 1ull : 0ull;  // lane j: e_j
-#pragma unroll
-  for (int j = 1; j <= kEsymMaxL; ++j) {
-    if (j <= l) {
-      u64 pos = 0, neg = 0;
-#pragma unroll
-      for (int i = 1; i <= j; ++i) {
-        const u64 t = mulp(readlane64(el, j - i), readlane64(pl, i));
-        if (i & 1) pos = addp(pos, t);
-        else neg = addp(neg, t);
-      }
-      const u64 ej = mulp(subp(pos, neg), kInvSmall.v[j]);
-      if (lane == j) el = ej;
+#pragma unroll 1
+  for (int j = 1; j <= l; ++j) {
+    u64 pos = 0, neg = 0;
+#pragma unroll 1
+    for (int i = 1; i <= j; ++i) {
+      const u64 t = mulp(readlane64(el, j - i), readlane64(pl, i));
+      if (i & 1) pos = addp(pos, t);
+      else neg = addp(neg, t);
     }
+    const u64 ej = mulp(subp(pos, neg), c_inv_small[j]);
+    if (lane == j) el = ej;
   }
   return el;
 }
@@ -495,11 +505,20 @@ __device__ __forceinline__ void wave_sum128(u64& lo, u64& hi) {
 // With FP, e_{l - v}(P \ V(S)) comes from the coefficients of
 // prod_{x in P} (1 + g(x) t) (mem, gl: the members and their weights) divided
 // by (1 + g(v) t) for each v in V(S): q_0 = 1, q_j = f_j - g(v) q_{j-1}.
+// The result comes back by value (in registers, not through the stack).
+struct Closed {
+  u64 lo, hi, fp;
+  bool ok;
+};
+
 template <int W, bool FP>
-__device__ __noinline__ bool near_complete(const uint16_t* pairs, int e, int np, int l, const uint16_t* mem,
-                                           const u64* gl, u64& lo, u64& hi, u64& fp) {
+__device__ __noinline__ Closed near_complete_impl(const uint16_t* pairs_, int e, int np, int l, const uint16_t* mem,
+                                                  const u64* gl_) {
+  const auto* pairs = as_lds(pairs_);
+  const auto* gl = as_lds(gl_);
   const int lane = lane_id();
-  if (FP && l > kNearFpL) return false;
+  Closed r{0, 0, 0, false};
+  if (FP && l > kNearFpL) return r;
   // distinct endpoints: lane t < 2e holds the t-th endpoint; idx numbers the
   // distinct ones in order of first appearance
   const int a = lane < 2 * e ? (int)pairs[lane] : -1;
@@ -524,13 +543,13 @@ __device__ __noinline__ bool near_complete(const uint16_t* pairs, int e, int np,
   u64 cvlo = 0, cvhi = 0;
   bool ok = true;
   if (lane <= nv && lane <= l) ok = binom128(np - lane, l - lane, cvlo, cvhi);
-  if (__ballot(!ok)) return false;
+  if (__ballot(!ok)) return r;
   // fingerprint: lane j holds the coefficient f_j = e_j(g(P)) and lane i the
   // weight of the i-th distinct endpoint; read back with readlane (uniform
   // lane numbers), so only the quotient stays in registers per lane
   u64 ep = 0, gyl = 0;
   if constexpr (FP) {
-    ep = esym_lanes<W>(mem, np, gl, l);
+    ep = esym_lanes<W>(mem, np, gl_, l);
     const u64 wt = lane < 2 * e ? gl[a] : 0ull;
     u64 fb = firsts;
     for (int i = 0; i < nv; ++i) {
@@ -568,10 +587,10 @@ __device__ __noinline__ bool near_complete(const uint16_t* pairs, int e, int np,
 #pragma unroll
           for (int j = 0; j <= kNearFpL; ++j) q[j] = j <= l ? readlane64(ep, j) : 0ull;
           u64 gprod = 1;
-#pragma unroll
-          for (int i = 0; i < 2 * kNearMissing; ++i) {
-            if (i < nv && ((m >> i) & 1u)) {
-              const u64 gi = readlane64(gyl, i);
+#pragma unroll 1
+          for (int i = 0; i < nv; ++i) {
+            const u64 gi = readlane64(gyl, i);  // uniform i: read even where lanes diverge
+            if ((m >> i) & 1u) {
               gprod = mulp(gprod, gi);
 #pragma unroll
               for (int j = 1; j <= kNearFpL; ++j)
@@ -591,10 +610,21 @@ __device__ __noinline__ bool near_complete(const uint16_t* pairs, int e, int np,
   }
   wave_sum128(plo, phi);
   wave_sum128(nlo, nhi);
-  lo = plo - nlo;
-  hi = phi - nhi - (plo < nlo ? 1ull : 0ull);
-  fp = FP ? subp(wave_sum_p(fpos), wave_sum_p(fneg)) : 0ull;
-  return true;
+  r.lo = plo - nlo;
+  r.hi = phi - nhi - (plo < nlo ? 1ull : 0ull);
+  r.fp = FP ? subp(wave_sum_p(fpos), wave_sum_p(fneg)) : 0ull;
+  r.ok = true;
+  return r;
+}
+
+template <int W, bool FP>
+__device__ __forceinline__ bool near_complete(const uint16_t* pairs, int e, int np, int l, const uint16_t* mem,
+                                              const u64* gl, u64& lo, u64& hi, u64& fp) {
+  const Closed r = near_complete_impl<W, FP>(pairs, e, np, l, mem, gl);
+  lo = r.lo;
+  hi = r.hi;
+  fp = r.fp;
+  return r.ok;
 }
 
 // Collects the missing edges of G[P] (members mem[0..np), candidate words Pr)

@@ -248,10 +248,28 @@ __device__ __forceinline__ u64 weight_sum_any(const u64 (&q)[W], const u64* gl, 
   return weight_sum<W>(q, gl, bits);
 }
 
-// Edges of G[Y] and their fingerprint sum Σ g(y) g(z) over edges y<z.
+// Word w of the bitmap of local ids >= x.
+__device__ __forceinline__ u64 cut_mask(int x, int w) {
+  const int lo_b = w * 64;
+  return (x <= lo_b) ? ~0ull : (x >= lo_b + 64 ? 0ull : (~0ull << (x - lo_b)));
+}
+
+// Edges of G[Y] and their fingerprint sum Σ g(y) g(z) over edges y<z (rows
+// hold forward neighbours only).  For each y the sum over its neighbours z
+// above it is taken directly, or, where they are the majority of the members
+// above y, as the weight of all members above y (kept as a running
+// remainder) minus that of the non-neighbours among them: in a dense G[Y] the
+// second set is mostly empty words, which the table sum skips.
 template <int W>
 __device__ __forceinline__ void edges_in(const u64 (&Y)[W], const u64* A, const u64* gl, const u64* tab, int fpon,
                                          u64& cnt, u64& fp, u64& wops, u64& bits) {
+  int rest = 0;   // members of Y above the current y
+  u64 wrest = 0;  // and their weight sum
+  if (fpon) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) rest += __popcll(Y[w]);
+    wrest = weight_sum_any<W>(Y, gl, tab, bits);
+  }
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     u64 b = Y[w];
@@ -268,7 +286,19 @@ __device__ __forceinline__ void edges_in(const u64 (&Y)[W], const u64* A, const 
       }
       wops += W;
       cnt += (u64)c;
-      if (fpon && c) fp = addp(fp, mulp(gl[y], weight_sum_any<W>(q, gl, tab, bits)));
+      if (fpon) {
+        const u64 gy = gl[y];
+        wrest = subp(wrest, gy);
+        --rest;
+        if (c) {
+          const bool comp = 2 * c > rest;
+          u64 z[W];
+#pragma unroll
+          for (int v = 0; v < W; ++v) z[v] = comp ? (Y[v] & cut_mask(y + 1, v) & ~A[y * W + v]) : q[v];
+          const u64 ws = weight_sum_any<W>(z, gl, tab, bits);
+          fp = addp(fp, mulp(gy, comp ? subp(wrest, ws) : ws));
+        }
+      }
     }
   }
 }

@@ -132,11 +132,6 @@ struct Params {
 
 // Keys are candidate sets read from LDS: P (W words), optionally cut to its
 // members >= x (x < 0: no cut), i.e. the trie node P & [x, inf).
-__device__ __forceinline__ u64 cut_mask(int x, int w) {
-  const int lo_b = w * 64;
-  return (x <= lo_b) ? ~0ull : (x >= lo_b + 64 ? 0ull : (~0ull << (x - lo_b)));
-}
-
 template <int W>
 __device__ __forceinline__ u64 memo_hash(u64 tag, const u64* P, int x) {
   u64 h = tag * 0x9E3779B97F4A7C15ull;

@@ -91,6 +91,17 @@ __device__ __forceinline__ u64 ld_coherent(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Device memory private to one wave (a per-wave stack, trie or memo table),
+// written by some of its lanes and read back by others.  The wave's lanes run
+// on one CU, whose vector L1 is write-through and shared by the CU's waves,
+// so workgroup scope is enough: the fence waits for the wave's stores, and the
+// loads may hit L1 and L2.  (Agent scope would write back and bypass the
+// XCD's own L2 on every use.)
+__device__ __forceinline__ u64 ld_wave(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
 // ---- LDS layout -------------------------------------------------------------
 // u64 part: A (D*W), gl (D, only with fingerprints), per-level stacks, R (W).  Then a union of the
 // arrays used only while G_u is built (nb, rowbeg, rowptr) with the arrays

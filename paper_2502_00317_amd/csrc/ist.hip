@@ -76,15 +76,15 @@ __device__ Trie trie_view(const IstParams& p) {
   return t;
 }
 
-// trie metadata is read and written by lane 0 only, through L2
+// trie metadata is read and written by lane 0 only (wave-private memory)
 __device__ __forceinline__ uint32_t tget32(const uint32_t* a) {
-  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void tput32(uint32_t* a, uint32_t v) {
-  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void tput64(u64* a, u64 v) {
-  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ uint32_t bcast32(uint32_t v) { return (uint32_t)__shfl((int)v, 0); }
@@ -93,7 +93,7 @@ __device__ __forceinline__ u64 bcast64(u64 v) { return __shfl(v, 0); }
 // Wave-uniform reads of a node's fields (lane 0 loads, every lane gets it).
 __device__ __forceinline__ u64 node_marked(const Trie& T, uint32_t t) {
   u64 v = 0;
-  if (lane_id() == 0) v = ld_coherent(T.marked + t);
+  if (lane_id() == 0) v = ld_wave(T.marked + t);
   return bcast64(v);
 }
 __device__ __forceinline__ uint32_t node_lc(const Trie& T, int k, uint32_t t, int l) {
@@ -126,7 +126,7 @@ __device__ __forceinline__ bool memoised(const Trie& T, uint32_t t, int l) {
 }
 __device__ __forceinline__ void set_marked(const Trie& T, uint32_t t, int l) {
   if (lane_id() == 0) {
-    const u64 m = ld_coherent(T.marked + t);
+    const u64 m = ld_wave(T.marked + t);
     tput64(T.marked + t, m | (1ull << l));
   }
 }
@@ -182,12 +182,12 @@ __device__ bool trie_insert(const Trie& T, const u64 (&S)[W], uint16_t* scratch,
       bool need = false;
       u64 slot = 0;
       if (!done) {
-        slot = ld_coherent(T.hash + (h & hmask));
+        slot = ld_wave(T.hash + (h & hmask));
         if ((slot & ~0xFFFFFFull) == tag) {
           const uint32_t nd = (uint32_t)(slot & 0xFFFFFFull);
           bool eq = true;
 #pragma unroll
-          for (int w = 0; w < W; ++w) eq = eq && (ld_coherent(T.keys + (u64)nd * W + w) == key[w]);
+          for (int w = 0; w < W; ++w) eq = eq && (ld_wave(T.keys + (u64)nd * W + w) == key[w]);
           if (eq) {
             node = nd;
             done = true;
@@ -215,7 +215,7 @@ __device__ bool trie_insert(const Trie& T, const u64 (&S)[W], uint16_t* scratch,
           T.label[mine] = (uint32_t)y;
           created += 1;
         }
-        __threadfence();
+        wave_fence();
       }
       if (need) {
         const u64 old = atomicCAS((unsigned long long*)(T.hash + (h & hmask)), (unsigned long long)slot,
@@ -229,7 +229,7 @@ __device__ bool trie_insert(const Trie& T, const u64 (&S)[W], uint16_t* scratch,
     }
     if (ok && act) path[y] = node;
   }
-  __threadfence();
+  wave_fence();
   __syncthreads();
   return ok;
 }
@@ -501,7 +501,7 @@ __device__ void listing_ist(const IstParams& p, const Lds& s, const IstLds& x, c
   const u64 before = cnt;
   if (l0 == 1) {
 #pragma unroll
-    for (int w = 0; w < W; ++w) key[w] = ld_coherent(T.keys + (u64)t0 * W + w);
+    for (int w = 0; w < W; ++w) key[w] = ld_wave(T.keys + (u64)t0 * W + w);
     make_prefix(x.cid, x.cw, nc, x.pre, fp, P);
     emit_set<W>(p, s, x.oid, key, P, o, cnt, fpacc);
     retrieved += cnt - before;
@@ -543,7 +543,7 @@ __device__ void listing_ist(const IstParams& p, const Lds& s, const IstLds& x, c
       }
       __syncthreads();
 #pragma unroll
-      for (int w = 0; w < W; ++w) key[w] = ld_coherent(T.keys + (u64)child * W + w);
+      for (int w = 0; w < W; ++w) key[w] = ld_wave(T.keys + (u64)child * W + w);
       make_prefix(x.cid, x.cw, nc + dep + 1, x.pre, fp, P);
       emit_set<W>(p, s, x.oid, key, P, o, cnt, fpacc);
     } else {
@@ -875,11 +875,11 @@ __global__ __launch_bounds__(64, 1) void k_list_ist(IstParams p) {
         const u64 tag = (epoch & kEpochMask) << 24;
         u64 h = set_hash<W>(key);
         for (uint32_t probe = 0; probe <= (uint32_t)p.hmask; ++probe, ++h) {
-          const u64 slot = ld_coherent(T.hash + (h & p.hmask));
+          const u64 slot = ld_wave(T.hash + (h & p.hmask));
           if ((slot & ~0xFFFFFFull) != tag) break;
           const uint32_t nd = (uint32_t)(slot & 0xFFFFFFull);
           bool eq = true;
-          for (int w = 0; w < W; ++w) eq = eq && ld_coherent(T.keys + (u64)nd * W + w) == key[w];
+          for (int w = 0; w < W; ++w) eq = eq && ld_wave(T.keys + (u64)nd * W + w) == key[w];
           if (eq) {
             node = nd;
             break;

@@ -128,8 +128,8 @@ __device__ __forceinline__ void binom_at(const u64* tab, int n, int r, u64& lo, 
   }
 }
 
-// Stack words are written by some lanes and read back by all: through L2.
-__device__ __forceinline__ u64 sld(const u64* a) { return ld_coherent(a); }
+// Stack words are written by some lanes and read back by all (wave-private).
+__device__ __forceinline__ u64 sld(const u64* a) { return ld_wave(a); }
 
 template <int W>
 __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
       }
       if (lane <= K) f0.E[lane] = lane == 0 ? 1ull : 0ull;
     }
-    __threadfence();
+    wave_fence();
     int depth = 0;
     int h = 1, q = 0;  // held (the root first) and pivot counts
     u64 prod = fp ? p.gw[r] : 0ull;
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
           if (fp && lane >= 1 && lane <= K) ne = addp(e, mulp(prev, s.gl[best]));
           if (lane <= K) c.E[lane] = ne;
         }
-        __threadfence();
+        wave_fence();
         ++depth;
         ++q;
         continue;
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
           f.Dn[lane] = dn | bit;
         }
         if (lane <= K) c.E[lane] = sld(f.E + lane);
-        __threadfence();
+        wave_fence();
         if (fp) prod = mulp(prod, s.gl[v]);
         ++h;
         ++depth;

@@ -168,7 +168,7 @@ __device__ __forceinline__ int memo_find(const Params& p, const u64* table, u64 
       const int i = g / kMemoProbe, t = g % kMemoProbe;
       const int x = cuts ? (int)cuts[i] : -1;
       const u64 h = memo_hash<W>(tag, P, x);
-      v = ld_coherent(table + ((h + (u64)t) & p.memo_mask) * ES + w);
+      v = ld_wave(table + ((h + (u64)t) & p.memo_mask) * ES + w);
       ok = w > W || v == (w == 0 ? tag : (P[w - 1] & cut_mask(x, w - 1)));
     }
     const u64 b = __ballot(ok);

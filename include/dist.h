@@ -212,7 +212,9 @@ int dist_count_ex(const dist_graph* g, int k, const dist_config* cfg,
  * 1 <= kmax <= DIST_ALL_K_MAX (so every C(|Q|, j) is exact in 128 bits).  per_root (optional, host or device, 3 * n
  * words) receives, for k = per_root_k (2 .. kmax), each root's count and fp
  * as in dist_count_ex.  cfg (NULL = the graph's): fingerprint and
- * deadline_ms apply.  Returns DIST_OK, DIST_E_OVERFLOW (some count >= 2^64;
+ * deadline_ms apply, and sub_units > 0 sets how many work units share each
+ * root (0 = auto: launches with few roots per wavefront split them, up to
+ * 64; results do not depend on it).  Returns DIST_OK, DIST_E_OVERFLOW (some count >= 2^64;
  * results exact), DIST_E_CANCELLED (deadline; results partial), DIST_E_K,
  * DIST_E_UNSUPPORTED, DIST_E_NOMEM or DIST_E_DEVICE. */
 #define DIST_ALL_K_MAX 16

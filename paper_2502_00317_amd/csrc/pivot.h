@@ -22,6 +22,11 @@ struct PivParams {
   u64 deadline;          // wall_clock64 ticks from the launch; 0 = none
   u64* per_root;         // optional: 3 words per input id, for k = per_root_k
   int per_root_k;
+  int nsub;              // work units per root (>= 1): unit s of a root takes
+                         // the tree nodes at depth split_depth whose entry
+                         // number is s mod nsub (and, for s = 0, the leaves
+                         // above that depth)
+  int split_depth;       // >= 1
 };
 
 int pivot_launch(int W, const PivParams& prm, int grid, size_t lds, hipStream_t s);

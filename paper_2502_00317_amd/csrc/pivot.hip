@@ -159,11 +159,20 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
   bool aborted = false;
   const u64 t_start = wall_clock64();
   const u64 deadline = p.deadline ? t_start + p.deadline : 0;
+  // A heavy root is shared by nsub units.  Every unit builds G_u and walks
+  // the tree down to depth split_depth (the pivot choice is
+  // deterministic, so all of them see the same nodes in the same order); the
+  // nodes at that depth are dealt out round-robin, and the leaves above it
+  // count in unit 0 only.
+  const uint32_t nsub = p.nsub > 1 ? (uint32_t)p.nsub : 1u;
+  const int split_depth = p.split_depth > 0 ? p.split_depth : 1;
+  const uint32_t nunits = (uint32_t)p.nroots * nsub;
   for (;;) {
-    uint32_t ri = 0;
-    if (lane == 0) ri = atomicAdd(p.cursor, 1u);
-    ri = (uint32_t)__shfl((int)ri, 0);
-    if (ri >= (uint32_t)p.nroots) break;
+    uint32_t ui = 0;
+    if (lane == 0) ui = atomicAdd(p.cursor, 1u);
+    ui = (uint32_t)__shfl((int)ui, 0);
+    if (ui >= nunits) break;
+    const uint32_t ri = ui / nsub, sub = ui % nsub;
     if (__hip_atomic_load(p.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       aborted = true;
       break;
@@ -171,7 +180,7 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
     const int32_t r = p.roots[ri];
     const int32_t beg = p.dptr[r];
     const int d = p.dptr[r + 1] - beg;
-    ++n_roots;
+    if (sub == 0) ++n_roots;
     arcs += build_sym<W>(s, p.dptr, p.dcol, p.gw, beg, d);
     u64 r_lo = 0, r_hi = 0, r_fp = 0;  // this root's cliques of size per_root_k
     {
@@ -187,10 +196,16 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
     int h = 1, q = 0;  // held (the root first) and pivot counts
     u64 prod = fp ? p.gw[r] : 0ull;
     enum { ENTER, NEXT, FINISH } mode = ENTER;
+    uint32_t n_split = 0;  // nodes entered so far at depth split_depth
     while (true) {
       const PivFrame f = F(depth);
       if (mode == ENTER) {
-        ++n_nodes;
+        const bool shared = nsub > 1 && depth < split_depth;  // walked by every unit of the root
+        if (nsub > 1 && depth == split_depth && (n_split++ % nsub) != sub) {
+          mode = FINISH;
+          continue;
+        }
+        if (!shared || sub == 0) ++n_nodes;
         if (deadline && (n_nodes & 63) == 0 && wall_clock64() > deadline) {
           if (lane == 0) atomicOr(p.abort_flag, 1);
           aborted = true;
@@ -206,6 +221,10 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
         if (np == 0 || h >= K) {
           // a leaf: the cliques H + S, S any subset of the pivots Q.  With
           // h = K only S = {} still has size <= K: the held set alone.
+          if (shared && sub != 0) {
+            mode = FINISH;
+            continue;
+          }
           ++n_leaves;
           const int qq = np == 0 ? q : 0;
           const u64 e_here = (lane <= K) ? sld(f.E + lane) : 0ull;
@@ -336,9 +355,20 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
       const u64 rl = __shfl(r_lo, src), rh = __shfl(r_hi, src), rf = __shfl(r_fp, src);
       if (lane == 0) {
         u64* o = p.per_root + 3 * (u64)p.orig[r];
-        o[0] = rl;
-        o[1] = rh;
-        o[2] = rf;
+        if (nsub == 1) {
+          o[0] = rl;
+          o[1] = rh;
+          o[2] = rf;
+        } else {
+          // the root's units add up (the output starts at zero)
+          const u64 old = atomicAdd((unsigned long long*)&o[0], (unsigned long long)rl);
+          atomicAdd((unsigned long long*)&o[1], (unsigned long long)(rh + (old + rl < old ? 1ull : 0ull)));
+          u64 cur = o[2], seen;
+          do {
+            seen = cur;
+            cur = atomicCAS((unsigned long long*)&o[2], seen, addp(seen, rf));
+          } while (cur != seen);
+        }
       }
     }
   }

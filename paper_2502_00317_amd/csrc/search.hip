@@ -2531,14 +2531,34 @@ int search_count_all(const dist_graph* g, int kmax, const dist_config& cfg, u64*
   DIST_CHECK(hipGetDevice(&g_ws.device));
   DIST_CHECK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, g_ws.device));
   DIST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g_ws.device));
-  std::vector<int> grids(buckets.size());
+  std::vector<int> grids(buckets.size()), nsubs(buckets.size()), sdepth(buckets.size());
   size_t stack_words = 0;
   for (size_t b = 0; b < buckets.size(); ++b) {
     const size_t lds = pivot_lds_bytes(buckets[b].W, cfg.fingerprint, buckets[b].D);
     if (lds > (size_t)maxlds) return DIST_E_UNSUPPORTED;
     int64_t grid = (int64_t)pivot_occupancy(buckets[b].W, lds) * cus;
     if (grid > kPivMaxWaves) grid = kPivMaxWaves;
-    if (grid > buckets[b].end - buckets[b].begin) grid = buckets[b].end - buckets[b].begin;
+    // units per root: a launch with fewer than 8 roots per wave shares each
+    // root among up to 64 units (a power of two), so that its few heavy
+    // roots do not hold the launch; cfg.sub_units forces a count.  The units
+    // part ways at depth 2 of the tree, or at depth 24 where the launch has
+    // fewer roots than waves: a pivot tree keeps most of its nodes under the
+    // chain of pivot children, so a shallow split leaves one unit most of a
+    // heavy root (on the 10^6-vertex Chung-Lu graph, all k <= 9: one unit
+    // held 5.6M of a root's nodes and the whole 11 s of its launch at depth
+    // 2; the launch took 2.2 s at depth 24, while the walk above the split,
+    // repeated by every unit, made depth 32 slower again)
+    const int64_t nr = buckets[b].end - buckets[b].begin;
+    sdepth[b] = nr < grid ? 24 : 2;
+    int nsub = 1;
+    if (cfg.sub_units > 0) {
+      nsub = std::min(cfg.sub_units, 64);
+    } else {
+      while (nsub < 64 && (int64_t)nsub * nr < 8 * grid) nsub *= 2;
+    }
+    while (nsub > 1 && nr * nsub > (int64_t)UINT32_MAX) nsub /= 2;  // unit numbers are 32-bit
+    nsubs[b] = nsub;
+    if (grid > nr * nsub) grid = nr * nsub;
     if (grid < 1) grid = 1;
     grids[b] = (int)grid;
     stack_words = std::max(stack_words, (size_t)grid * pivot_stack_words(buckets[b].W, kmax, buckets[b].D));
@@ -2579,6 +2599,8 @@ int search_count_all(const dist_graph* g, int kmax, const dist_config& cfg, u64*
     prm.deadline = deadline;
     prm.per_root = per_root;
     prm.per_root_k = per_root ? per_root_k : -1;
+    prm.nsub = nsubs[b];
+    prm.split_depth = sdepth[b];
     const size_t lds = pivot_lds_bytes(bk.W, cfg.fingerprint, bk.D);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, g_ws.cursor, 64);
     hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, g_ws.wave_out, (u64)grids[b] * kPivWords);

@@ -93,6 +93,28 @@ def test_powerlaw_every_k_and_per_root(D, oracle_mod):
     assert got == want
 
 
+@pytest.mark.parametrize("nsub", [2, 3, 7, 64])
+def test_split_roots_every_k(D, oracle_mod, nsub):
+    """Roots shared by nsub work units (the units deal out the tree nodes at
+    depth 2; leaves above count once): every k and the per-root results
+    unchanged, against the oracle."""
+    for name, g in (("fig2", gg.fig2()), ("gnp", gg.gnp(60, 0.6, 77)), ("turan", gg.turan(40, 10))):
+        res, G = _all(D, g, 10, D.ORDER_DEGREE, sub_units=nsub)
+        for k in range(1, 11):
+            print("split pivot", nsub, name, k, flush=True)
+            assert res[k] == oracle_mod.count(g.row_ptr, g.col, k), (nsub, name, k)
+    g = gg.small_powerlaw()
+    G = D.orient(g.row_ptr, g.col)
+    per = np.zeros(3 * g.n, np.uint64)
+    res, rc = D.count_all(G, 6, cfg=D.config(sub_units=nsub), per_root=per, per_root_k=5)
+    assert rc == D.OK
+    for k in range(1, 7):
+        assert res[k] == oracle_mod.count(g.row_ptr, g.col, k), (nsub, k)
+    want = oracle_mod.count_roots(g.row_ptr, g.col, 5, np.arange(g.n, dtype=np.int32))
+    got = [(int(per[3 * v]) | (int(per[3 * v + 1]) << 64), int(per[3 * v + 2])) for v in range(g.n)]
+    assert got == want
+
+
 def test_large_graph_golden_totals(D):
     """The one-large-graph workload (Chung-Lu n = 10^6): one call gives k = 5,
     7 and 9, equal to the oracle's totals (tests/golden/cfg2_totals.json),

@@ -298,7 +298,8 @@ int dist_ist_inspect(const dist_graph* g, int k, int32_t root,
                      void* hip_stream);
 
 /* Count many (graph, k) pairs in one persistent launch per bitmap width
- * class (at most five launches for the whole batch).  gs[i], ks[i] for
+ * class (at most DIST_WIDTH_CLASSES launches for the whole batch; with
+ * per-pair budgets, one such set per cost tier).  gs[i], ks[i] for
  * i < n (the same graph may appear with several k); out[i] receives the
  * result of pair i.  The launch sequence is captured as a HIP graph and
  * replayed when the same batch (same graphs, ks and switches) is submitted
@@ -321,6 +322,32 @@ int dist_count_batch_ex(const dist_graph* const* gs, const int* ks, int n,
                         const dist_config* cfg, int use_graph,
                         const int64_t* pair_deadline_ms, void* hip_stream,
                         dist_result* out, int* pair_status, double* ms);
+
+/* Per-pair switches of dist_count_batch_tuned; a negative field (or, for
+ * min_width, 0) takes the value of the batch's cfg.  min_width: smallest
+ * bitmap width in words given to the pair's roots (one of DIST_WIDTHS;
+ * larger values put the pair's narrow roots into wider launches);
+ * chunk_work: the pair's work-unit size (as dist_config.chunk_work; 0 =
+ * automatic); memo: 0, 1 or 2 as dist_config.memo.  None of them changes a
+ * result. */
+typedef struct dist_pair_switches {
+  int32_t min_width;
+  int32_t chunk_work;
+  int32_t memo;
+  int32_t reserved;  /* 0 */
+} dist_pair_switches;
+
+/* dist_count_batch_ex with switches chosen per pair (sw[i] for pair i; sw
+ * NULL = dist_count_batch_ex): an autotuner that picks the switches per
+ * size bucket of a batch still runs the whole batch as one launch per width
+ * class, captured and replayed like dist_count_batch_ex (a replay requires
+ * the same switches too).  Returns DIST_E_INVALID for a switch out of range;
+ * otherwise as dist_count_batch_ex. */
+int dist_count_batch_tuned(const dist_graph* const* gs, const int* ks, int n,
+                           const dist_config* cfg,
+                           const dist_pair_switches* sw, int use_graph,
+                           const int64_t* pair_deadline_ms, void* hip_stream,
+                           dist_result* out, int* pair_status, double* ms);
 
 /* Called from the thread of dist_count_batch_stream as soon as pair `pair`
  * is finished on the device (or cut off by its budget), while the rest of

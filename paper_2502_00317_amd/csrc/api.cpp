@@ -235,6 +235,22 @@ int dist_count_batch_ex(const dist_graph* const* gs, const int* ks, int n, const
                             ms);
 }
 
+int dist_count_batch_tuned(const dist_graph* const* gs, const int* ks, int n, const dist_config* cfg,
+                           const dist_pair_switches* sw, int use_graph, const int64_t* pair_deadline_ms,
+                           void* hip_stream, dist_result* out, int* pair_status, double* ms) {
+  if (n < 0 || (n > 0 && (!gs || !ks || !out))) return DIST_E_INVALID;
+  if (n == 0) return DIST_OK;
+  for (int i = 0; sw && i < n; ++i) {
+    const dist_pair_switches& w = sw[i];
+    if (w.min_width > 16 || w.memo > 2 || w.reserved != 0) return DIST_E_INVALID;
+  }
+  dist_config c;
+  if (cfg) c = *cfg;
+  else dist_config_init(&c);
+  return search_count_batch(gs, ks, n, c, use_graph, pair_deadline_ms, (hipStream_t)hip_stream, out, pair_status,
+                            ms, nullptr, nullptr, nullptr, sw);
+}
+
 int dist_count_batch_stream(const dist_graph* const* gs, const int* ks, int n, const dist_config* cfg,
                             const int64_t* pair_deadline_ms, const double* pair_cost, void* hip_stream,
                             dist_result* out, int* pair_status, dist_pair_done on_done, void* user) {

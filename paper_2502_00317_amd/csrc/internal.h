@@ -58,7 +58,7 @@ int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out,
 int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const dist_config& cfg, int use_graph,
                        const int64_t* pair_deadline_ms, hipStream_t s, dist_result* out, int* pair_status,
                        double* ms, dist_pair_done on_done = nullptr, void* user = nullptr,
-                       const double* pair_cost = nullptr);
+                       const double* pair_cost = nullptr, const dist_pair_switches* sw = nullptr);
 
 // Upper bound on the search size of (g, k): sum over roots of C(d+, k - 1).
 double estimate_cost(const dist_graph* g, int k);

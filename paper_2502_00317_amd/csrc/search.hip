@@ -78,6 +78,8 @@ struct BatchGraph {
   int32_t k;
   int32_t own_clock;  // 1: the budget runs from the pair's first unit; 0: from the batch's
   u64 budget;         // wall-clock ticks this pair may use; 0 = no limit
+  int32_t memo = -1;  // this pair's memo switch; < 0: the launch's
+  int32_t pad_ = 0;
 };
 
 struct BatchSeg {
@@ -731,6 +733,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
   extern __shared__ __align__(16) char smem[];
   const int lane = lane_id();
   int k = p.k;  // batch mode: the largest k of the launch (sizes the stacks)
+  int memo_mode = p.memo;  // batch mode: the unit's pair's
   const Lds s = carve<W>(smem, p.k, FP, p.drows);
   const int ES = W + 4;
   u64* table = p.memo_base ? p.memo_base + (u64)blockIdx.x * (p.memo_mask + 1) * ES : nullptr;
@@ -790,6 +793,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
       k = bgr.k;
       pair_budget = bgr.budget;
       own_clock = bgr.own_clock;
+      memo_mode = bgr.memo >= 0 ? bgr.memo : p.memo;
     }
     pair_deadline = 0;
     if (p.pair_t0) {
@@ -887,7 +891,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
     int j = 0;
     enum { ENTER, NEXT, FINISH } mode = ENTER;
     u64 r_look = 0, r_hit = 0;  // this root's memo lookups and hits
-    bool memo_live = table != nullptr;
+    bool memo_live = table != nullptr && memo_mode != 0;
     u64 res_lo = 0, res_hi = 0, res_fp = 0;
     bool stop = false, unit_cancel = false;
     while (true) {
@@ -926,8 +930,8 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
           continue;
         }
         bool memo_j = false;
-        if (p.memo == 2) memo_j = (l >= 3);
-        else if (p.memo == 1) memo_j = (l >= 3) && j > 0 && s.stMemo[j - 1];
+        if (memo_mode == 2) memo_j = (l >= 3);
+        else if (memo_mode == 1) memo_j = (l >= 3) && j > 0 && s.stMemo[j - 1];
         const u64 tag = (root_tag << 8) | (u64)l;
         if (memo_j && memo_live && j > 0 && j != jsplit) {
           ++n_look;
@@ -1094,7 +1098,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             }
           }
         }
-        if (!memo_j && p.memo == 1 && memo_live) {
+        if (!memo_j && memo_mode == 1 && memo_live) {
           // criterion (1) in integer form: 2 m l > (l - 1) n^2
           u64 lhs = 2ull * m_edges * (u64)l;
           u64 rhs = (u64)(l - 1) * (u64)np * (u64)np;
@@ -1177,7 +1181,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             // first, without a frame push each.  The memo is used exactly as
             // by child frames: a child's set is looked up and stored under
             // l = 3, and after each child the prefix P & [x, inf) under l = 4.
-            const bool memo_c = p.memo == 2 || (p.memo == 1 && memo_j);
+            const bool memo_c = memo_mode == 2 || (memo_mode == 1 && memo_j);
             const u64 ctag = (root_tag << 8) | 3ull;
             __syncthreads();
             while (true) {
@@ -2722,6 +2726,7 @@ struct BatchWs {
   std::vector<int> ks;
   std::vector<int64_t> dls;
   dist_config cfg{};
+  std::vector<dist_pair_switches> sw;  // per-pair switches (empty: none)
   std::vector<int> status;
   std::vector<uint32_t> units;          // units per pair
   std::vector<BatchLaunch> launches;
@@ -2780,7 +2785,8 @@ u64 fold_p_host(u64 hi, u64 lo) {
 }
 
 int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int64_t* dls, int n,
-               const dist_config& cfg, hipStream_t s, bool stream_done, const double* pair_cost) {
+               const dist_config& cfg, hipStream_t s, bool stream_done, const double* pair_cost,
+               const dist_pair_switches* sw) {
   P->drop_graph();
   P->launches.clear();
   P->status.assign(n, DIST_OK);
@@ -2822,6 +2828,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return est[a] < est[b]; });
   }
   std::vector<uint32_t> rem_init(n > 0 ? n : 1, 0);
+  bool any_memo = false;
   for (int oi = 0; oi < n; ++oi) {
     const int i = order[oi];
     const int t = tier[i];
@@ -2829,6 +2836,11 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     const int k = ks[i];
     u64 budget = (dls && dls[i] > 0) ? (u64)dls[i] * (u64)rate_khz : 0;
     bg[i] = BatchGraph{g->dptr, g->dcol, g->orig, g->roots, g->gw, k, own_clock ? 1 : 0, budget};
+    // this pair's switches (< 0: the batch's)
+    const int pmw = (sw && sw[i].min_width > 0) ? sw[i].min_width : min_w;
+    const int pcw = (sw && sw[i].chunk_work >= 0) ? sw[i].chunk_work : cw;
+    if (sw && sw[i].memo >= 0) bg[i].memo = sw[i].memo;
+    if ((sw && sw[i].memo >= 0 ? sw[i].memo : cfg.memo) != 0) any_memo = true;
     if (k < 2) continue;  // k = 1 is answered on the host side
     int32_t lo = 0, hi = g->n;
     while (lo < hi) {
@@ -2843,7 +2855,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     uint64_t* u = units64[t];
     uint64_t before = 0;
     for (int c = 0; c < kClasses; ++c) before += u[c];
-    add_segments(g, i, nroots, k, cw, false, min_w, sub_of, segs[t], units64[t], kmax[t]);
+    add_segments(g, i, nroots, k, pcw, false, pmw, sub_of, segs[t], units64[t], kmax[t]);
     uint64_t after = 0;
     for (int c = 0; c < kClasses; ++c) after += u[c];
     rem_init[i] = (uint32_t)(after - before);
@@ -2953,7 +2965,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
   if ((rc = grow_dev(&P->d_wave_out, P->cap_wave, (size_t)(maxgrid > 0 ? maxgrid : 1) * kOutWords))) return rc;
   u64 entries = 0;
   size_t memo_bytes = 0;
-  if (cfg.memo != 0 && maxgrid > 0) {
+  if (any_memo && maxgrid > 0) {
     size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)16 << 30);
     size_t es = (size_t)(maxW + 4) * 8;
     entries = cfg.memo_entries > 0 ? 1 : (1 << 16);
@@ -2976,6 +2988,8 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
   P->dls.assign(n, 0);
   if (dls) P->dls.assign(dls, dls + n);
   P->cfg = cfg;
+  P->sw.clear();
+  if (sw) P->sw.assign(sw, sw + n);
   P->serials.clear();
   for (int i = 0; i < n; ++i) P->serials.push_back(gs[i]->serial);
   return DIST_OK;
@@ -3008,7 +3022,7 @@ int enqueue_batch(BatchWs* P, hipStream_t s) {
 
 int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const dist_config& cfg, int use_graph,
                        const int64_t* dls, hipStream_t s, dist_result* out, int* pair_status, double* ms,
-                       dist_pair_done on_done, void* user, const double* pair_cost) {
+                       dist_pair_done on_done, void* user, const double* pair_cost, const dist_pair_switches* sw) {
   if (on_done) use_graph = 0;
   for (int i = 0; i < n; ++i)
     if (!gs[i] || ks[i] < 1 || ks[i] > DIST_K_MAX) return gs[i] ? DIST_E_K : DIST_E_INVALID;
@@ -3028,7 +3042,7 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
     }
     DIST_CHECK(hipDeviceSynchronize());
     int rc2 = search_count_batch(gs, ks, n, cfg, use_graph, dls, own, out, pair_status, ms, on_done, user,
-                                 pair_cost);
+                                 pair_cost, sw);
     DIST_CHECK(hipStreamSynchronize(own));
     return rc2;
   }
@@ -3049,12 +3063,13 @@ int search_count_batch(const dist_graph* const* gs, const int* ks, int n, const 
   bool reuse = use_graph && P->exec && P->n == n && same_cfg(P->cfg, cfg) &&
                std::equal(P->ks.begin(), P->ks.end(), ks) && (int)P->serials.size() == n;
   for (int i = 0; i < n && reuse; ++i) reuse = P->serials[i] == gs[i]->serial && P->dls[i] == (dls ? dls[i] : 0);
+  if (reuse) reuse = sw ? (P->sw.size() == (size_t)n && memcmp(P->sw.data(), sw, sizeof(*sw) * n) == 0) : P->sw.empty();
   hipEvent_t e0, e1;
   DIST_CHECK(hipEventCreate(&e0));
   DIST_CHECK(hipEventCreate(&e1));
   int rc = DIST_OK;
   if (!reuse) {
-    rc = plan_batch(P, gs, ks, dls, n, cfg, s, on_done != nullptr, pair_cost);
+    rc = plan_batch(P, gs, ks, dls, n, cfg, s, on_done != nullptr, pair_cost, sw);
     if (rc) {
       P->drop_graph();
       return rc;

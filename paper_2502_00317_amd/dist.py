@@ -51,6 +51,13 @@ class Result(ctypes.Structure):
         return int(self.count_lo) | (int(self.count_hi) << 64)
 
 
+class PairSwitches(ctypes.Structure):
+    """dist_pair_switches: per-pair min_width, chunk_work, memo (< 0: the
+    batch's; min_width 0 also)."""
+    _fields_ = [("min_width", ctypes.c_int32), ("chunk_work", ctypes.c_int32),
+                ("memo", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("roots", ctypes.c_uint64), ("roots_pruned", ctypes.c_uint64),
                 ("frames", ctypes.c_uint64), ("word_ops", ctypes.c_uint64),
@@ -130,6 +137,12 @@ def _load():
                                         ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_double)]
     lib.dist_count_batch_ex.restype = ctypes.c_int
+    lib.dist_count_batch_tuned.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
+                                           ctypes.c_int, ctypes.POINTER(Config), ctypes.POINTER(PairSwitches),
+                                           ctypes.c_int, ctypes.POINTER(ctypes.c_int64), vp,
+                                           ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_double)]
+    lib.dist_count_batch_tuned.restype = ctypes.c_int
     lib.dist_count_batch_stream.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int),
                                             ctypes.c_int, ctypes.POINTER(Config),
                                             ctypes.POINTER(ctypes.c_int64),
@@ -323,6 +336,32 @@ def count_batch(graphs, ks, cfg: Config | None = None, use_graph=True, stream=No
     if with_status:
         return res, rc, ms.value, [int(st[i]) for i in range(n)]
     return res, rc, ms.value
+
+
+def count_batch_tuned(graphs, ks, switches, cfg: Config | None = None, use_graph=True, stream=None,
+                      deadlines_ms=None):
+    """dist_count_batch_tuned: count_batch with per-pair switches; switches[i]
+    is a dict with any of min_width, chunk_work, memo (missing: the batch's).
+    Returns ([(count, fp)] per pair, status, device ms)."""
+    n = len(graphs)
+    arr = (ctypes.c_void_p * max(n, 1))(*[g.handle for g in graphs])
+    karr = (ctypes.c_int * max(n, 1))(*[int(k) for k in ks])
+    sw = (PairSwitches * max(n, 1))()
+    for i, d in enumerate(switches):
+        sw[i].min_width = int(d.get("min_width", 0))
+        sw[i].chunk_work = int(d.get("chunk_work", -1))
+        sw[i].memo = int(d.get("memo", -1))
+    out = (Result * max(n, 1))()
+    st = (ctypes.c_int * max(n, 1))()
+    dl = None
+    if deadlines_ms is not None:
+        dl = (ctypes.c_int64 * max(n, 1))(*[int(x) for x in deadlines_ms])
+    ms = ctypes.c_double(0)
+    rc = _load().dist_count_batch_tuned(arr, karr, n, ctypes.byref(cfg) if cfg is not None else None, sw,
+                                        1 if use_graph else 0, dl, _stream_ptr(stream), out, st, ctypes.byref(ms))
+    if rc not in (OK, E_OVERFLOW, E_CANCELLED):
+        _check(rc, "dist_count_batch_tuned")
+    return [(out[i].count, int(out[i].fp)) for i in range(n)], rc, ms.value
 
 
 def count_batch_stream(graphs, ks, on_done, cfg: Config | None = None, stream=None,

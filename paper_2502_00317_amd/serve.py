@@ -174,13 +174,22 @@ class Server:
     plain      -- one query at a time through the per-graph call (the
                   baseline without batching);
     stream_results -- complete each query as soon as the device reports it,
-                  not when its whole batch ends.
+                  not when its whole batch ends;
+    router_table -- routing state to start from (router_state() of an
+                  earlier run): the per-k thresholds of both lanes, the
+                  (graph, k) known to be heavy or hopeless, and measured
+                  service times;
+    learn      -- update that state from this run's completions (False: the
+                  table is frozen, so routing, shedding and batch order
+                  depend only on the arrival stream, and p50/p99 repeat from
+                  the seed up to device timing).
     """
 
     def __init__(self, backend, pool_handles: dict, slots: int = 2,
                  mem_limit: int = 1 << 62, pool_bytes: int = 0, max_batch: int = 4096,
                  clock=time.perf_counter, stream_results: bool = True, express_ms: int = 0,
-                 plain: bool = False, express_batch_ms: float = 0.0, shed_frac: float = 0.0):
+                 plain: bool = False, express_batch_ms: float = 0.0, shed_frac: float = 0.0,
+                 router_table: dict | None = None, learn: bool = True):
         self.stream_results = stream_results
         self.pool_bytes = pool_bytes
         self.backend = backend
@@ -215,6 +224,32 @@ class Server:
         self.errors = []
         self._batch_ids = 0
         self._running = {}    # slot -> batch id while a batch runs
+        self.learn = learn
+        if router_table:
+            self.load_router(router_table)
+
+    # ---- routing state ----------------------------------------------------------
+    def router_state(self) -> dict:
+        """The routing state as JSON-serialisable data (see load_router)."""
+        def per_k(d):
+            return {str(k): v for k, v in sorted(d.items()) if math.isfinite(v)}
+
+        def per_pair(d):
+            return [[int(g), int(k), float(v)] for (g, k), v in sorted(d.items())]
+
+        return {"light_max": per_k(self.light_max), "heavy_min": per_k(self.heavy_min),
+                "bulk_light_max": per_k(self.bulk_light_max), "bulk_heavy_min": per_k(self.bulk_heavy_min),
+                "heavy": [[int(g), int(k)] for g, k in sorted(self.heavy)],
+                "bulk_cut_ms": per_pair(self.bulk_cut_ms), "service_ms": per_pair(self.service_ms)}
+
+    def load_router(self, t: dict):
+        self.light_max = {int(k): float(v) for k, v in t.get("light_max", {}).items()}
+        self.heavy_min = {int(k): float(v) for k, v in t.get("heavy_min", {}).items()}
+        self.bulk_light_max = {int(k): float(v) for k, v in t.get("bulk_light_max", {}).items()}
+        self.bulk_heavy_min = {int(k): float(v) for k, v in t.get("bulk_heavy_min", {}).items()}
+        self.heavy = {(int(g), int(k)) for g, k in t.get("heavy", [])}
+        self.bulk_cut_ms = {(int(g), int(k)): float(v) for g, k, v in t.get("bulk_cut_ms", [])}
+        self.service_ms = {(int(g), int(k)): float(v) for g, k, v in t.get("service_ms", [])}
 
     # ---- lifecycle ------------------------------------------------------------
     def start(self):
@@ -365,6 +400,19 @@ class Server:
     def _settle(self, lane, q, res, status, cut, t, dms=-1.0):
         """A reported pair: complete it, or move it to the bulk lane when the
         express lane's budget (not its own) cut it off.  Lock held."""
+        if self.learn:
+            self._learn(lane, q, status, cut, dms)
+        if status == "dnf" and lane == "express" and cut:
+            q.lane = "bulk"
+            q.moves += 1
+            self.demoted += 1
+            self.queues["bulk"].append(q)
+            self.cv.notify_all()
+            return
+        self._complete(q, res[0], res[1], status, t)
+
+    def _learn(self, lane, q, status, cut, dms):
+        """Routing state from a reported pair.  Lock held."""
         if q.adhoc is None and status in ("ok", "overflow") and dms >= 0:
             self.service_ms[(q.graph, q.k)] = dms
         if q.adhoc is None and lane == "bulk" and status == "dnf" and dms >= 0:
@@ -379,16 +427,8 @@ class Server:
                 self.light_max[q.k] = max(self.light_max.get(q.k, -1.0), q.est)
             elif status == "dnf" and cut:
                 self.heavy_min[q.k] = min(self.heavy_min.get(q.k, float("inf")), q.est)
-        if status == "dnf" and lane == "express" and cut:
-            if q.adhoc is None:
-                self.heavy.add((q.graph, q.k))
-            q.lane = "bulk"
-            q.moves += 1
-            self.demoted += 1
-            self.queues["bulk"].append(q)
-            self.cv.notify_all()
-            return
-        self._complete(q, res[0], res[1], status, t)
+        if status == "dnf" and lane == "express" and cut and q.adhoc is None:
+            self.heavy.add((q.graph, q.k))
 
     def _predict_ms(self, q):
         ms = self.service_ms.get((q.graph, q.k)) if q.adhoc is None else None

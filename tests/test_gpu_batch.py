@@ -108,3 +108,24 @@ def test_estimate_cost_orders_work(D):
     z = gg.empty(4)
     e = D.orient(z.row_ptr, z.col)
     assert D.estimate_cost(e, 3) == 0.0
+
+
+def test_per_pair_switches(D, oracle_mod):
+    """dist_count_batch_tuned: random per-pair (min_width, chunk_work, memo)
+    give every pair the oracle's result, in replays of the captured graph
+    too; new switches are planned afresh; a switch out of range is
+    rejected."""
+    graphs, ks = _small_batch(seed=23)
+    G = [D.orient(g.row_ptr, g.col) for g in graphs]
+    want = [oracle_mod.count(g.row_ptr, g.col, k) for g, k in zip(graphs, ks)]
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        sw = [dict(min_width=int(rng.choice([0, 1, 2, 4, 8])), chunk_work=int(rng.choice([-1, 0, 64, 512])),
+                   memo=int(rng.choice([-1, 0, 1, 2]))) for _ in ks]
+        for rep in range(3):
+            print("tuned batch", trial, rep, flush=True)
+            got, rc, ms = D.count_batch_tuned(G, ks, sw, cfg=D.config(memo=1), use_graph=True)
+            assert rc in (D.OK, D.E_OVERFLOW)
+            assert got == want, (trial, rep)
+    with pytest.raises(D.DistError):
+        D.count_batch_tuned(G, ks, [dict(memo=3)] * len(ks))

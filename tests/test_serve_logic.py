@@ -282,3 +282,58 @@ def test_summary_charges_unfinished_queries_their_budget():
     assert abs(s["p50_ms"] - 10.0) < 1e-6
     assert abs(s["p99_ms"] - 2000.0) < 1e-6          # the unfinished tail, at its budget
     assert abs(s["p99_completed_ms"] - 10.0) < 1e-6
+
+
+def test_router_table_round_trip_and_frozen_routing(oracle_mod):
+    """The routing state learned in one run, stored and loaded into a new
+    server with learning off, routes a new query by the stored threshold
+    (no express attempt), and stays unchanged by the run."""
+    import json
+    graphs, handles = _pool(4)              # n = 200, 350, 500, 650
+    cost = lambda g, k: 120.0 if g.n >= 500 else 1.0
+    mk = lambda: FakeBackend(oracle_mod, cost, seconds_per_cost=1e-3, estimate_fn=lambda g, k: float(g.n))
+    srv = Server(mk(), handles, slots=2, express_ms=20)
+    srv.start()
+    replay(srv, [Query(qid=0, k=4, t_arrival=0.0, graph=2, deadline_ms=5000),
+                 Query(qid=1, k=4, t_arrival=0.0, graph=0, deadline_ms=5000)])
+    srv.stop()
+    table = json.loads(json.dumps(srv.router_state()))   # as stored on disk
+    assert table["heavy_min"] == {"4": 500.0} and table["light_max"] == {"4": 200.0}
+    assert table["heavy"] == [[2, 4]]
+    frozen = Server(mk(), handles, slots=2, express_ms=20, router_table=table, learn=False)
+    assert frozen.router_state() == table
+    frozen.start()
+    qs = [Query(qid=2, k=4, t_arrival=0.0, graph=3, deadline_ms=5000),   # 650 >= 500: bulk at once
+          Query(qid=3, k=4, t_arrival=0.0, graph=1, deadline_ms=5000),   # 350: express
+          Query(qid=4, k=5, t_arrival=0.0, graph=3, deadline_ms=5000)]   # k = 5: express, cut, bulk
+    replay(frozen, qs)
+    frozen.stop()
+    assert qs[0].lane == "bulk" and qs[0].moves == 0
+    assert qs[1].lane == "express"
+    assert qs[2].moves == 1
+    assert frozen.router_state() == table                                # nothing learned
+    for q in qs:
+        g = graphs[q.graph]
+        assert q.status == "ok" and (q.count, q.fp) == oracle_mod.count(g.row_ptr, g.col, q.k)
+
+
+def test_frozen_router_repeats_lanes(oracle_mod):
+    """Two runs of one seeded stream under the same frozen table take the
+    same lane decisions for every query."""
+    graphs, handles = _pool(4)
+    cost = lambda g, k: 60.0 if (g.n >= 500 and k >= 5) else 1.0
+    table = {"heavy_min": {"5": 500.0}, "light_max": {"5": 350.0}, "heavy": [[3, 6]]}
+    runs = []
+    for _ in range(2):
+        be = FakeBackend(oracle_mod, cost, seconds_per_cost=1e-3, estimate_fn=lambda g, k: float(g.n))
+        srv = Server(be, handles, slots=2, express_ms=20, router_table=table, learn=False)
+        rng = np.random.default_rng(11)
+        t = np.cumsum(rng.exponential(1 / 200.0, size=40))
+        qs = [Query(qid=i, k=int(rng.integers(3, 7)), t_arrival=float(t[i]), graph=int(rng.integers(0, 4)),
+                    deadline_ms=5000) for i in range(40)]
+        srv.start()
+        replay(srv, qs)
+        srv.stop()
+        assert all(q.status == "ok" for q in qs)
+        runs.append([(q.lane, q.moves) for q in qs])
+    assert runs[0] == runs[1]

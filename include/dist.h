@@ -122,6 +122,17 @@ typedef struct {
   int64_t list_bytes;    /* listing: device record buffer in bytes; 0 = auto
                             (512 MiB).  Roots are listed in batches whose
                             records fit it; one root's records must fit */
+  int64_t trie_tau;      /* counting with memo != 0: 0 = each root keeps its
+                            own memo entries (keyed by the root's local ids);
+                            tau > 0 = the Induced Subgraph Trie is shared by
+                            the consecutive roots a wavefront takes (it takes
+                            runs of 8 work units), Section VI: nodes are
+                            keyed by their vertex sets as global ranks (sets
+                            of up to 60 vertices), the table is cleared before
+                            the next root once more than tau nodes were
+                            inserted since the last clear (soft bound), and
+                            no node is inserted past 2 tau (hard bound).
+                            Results do not depend on it */
 } dist_config;
 
 typedef struct {

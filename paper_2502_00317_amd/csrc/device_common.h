@@ -115,6 +115,7 @@ struct Lds {
   u64* stCnt;    // (k-1) * 2
   u64* stFp;     // (k-1)
   u64* R;        // W   (soft-embedding level bitmap)
+  u64* ctl;      // 4   (per-wave state used once per work unit or memo call)
   int32_t* nb;      // D       (build)
   int32_t* rowbeg;  // D + 1   (build)
   int32_t* rowptr;  // D       (build)
@@ -147,7 +148,7 @@ __host__ __device__ inline int lds_rows(int W, int dmax) {
 // fp = 0 leaves out the fingerprint weights (8 D bytes).
 __host__ __device__ inline size_t lds_bytes(int W, int k, int fp, int Drows) {
   size_t D = (size_t)Drows, L = (size_t)(k > 1 ? k - 1 : 1);
-  size_t b = 8 * (D * W + (fp ? D : 0) + wtab_words(W, fp) + 2 * L * W + 3 * L + W);
+  size_t b = 8 * (D * W + (fp ? D : 0) + wtab_words(W, fp) + 2 * L * W + 3 * L + W + 4);
   size_t build = 4 * (3 * D + 1), post = 5 * D;
   b += align8(build > post ? build : post);
   b += align8(3 * L);
@@ -175,6 +176,7 @@ __device__ inline Lds carve(char* base, int k, int fp, int Drows) {
   s.stCnt = p; p += 2 * L;
   s.stFp = p; p += L;
   s.R = p; p += W;
+  s.ctl = p; p += 4;
   char* u = (char*)p;
   s.nb = (int32_t*)u;
   s.rowbeg = s.nb + D;

@@ -126,6 +126,8 @@ struct Params {
   const u64* epoch;          // if set, root tags start at *epoch + tag_base
   u64 deadline;     // wall_clock64() limit; 0 = none
   int* abort_flag;
+  u64 tau;          // > 0: memo shared by the consecutive roots of a wave (see below)
+  uint32_t chunk;   // units a wave takes from the cursor at a time (>= 1)
 };
 
 
@@ -152,12 +154,143 @@ __device__ __forceinline__ u64 memo_hash(u64 tag, const u64* P, int x) {
 // a node's prefixes together, costs one memory latency and each lane holds a
 // single word.
 
+// ---- the shared form (p.tau > 0) ---------------------------------------------
+// Section VI keeps one Induced Subgraph Trie for the consecutive depth-1
+// subtasks a thread takes, bounded by tau nodes: past tau it is cleared
+// before the next subtask, and it never grows past 2 tau.  Here a wave's table
+// lives on across the roots it takes (units come in runs of consecutive
+// roots), so a node must be named by something every root agrees on: its
+// vertex set as global ranks, not as a root's local ids.  An entry holds the
+// tag (the wave's clear tag << 8 | l), a hash of the ranks, their number and
+// the ranks themselves (two per word), so a hit is an exact match of the set.
+// Sets of more than kShMax members are not memoised in this form.  The count
+// (and fingerprint) of the l-cliques of G[S] depends on S alone -- pruning and
+// closed forms never change it -- so an entry made under one root is valid
+// under every other root of the same graph.
+constexpr int kShMax = 60;
+constexpr uint32_t kShChunk = 8;  // units a wave takes at a time in the shared form
+constexpr int kShES = 6 + kShMax / 2;  // entry words
+
+// Position of the t-th set bit of v (t < popcount(v)).
+__device__ __forceinline__ int select_bit(u64 v, int t) {
+  int pos = 0;
+#pragma unroll
+  for (int sh = 32; sh >= 1; sh >>= 1) {
+    const u64 low = (1ull << sh) - 1;
+    const int c = __popcll(v & low);
+    if (t >= c) {
+      t -= c;
+      v >>= sh;
+      pos += sh;
+    } else {
+      v &= low;
+    }
+  }
+  return pos;
+}
+
+// The members of P & [x, inf) as global ranks (nbr: the root's out-neighbour
+// list, local id i = nbr[i]); lane t holds the t-th (ranks ascend with local
+// ids), h their hash.  Returns their number, or -1 past kShMax.
+template <int W>
+__device__ __forceinline__ int shared_key(const u64 (&P)[W], int x, const int32_t* nbr, uint32_t& rank, u64& h) {
+  const int lane = lane_id();
+  int base = 0, mine = -1;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const u64 bits = P[w] & cut_mask(x, w);
+    const int c = __popcll(bits);
+    if (lane >= base && lane < base + c) mine = w * 64 + select_bit(bits, lane - base);
+    base += c;
+  }
+  if (base > kShMax) return -1;
+  rank = mine >= 0 ? (uint32_t)nbr[mine] : 0xffffffffu;
+  u64 z = mine >= 0 ? ((u64)rank + 1) * 0x9E3779B97F4A7C15ull : 0ull;
+  z = (z ^ (z >> 31)) * 0xBF58476D1CE4E5B9ull;
+  h = wave_sum(mine >= 0 ? (z ^ (z >> 29)) : 0ull) + (u64)base;
+  h ^= h >> 32;
+  return base;
+}
+
+// Entry word w of the shared form for the key (tag, ranks in lanes, n).
+// Wave-collective (lane shuffles): call it on every lane.
+__device__ __forceinline__ u64 shared_word(int w, u64 tag, u64 h, int n, uint32_t rank) {
+  const int i = w >= 6 ? w - 6 : 0;
+  const uint32_t r0 = (uint32_t)__shfl((int)rank, 2 * i);
+  const uint32_t r1 = (2 * i + 1 < n) ? (uint32_t)__shfl((int)rank, 2 * i + 1) : 0xffffffffu;
+  if (w == 0) return tag;
+  if (w == 1) return h;
+  if (w == 2) return (u64)n;
+  return ((u64)r1 << 32) | r0;
+}
+
+// Not inlined (the shared form is a mode of its own; inline, its key code
+// would add registers to every memo call of the search).  P is in LDS.
+struct ShHit {
+  u64 lo, hi, fp;
+  bool hit;
+};
+
+template <int W>
+__device__ __noinline__ ShHit shared_find(u64* table, u64 mask, u64 tag, const u64* P_, int x, const int32_t* nbr) {
+  const auto* P = as_lds(P_);
+  const int lane = lane_id();
+  ShHit r{0, 0, 0, false};
+  uint32_t rank = 0;
+  u64 h = 0;
+  u64 Pw[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) Pw[w] = P[w];
+  const int n = shared_key<W>(Pw, x, nbr, rank, h);
+  if (n < 0) return r;
+  const int w = lane;
+  u64 v = 0;
+  if (w < kShES) v = ld_wave(table + (h & mask) * kShES + w);
+  const u64 want = shared_word(w, tag, h, n, rank);
+  const bool ok = w >= kShES || (w >= 3 && w < 6) || (w >= 6 && 2 * (w - 6) >= n) || v == want;
+  if (__ballot(!ok)) return r;
+  r.lo = __shfl(v, 3);
+  r.hi = __shfl(v, 4);
+  r.fp = __shfl(v, 5);
+  r.hit = true;
+  return r;
+}
+
+template <int W>
+__device__ __noinline__ void shared_put(u64* table, u64 mask, u64 tag, const u64* P_, int x, const int32_t* nbr,
+                                        u64 lo, u64 hi, u64 fp) {
+  const auto* P = as_lds(P_);
+  const int lane = lane_id();
+  uint32_t rank = 0;
+  u64 h = 0;
+  u64 Pw[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) Pw[w] = P[w];
+  const int n = shared_key<W>(Pw, x, nbr, rank, h);
+  if (n < 0) return;
+  const u64 kw = shared_word(lane, tag, h, n, rank);  // every lane: it reads ranks across lanes
+  const u64 v = lane == 3 ? lo : (lane == 4 ? hi : (lane == 5 ? fp : kw));
+  if (lane < kShES) table[(h & mask) * kShES + lane] = v;
+}
+
 // Wave-collective lookup of the keys P & [cut_i, inf), i = 0..ncut-1, where
 // cut_i = cuts[i] (cuts == nullptr: one key, no cut).  Returns the smallest i
 // whose key is in the table (its count and fingerprint in lo, hi, fp), or -1.
+// nbr (shared form only): the root's out-neighbour list; the shared form
+// takes one key per lookup.
 template <int W>
 __device__ __forceinline__ int memo_find(const Params& p, const u64* table, u64 tag, const u64* P,
-                                         const uint16_t* cuts, int ncut, u64& lo, u64& hi, u64& fp) {
+                                         const uint16_t* cuts, int ncut, u64& lo, u64& hi, u64& fp,
+                                         const int32_t* nbr = nullptr) {
+  if (p.tau) {
+    if (ncut != 1) return -1;
+    const ShHit r = shared_find<W>(const_cast<u64*>(table), p.memo_mask, tag, P, cuts ? (int)cuts[0] : -1, nbr);
+    if (!r.hit) return -1;
+    lo = r.lo;
+    hi = r.hi;
+    fp = r.fp;
+    return 0;
+  }
   constexpr int ES = W + 4;
   constexpr int GPR = kWave / ES;  // (key, slot) groups per round
   const int lane = lane_id();
@@ -192,7 +325,11 @@ __device__ __forceinline__ int memo_find(const Params& p, const u64* table, u64 
 // there is evicted).
 template <int W>
 __device__ __forceinline__ void memo_put(const Params& p, u64* table, u64 tag, const u64* P, int x, u64 lo, u64 hi,
-                                         u64 fp) {
+                                         u64 fp, const int32_t* nbr = nullptr, bool room = true) {
+  if (p.tau) {
+    if (room) shared_put<W>(table, p.memo_mask, tag, P, x, nbr, lo, hi, fp);
+    return;
+  }
   constexpr int ES = W + 4;
   const int lane = lane_id();
   if (lane < ES) {
@@ -735,7 +872,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
   int k = p.k;  // batch mode: the largest k of the launch (sizes the stacks)
   int memo_mode = p.memo;  // batch mode: the unit's pair's
   const Lds s = carve<W>(smem, p.k, FP, p.drows);
-  const int ES = W + 4;
+  const u64 ES = p.tau ? (u64)kShES : (u64)(W + 4);  // entry words
   u64* table = p.memo_base ? p.memo_base + (u64)blockIdx.x * (p.memo_mask + 1) * ES : nullptr;
 
   // per-wave totals (uniform) and per-lane counters
@@ -752,6 +889,19 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
 
   int cur_rel = -1;       // root whose G_u is in LDS
   int cur_pair = -1;
+  // shared memo state, in LDS (it is used once per unit or memo call):
+  // ctl[0] the wave's clear tag (~0: none yet), ctl[1] the inserts counted at
+  // its last clear, ctl[2] the wave's run of units (next | end << 32),
+  // ctl[3] the root's first arc (its out-neighbour list maps a memo key's
+  // local ids to ranks)
+  if (lane == 0) {
+    s.ctl[0] = ~0ull;
+    s.ctl[1] = 0;
+    s.ctl[2] = 0;
+    s.ctl[3] = 0;
+  }
+  __syncthreads();
+  auto room = [&]() { return !p.tau || n_ins - s.ctl[1] < 2 * p.tau; };  // hard bound 2 tau
   bool cur_pruned = false;
   const int32_t* Gdptr = nullptr;
   const int32_t* Gdcol = nullptr;
@@ -764,8 +914,26 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
   for (;;) {
     // ---- 0. next work unit: (root, range of depth-1 children) -------------------
     uint32_t u = 0;
-    if (lane == 0) u = atomicAdd(p.cursor, 1u);
-    u = __shfl(u, 0);
+    if (p.chunk > 1) {
+      // runs of consecutive units (consecutive roots), so that a shared memo
+      // sees neighbouring roots one after another
+      const u64 run = s.ctl[2];
+      uint32_t u_next = (uint32_t)run, u_end = (uint32_t)(run >> 32);
+      if (u_next >= u_end) {
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(p.cursor, p.chunk);
+        b = __shfl(b, 0);
+        u_next = b;
+        u_end = b + p.chunk;
+      }
+      u = u_next++;
+      __syncthreads();
+      if (lane == 0) s.ctl[2] = ((u64)u_end << 32) | u_next;
+      __syncthreads();
+    } else {
+      if (lane == 0) u = atomicAdd(p.cursor, 1u);
+      u = __shfl(u, 0);
+    }
     if (u >= p.units) break;
     // segment: consecutive roots of one (graph, k) pair, upr units each
     int lo = 0, hi = p.nsegs - 1;  // largest segment with unit_begin <= u
@@ -834,6 +1002,17 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
     // one tag per root (its first unit): chunks of a root share memo entries
     const u64 root_tag = tag0 + (u64)sg.unit_begin + (u64)(off / (uint32_t)upr) * (u64)upr;
     ++n_units;
+    if (p.tau && (s.ctl[0] == ~0ull || pair != cur_pair || (rel != cur_rel && n_ins - s.ctl[1] > p.tau))) {
+      // a new root past the soft bound tau (or a new graph): the shared memo
+      // starts empty (entries of earlier clear tags never match)
+      __syncthreads();
+      if (lane == 0) {
+        s.ctl[0] = root_tag;
+        s.ctl[1] = n_ins;
+      }
+      __syncthreads();
+    }
+    const u64 mtag = p.tau ? s.ctl[0] : root_tag;
 
     if (rel != cur_rel || pair != cur_pair) {
       cur_rel = rel;
@@ -841,6 +1020,9 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
       r = Groots[ridx];
       const int32_t beg = Gdptr[r];
       d = Gdptr[r + 1] - beg;  // <= 64 * W by the host's bucketing
+      __syncthreads();
+      if (lane == 0) s.ctl[3] = (u64)(uint32_t)beg;
+      __syncthreads();
       ++n_builds;
       // ---- 1. G_u in LDS ------------------------------------------------------
       arcs += build_subgraph<W>(s, Gdptr, Gdcol, Ggw, Gorig, nullptr, beg, d);
@@ -932,12 +1114,12 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
         bool memo_j = false;
         if (memo_mode == 2) memo_j = (l >= 3);
         else if (memo_mode == 1) memo_j = (l >= 3) && j > 0 && s.stMemo[j - 1];
-        const u64 tag = (root_tag << 8) | (u64)l;
+        const u64 tag = (mtag << 8) | (u64)l;
         if (memo_j && memo_live && j > 0 && j != jsplit) {
           ++n_look;
           ++r_look;
           u64 a, b, c;
-          if (memo_find<W>(p, table, tag, s.stP + j * W, nullptr, 1, a, b, c) >= 0) {
+          if (memo_find<W>(p, table, tag, s.stP + j * W, nullptr, 1, a, b, c, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr) >= 0) {
             ++n_hit;
             ++r_hit;
             res_lo = a; res_hi = b; res_fp = c;
@@ -985,7 +1167,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
                   res_hi = chi;
                   res_fp = cfp;
                   if (memo_j && memo_live) {
-                    memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+                    memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr, room());
                     ++n_ins;
                   }
                   __syncthreads();
@@ -999,7 +1181,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
               res_hi = chi;
               res_fp = FP ? esym_members<W>(s.mem, np, s.gl, 3) : 0;
                 if (memo_j && memo_live) {
-                memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+                memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr, room());
                 ++n_ins;
               }
               __syncthreads();
@@ -1036,7 +1218,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
           res_lo = wave_sum(c_acc);
           res_hi = 0;
           res_fp = FP ? wave_sum_p(f_acc) : 0;
-          if (memo_j && memo_live && j > 0) memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+          if (memo_j && memo_live && j > 0) memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr, room());
           if (memo_j && memo_live && j > 0) ++n_ins;
           __syncthreads();
           mode = FINISH;
@@ -1109,7 +1291,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             ++n_look;
             ++r_look;
             u64 a, b, c;
-            if (memo_find<W>(p, table, tag, s.stP + j * W, nullptr, 1, a, b, c) >= 0) {
+            if (memo_find<W>(p, table, tag, s.stP + j * W, nullptr, 1, a, b, c, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr) >= 0) {
               ++n_hit;
               ++r_hit;
               res_lo = a; res_hi = b; res_fp = c;
@@ -1135,7 +1317,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
           // m_i the i-th smallest member, i = 1..kMemoProbe, all probed at once
           const int ncut = np - 1 < kMemoProbe ? np - 1 : kMemoProbe;
           u64 a = 0, b = 0, c = 0;
-          const int hi_ = memo_find<W>(p, table, tag, s.stP + j * W, s.mem + 1, ncut, a, b, c);
+          const int hi_ = memo_find<W>(p, table, tag, s.stP + j * W, s.mem + 1, ncut, a, b, c, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr);
           n_look += (u64)ncut;
           r_look += (u64)ncut;
           if (hi_ >= 0) {
@@ -1182,7 +1364,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             // by child frames: a child's set is looked up and stored under
             // l = 3, and after each child the prefix P & [x, inf) under l = 4.
             const bool memo_c = memo_mode == 2 || (memo_mode == 1 && memo_j);
-            const u64 ctag = (root_tag << 8) | 3ull;
+            const u64 ctag = (mtag << 8) | 3ull;
             __syncthreads();
             while (true) {
               int x = -1;
@@ -1218,7 +1400,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
               if (memo_c && memo_live) {
                 ++n_look;
                 ++r_look;
-                if (memo_find<W>(p, table, ctag, Pn, nullptr, 1, clo, chi, cfp) >= 0) {
+                if (memo_find<W>(p, table, ctag, Pn, nullptr, 1, clo, chi, cfp, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr) >= 0) {
                   ++n_hit;
                   ++r_hit;
                   got = true;
@@ -1238,7 +1420,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
                 __syncthreads();
                 if (np2 >= 3) leaf3_count<W, FP>(s, Pc, np2, clo, chi, cfp, wops, bits);
                 if (memo_c && memo_live) {
-                  memo_put<W>(p, table, ctag, Pn, -1, clo, chi, cfp);
+                  memo_put<W>(p, table, ctag, Pn, -1, clo, chi, cfp, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr, room());
                   ++n_ins;
                 }
               }
@@ -1248,7 +1430,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
               if (FP) acc_fp = addp(acc_fp, mulp(s.gl[x], cfp));
               if (memo_j && memo_live && j > 0 && j != jsplit) {
                 // trie node P & [x, inf) is now complete for l = 4
-                memo_put<W>(p, table, tag, s.stP + j * W, x, acc_lo, acc_hi, acc_fp);
+                memo_put<W>(p, table, tag, s.stP + j * W, x, acc_lo, acc_hi, acc_fp, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr, room());
                 ++n_ins;
               }
               __syncthreads();
@@ -1258,7 +1440,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             res_hi = acc_hi;
             res_fp = acc_fp;
             if (memo_j && memo_live && j > 0 && j != jsplit) {
-              memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+              memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr, room());
               ++n_ins;
             }
             __syncthreads();
@@ -1296,7 +1478,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             u64 Pr[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) Pr[w] = s.stP[j * W + w];
-            memo_put<W>(p, table, (root_tag << 8) | (u64)l, s.stP + j * W, -1, res_lo, res_hi, res_fp);
+            memo_put<W>(p, table, (mtag << 8) | (u64)l, s.stP + j * W, -1, res_lo, res_hi, res_fp, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr, room());
             ++n_ins;
           }
           __syncthreads();
@@ -1332,7 +1514,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
         }
         if (s.stMemo[j] && memo_live && j > 0 && j != jsplit) {
           // trie node t_i = P & [x, inf) is now complete for l
-          memo_put<W>(p, table, (root_tag << 8) | (u64)l, s.stP + j * W, x, lo, hi, f);
+          memo_put<W>(p, table, (mtag << 8) | (u64)l, s.stP + j * W, x, lo, hi, f, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr, room());
           ++n_ins;
         }
         __syncthreads();
@@ -1812,7 +1994,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)16 << 30);
     int maxW = 1;
     for (size_t b = 0; b < nbk; ++b) maxW = buckets[b].W > maxW ? buckets[b].W : maxW;
-    size_t es = (size_t)(maxW + 4) * 8;
+    size_t es = (size_t)(base.tau ? kShES : maxW + 4) * 8;
     if (cfg.memo_entries > 0) {
       entries = 1;
       while (entries < (u64)cfg.memo_entries) entries <<= 1;
@@ -2028,6 +2210,8 @@ int search_count(const SearchLaunch& L, dist_result* out, dist_stats* st, bool n
   prm.soft_only = 0;
   prm.chunk_work = L.cfg.chunk_work;
   prm.per_root = L.per_root;
+  prm.tau = (L.cfg.trie_tau > 0 && !fixed) ? (u64)L.cfg.trie_tau : 0;  // no memo without allocation
+  prm.chunk = prm.tau ? kShChunk : 1;
   u64 tot[kOutWords];
   double ms = 0;
   rc = run_buckets(g, prm, nroots, L.cfg, s, tot, &ms, &stats, fixed);
@@ -2942,6 +3126,8 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     prm.prune = cfg.prune;
     prm.memo = cfg.memo;
     prm.fingerprint = cfg.fingerprint;
+    prm.tau = cfg.trie_tau > 0 ? (u64)cfg.trie_tau : 0;
+    prm.chunk = prm.tau ? kShChunk : 1;
     prm.cursor = P->d_cursor + (t * kClasses + b);
     prm.units = (uint32_t)units64[t][b];
     prm.chunk_work = cw;
@@ -2967,7 +3153,7 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
   size_t memo_bytes = 0;
   if (any_memo && maxgrid > 0) {
     size_t budget = cfg.memo_bytes > 0 ? (size_t)cfg.memo_bytes : ((size_t)16 << 30);
-    size_t es = (size_t)(maxW + 4) * 8;
+    size_t es = (size_t)(cfg.trie_tau > 0 ? kShES : maxW + 4) * 8;
     entries = cfg.memo_entries > 0 ? 1 : (1 << 16);
     if (cfg.memo_entries > 0)
       while (entries < (u64)cfg.memo_entries) entries <<= 1;

@@ -272,3 +272,65 @@ def test_large_k_nearly_complete(D, oracle_mod, removed, seed):
             assert c == want[0], (k, fp)
             if fp:
                 assert f == want[1], k
+
+
+@pytest.mark.parametrize("tau", [1, 64, 1 << 20])
+def test_shared_trie(D, oracle_mod, tau):
+    """The Induced Subgraph Trie shared by the consecutive roots a wave takes
+    (trie_tau = tau: cleared at a root once more than tau nodes were
+    inserted, never past 2 tau; nodes keyed by their vertex sets as global
+    ranks): per-root results and totals equal the oracle's under memo 1 and
+    2, with and without fingerprints and sub-units."""
+    P61 = (1 << 61) - 1
+    cases = [(gg.fig2(), (3, 4, 5)), (gg.gnp(80, 0.5, 3), (5, 7)), (_planted(150, 0.3, 40, 11), (5, 7)),
+             (gg.small_powerlaw(), (4, 6))]
+    for g, ks in cases:
+        G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+        for k in ks:
+            want = oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, np.arange(g.n, dtype=np.int32))
+            for cfg in (dict(memo=1), dict(memo=2), dict(memo=2, sub_units=3)):
+                for fp in (1, 0):
+                    print("shared trie", tau, g.name, k, cfg, fp, flush=True)
+                    per = np.zeros(3 * g.n, np.uint64)
+                    c, f, rc = D.count(G, k, cfg=D.config(trie_tau=tau, fingerprint=fp, **cfg), per_root=per)
+                    assert rc == D.OK
+                    got = [int(per[3 * v]) | (int(per[3 * v + 1]) << 64) for v in range(g.n)]
+                    assert got == [w for w, _ in want], (k, cfg, fp)
+                    assert c == sum(w for w, _ in want)
+                    if fp:
+                        assert [int(per[3 * v + 2]) for v in range(g.n)] == [x for _, x in want]
+                        assert f == sum(x for _, x in want) % P61
+
+
+def test_shared_trie_crosses_roots(D, oracle_mod):
+    """Two roots with the same out-neighbourhood (the situation N(u0) = N(u1)
+    of the paper's example): with the shared trie the second root finds the
+    nodes the first inserted, so it makes more memo hits than per-root memos
+    do, with the same results; the batched form clears the trie between
+    graphs, so equal vertex sets of different graphs never match."""
+    rng = np.random.default_rng(4)
+    iu, ju = np.triu_indices(24, 1)
+    keep = rng.random(len(iu)) < 0.7
+    a, b = list(iu[keep] + 2), list(ju[keep] + 2)
+    for twin in (0, 1):
+        a += [twin] * 24
+        b += list(range(2, 26))
+    g = gg.csr_from_edges(26, a, b, name="twins")
+    G = D.orient(g.row_ptr, g.col, order=D.ORDER_INPUT)
+    for k in (5, 6, 7):
+        want = oracle_mod.count(g.row_ptr, g.col, k)
+        hits = {}
+        for tau in (0, 1 << 20):
+            c, f, rc = D.count(G, k, cfg=D.config(memo=2, trie_tau=tau))
+            assert (c, f) == want, (k, tau)
+            hits[tau] = G.stats().memo_hits
+        print("twins", k, hits, flush=True)
+        assert hits[1 << 20] > hits[0], (k, hits)
+    # batches: the same vertex ids in different graphs
+    g2 = gg.gnp(26, 0.6, 9)
+    G2 = D.orient(g2.row_ptr, g2.col, order=D.ORDER_INPUT)
+    ks = [6, 6, 5, 7, 6]
+    graphs = [G, G2, G, G2, G2]
+    srcs = [g, g2, g, g2, g2]
+    res, rc, _ = D.count_batch(graphs, ks, cfg=D.config(memo=2, trie_tau=1 << 20))
+    assert res == [oracle_mod.count(x.row_ptr, x.col, k) for x, k in zip(srcs, ks)]

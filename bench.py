@@ -140,9 +140,9 @@ def summarize_profiles(d):
              "Commands (repository root, one MI355X; TMPDIR=/tmp):",
              "",
              "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $PWD/gpurun_out/pmc_FETCH_SIZE -o run -- \\",
-             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving",
+             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
              "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $PWD/gpurun_out/pmc_WRITE_SIZE -o run -- \\",
-             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving",
+             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
              "    rocprofv3 --pmc FETCH_SIZE (and WRITE_SIZE) ... -- python3 $PWD/bench.py --calib-copy 1024",
              "    python3 bench.py --summarize-profiles gpurun_out",
              "",
@@ -166,7 +166,7 @@ def summarize_profiles(d):
                  "",
                  "    export TMPDIR=/tmp",
                  "    rocprofv3 --kernel-trace --stats --output-format csv -d $PWD/gpurun_out/prof -o run -- \\",
-                 "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving",
+                 "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
                  "    python3 bench.py --summarize-profiles gpurun_out",
                  "",
                  "One orientation (degree order) and one dist_count per k (one launch per width",
@@ -197,6 +197,33 @@ def summarize_profiles(d):
         with open(os.path.join(ROOT, "profiles", "k_search_cfg2_kernel_stats.md"), "w") as f:
             f.write("\n".join(lines) + "\n")
     summarize_issue(d)
+    legs = glob.glob(os.path.join(d, "prof_legs", "*kernel_stats.csv"))
+    if legs:
+        lines = ["# rocprofv3 kernel summary: one bench step plus its pivot-based all-k and listing",
+                 "# sections (Chung-Lu n=1e6, k = 5, 7, 9; all k <= 9 by pivoting; listing on the",
+                 "# Chung-Lu n=1e4 graph, k = 4 and 6)",
+                 "",
+                 "Command (repository root, one MI355X):",
+                 "",
+                 "    export TMPDIR=/tmp",
+                 "    rocprofv3 --kernel-trace --stats --output-format csv -d $PWD/gpurun_out/prof_legs -o run -- \\",
+                 "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-cfg3",
+                 "    python3 bench.py --summarize-profiles gpurun_out",
+                 "",
+                 "k_pivot<W> counts every clique size by pivoting (one launch per width class);",
+                 "k_list_ist<W> lists cliques with the Induced Subgraph Trie (Algorithms 3 and 4).",
+                 "Kernel sources hash (search.hip, device_common.h): %s" % out["source_hash"],
+                 "",
+                 "| kernel | calls | total ms | average ms | % |",
+                 "|---|---|---|---|---|"]
+        for r in csv.DictReader(open(legs[0])):
+            name = r["Name"].replace("void (anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+            if float(r["Percentage"]) < 0.01:
+                continue
+            lines.append("| %s | %s | %.3f | %.3f | %.2f |" % (name, r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                                                           float(r["AverageNs"]) / 1e6, float(r["Percentage"])))
+        with open(os.path.join(ROOT, "profiles", "pivot_listing_kernel_stats.md"), "w") as f:
+            f.write("\n".join(lines) + "\n")
     print(json.dumps(out)[:400])
 
 
@@ -228,10 +255,10 @@ def summarize_issue(d):
              "",
              "    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_SMEM SQ_INSTS_BRANCH \\",
              "        SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR GRBM_GUI_ACTIVE --output-format csv -d $PWD/gpurun_out/sq_1 -o run -- \\",
-             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving",
+             "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
              "    rocprofv3 --pmc SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT SQ_BUSY_CYCLES SQ_WAVE_CYCLES \\",
              "        SQ_THREAD_CYCLES_VALU SQ_WAIT_INST_LDS SQ_ACTIVE_INST_ANY GRBM_COUNT --output-format csv \\",
-             "        -d $PWD/gpurun_out/sq_2 -o run -- python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving",
+             "        -d $PWD/gpurun_out/sq_2 -o run -- python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
              "    python3 bench.py --summarize-profiles gpurun_out",
              "",
              "Peaks (256 CUs, 2.4 GHz): VALU 614 G wave64 instructions/s (4 SIMDs per CU, one wave64",
@@ -716,6 +743,21 @@ def run_batched(a, dist, torch, specs, graphs, log):
     same_t = res_t == plain
     log("batched, per-bucket switches: %.3f s per batch (%.2fx the single best), same as plain: %s" % (
         tuned_s, batch_s / tuned_s, same_t))
+    # the Induced Subgraph Trie shared by the consecutive roots of a wave
+    # (soft bound tau, hard bound 2 tau) against the per-root memo, same switches
+    tau = 65536
+    scfg = dist.config(trie_tau=tau, **best)
+    res_s, rc, _ = dist.count_batch(G, ks, cfg=scfg, use_graph=True)
+    stimes = []
+    for _ in range(a.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r2, rc, _ = dist.count_batch(G, ks, cfg=scfg, use_graph=True)
+        torch.cuda.synchronize()
+        stimes.append(time.perf_counter() - t)
+        assert r2 == res_s
+    shared_s = float(np.median(stimes))
+    log("batched, shared trie (tau %d): %.3f s per batch, same as plain: %s" % (tau, shared_s, res_s == plain))
     for Gi in G:
         Gi.free()
     best_s = min(batch_s, tuned_s)
@@ -729,7 +771,9 @@ def run_batched(a, dist, torch, specs, graphs, log):
             "per_bucket": {"ms_per_batch": tuned_s * 1e3, "gain_vs_single_bucket": batch_s / tuned_s,
                            "buckets": {k: {"pairs": v["pairs"], "switches": v["switches"], "alone_ms": v["ms"]}
                                        for k, v in buckets.items()}},
-            "same_as_plain": same and same_t, "fingerprint": True}
+            "shared_trie": {"trie_tau": tau, "ms_per_batch": shared_s * 1e3, "vs_per_root_memo": batch_s / shared_s,
+                            "same_as_plain": res_s == plain},
+            "same_as_plain": same and same_t and res_s == plain, "fingerprint": True}
 
 
 def run_serving(a, dist, torch, inputs, log):

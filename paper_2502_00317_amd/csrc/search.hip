@@ -59,12 +59,18 @@ constexpr int kOutWords = 16;
 // insert is a plain store (no read first) and a lookup reads one entry.
 constexpr int kMemoProbe = 1;
 // A root stops using its memo table once at least kMemoMinLook lookups
-// found fewer than one hit in kMemoMinRatio (the table is a cache: using it
-// or not never changes a result).  Where the closed forms already cover the
-// dense branches, hits mostly save single leaf frames and do not repay the
-// lookups and inserts; one hit in four is about where they break even.
+// found fewer than one hit in kMemoMinRatio, or at least kMemoMinLook
+// inserts were answered by fewer than one hit in kMemoMinInsRatio (the table
+// is a cache: using it or not never changes a result).  Where the closed
+// forms already cover the dense branches, hits mostly save single leaf
+// frames and do not repay the lookups and inserts; one hit in four lookups
+// is about where they break even, and inserts (a trie node after each child)
+// outnumber lookups, so they are bounded on their own.
 constexpr int kMemoMinLook = 1024;
 constexpr int kMemoMinRatio = 4;
+constexpr int kMemoMinInsRatio = 8;
+constexpr u64 kMemoWaveIns = 4096;
+constexpr u64 kMemoWaveRatio = 16;
 
 // Batched counting: one entry per (graph, k) pair, and the units of a
 // launch as segments [unit_begin, next unit_begin) of consecutive roots of
@@ -1073,7 +1079,11 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
     int j = 0;
     enum { ENTER, NEXT, FINISH } mode = ENTER;
     u64 r_look = 0, r_hit = 0;  // this root's memo lookups and hits
-    bool memo_live = table != nullptr && memo_mode != 0;
+    const u64 r_ins0 = n_ins;   // and inserts, from here
+    // the same test over all of this wave's units so far: the roots of a
+    // launch are alike, so a wave whose inserts went unanswered stops early
+    bool memo_live = table != nullptr && memo_mode != 0 &&
+                     !(n_ins >= kMemoWaveIns && n_hit * kMemoWaveRatio < n_ins);
     u64 res_lo = 0, res_hi = 0, res_fp = 0;
     bool stop = false, unit_cancel = false;
     while (true) {
@@ -1126,7 +1136,9 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             mode = FINISH;
             continue;
           }
-          if (r_look >= kMemoMinLook && r_hit * kMemoMinRatio < r_look) memo_live = false;
+          if ((r_look >= kMemoMinLook && r_hit * kMemoMinRatio < r_look) ||
+              (n_ins - r_ins0 >= kMemoMinLook && r_hit * kMemoMinInsRatio < n_ins - r_ins0))
+            memo_live = false;
         }
         // members of P
         int np = 0;
@@ -1334,7 +1346,9 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
               Q[lane] &= keep;
             }
           }
-          if (r_look >= kMemoMinLook && r_hit * kMemoMinRatio < r_look) memo_live = false;
+          if ((r_look >= kMemoMinLook && r_hit * kMemoMinRatio < r_look) ||
+              (n_ins - r_ins0 >= kMemoMinLook && r_hit * kMemoMinInsRatio < n_ins - r_ins0))
+            memo_live = false;
         }
         if (j == jsplit) {
           // this unit's share of frame 1's children: every nsub-th survivor
@@ -1405,7 +1419,9 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
                   ++r_hit;
                   got = true;
                 }
-                if (r_look >= kMemoMinLook && r_hit * kMemoMinRatio < r_look) memo_live = false;
+                if ((r_look >= kMemoMinLook && r_hit * kMemoMinRatio < r_look) ||
+              (n_ins - r_ins0 >= kMemoMinLook && r_hit * kMemoMinInsRatio < n_ins - r_ins0))
+            memo_live = false;
               }
               if (!got) {
                 u64 Pc[W];

@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--serve-shed-frac", type=float, default=0.5,
                     help="report a (graph, k) DNF at once after a bulk cut-off that ran this share of the budget")
     ap.add_argument("--serve-modes", default="served,plain")
+    ap.add_argument("--state-dir", default="", metavar="DIR",
+                    help="write the autotuner's database and, when the router learns online, its routing "
+                         "state here (default: keep them in memory)")
     ap.add_argument("--serve-router", default=os.path.join(ROOT, "paper_2502_00317_amd", "router_cfg5.json"),
                     help="routing table of the served mode (stored from an earlier run's router_state); "
                          "used frozen when the file exists, else the router learns online")
@@ -137,14 +140,14 @@ def summarize_profiles(d):
     lines = ["# HBM traffic of the search kernels (rocprofv3 --pmc), plain count on the",
              "# Chung-Lu n=1e6 workload, k = 5 (fingerprint), 7 and 9, one launch each",
              "",
-             "Commands (repository root, one MI355X; TMPDIR=/tmp):",
+             "Commands (repository root, one MI355X; TMPDIR=/tmp; OUT = an absolute results directory):",
              "",
-             "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $PWD/gpurun_out/pmc_FETCH_SIZE -o run -- \\",
+             "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_FETCH_SIZE -o run -- \\",
              "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
-             "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $PWD/gpurun_out/pmc_WRITE_SIZE -o run -- \\",
+             "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_WRITE_SIZE -o run -- \\",
              "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
              "    rocprofv3 --pmc FETCH_SIZE (and WRITE_SIZE) ... -- python3 $PWD/bench.py --calib-copy 1024",
-             "    python3 bench.py --summarize-profiles gpurun_out",
+             "    python3 bench.py --summarize-profiles $OUT",
              "",
              "Calibration (1 GiB device copy): FETCH_SIZE factor %.3f, WRITE_SIZE factor %.3f." % (
                  out["calibration"]["FETCH_SIZE"]["factor"], out["calibration"]["WRITE_SIZE"]["factor"]),
@@ -162,12 +165,12 @@ def summarize_profiles(d):
     if stats:
         lines = ["# rocprofv3 kernel summary: plain count, Chung-Lu n=1e6, k = 5 (fingerprint), 7 and 9",
                  "",
-                 "Command (repository root, one MI355X):",
+                 "Command (repository root, one MI355X; OUT = an absolute results directory):",
                  "",
                  "    export TMPDIR=/tmp",
-                 "    rocprofv3 --kernel-trace --stats --output-format csv -d $PWD/gpurun_out/prof -o run -- \\",
+                 "    rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/prof -o run -- \\",
                  "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
-                 "    python3 bench.py --summarize-profiles gpurun_out",
+                 "    python3 bench.py --summarize-profiles $OUT",
                  "",
                  "One orientation (degree order) and one dist_count per k (one launch per width",
                  "class per k); k_search<W> is the search kernel for roots whose out-degree",
@@ -203,12 +206,12 @@ def summarize_profiles(d):
                  "# sections (Chung-Lu n=1e6, k = 5, 7, 9; all k <= 9 by pivoting; listing on the",
                  "# Chung-Lu n=1e4 graph, k = 4 and 6)",
                  "",
-                 "Command (repository root, one MI355X):",
+                 "Command (repository root, one MI355X; OUT = an absolute results directory):",
                  "",
                  "    export TMPDIR=/tmp",
-                 "    rocprofv3 --kernel-trace --stats --output-format csv -d $PWD/gpurun_out/prof_legs -o run -- \\",
+                 "    rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/prof_legs -o run -- \\",
                  "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-cfg3",
-                 "    python3 bench.py --summarize-profiles gpurun_out",
+                 "    python3 bench.py --summarize-profiles $OUT",
                  "",
                  "k_pivot<W> counts every clique size by pivoting (one launch per width class);",
                  "k_list_ist<W> lists cliques with the Induced Subgraph Trie (Algorithms 3 and 4).",
@@ -251,15 +254,15 @@ def summarize_issue(d):
     lines = ["# Instruction issue of the search kernels (rocprofv3 --pmc SQ counters), plain count",
              "# on the Chung-Lu n=1e6 workload, k = 5 (fingerprint), 7 and 9",
              "",
-             "Commands (repository root, one MI355X; TMPDIR=/tmp), one pass each:",
+             "Commands (repository root, one MI355X; TMPDIR=/tmp; OUT = an absolute results directory), one pass each:",
              "",
              "    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_SMEM SQ_INSTS_BRANCH \\",
-             "        SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR GRBM_GUI_ACTIVE --output-format csv -d $PWD/gpurun_out/sq_1 -o run -- \\",
+             "        SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR GRBM_GUI_ACTIVE --output-format csv -d $OUT/sq_1 -o run -- \\",
              "        python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
              "    rocprofv3 --pmc SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT SQ_BUSY_CYCLES SQ_WAVE_CYCLES \\",
              "        SQ_THREAD_CYCLES_VALU SQ_WAIT_INST_LDS SQ_ACTIVE_INST_ANY GRBM_COUNT --output-format csv \\",
-             "        -d $PWD/gpurun_out/sq_2 -o run -- python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
-             "    python3 bench.py --summarize-profiles gpurun_out",
+             "        -d $OUT/sq_2 -o run -- python3 $PWD/bench.py --steps 1 --warmup 0 --no-cpu --no-batched --no-serving --no-pivot --no-listing --no-cfg3",
+             "    python3 bench.py --summarize-profiles $OUT",
              "",
              "Peaks (256 CUs, 2.4 GHz): VALU 614 G wave64 instructions/s (4 SIMDs per CU, one wave64",
              "instruction per SIMD per 4 cycles = 39.3 T lane-ops/s); LDS 614 G instructions/s (one per CU",
@@ -711,8 +714,7 @@ def run_batched(a, dist, torch, specs, graphs, log):
     total = sum(c for c, _ in plain)
     log("batched: plain loop %.2f s, %d cliques" % (plain_s, total))
     m_total = sum(g.m for g in graphs)
-    db = autotune.TuningDB(os.path.join(ROOT, "gpurun_out", "autotune_db.json")
-                           if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    db = autotune.TuningDB(os.path.join(a.state_dir, "autotune_db.json") if a.state_dir else None)
     best, report = autotune.tune_batch(dist, G, ks, m_total, db=db, log=log)
     bcfg = dist.config(**best)
     res, rc, _ = dist.count_batch(G, ks, cfg=bcfg, use_graph=True)
@@ -853,8 +855,8 @@ def run_serving(a, dist, torch, inputs, log):
                          "heavy_keys": len(srv.heavy), "shed": srv.shed, "shed_frac": srv.shed_frac,
                          "router": ("stored table %s, frozen" % os.path.relpath(a.serve_router, ROOT))
                          if table is not None else "learned online"})
-            if table is None and os.path.isdir(os.path.join(ROOT, "gpurun_out")):
-                with open(os.path.join(ROOT, "gpurun_out", "router_state.json"), "w") as f:
+            if table is None and a.state_dir:
+                with open(os.path.join(a.state_dir, "router_state.json"), "w") as f:
                     json.dump(srv.router_state(), f, indent=1, sort_keys=True)
         ans[name] = {(q.qid): (q.count, q.fp) for q in qs if q.status in ("ok", "overflow")}
         lat[name] = {q.qid: q.latency for q in qs if q.status in ("ok", "overflow")}

@@ -2745,15 +2745,17 @@ int search_count_all(const dist_graph* g, int kmax, const dist_config& cfg, u64*
     // units per root: a launch with fewer than 8 roots per wave shares each
     // root among up to 64 units (a power of two), so that its few heavy
     // roots do not hold the launch; cfg.sub_units forces a count.  The units
-    // part ways at depth 2 of the tree, or at depth 24 where the launch has
-    // fewer roots than waves: a pivot tree keeps most of its nodes under the
-    // chain of pivot children, so a shallow split leaves one unit most of a
-    // heavy root (on the 10^6-vertex Chung-Lu graph, all k <= 9: one unit
-    // held 5.6M of a root's nodes and the whole 11 s of its launch at depth
-    // 2; the launch took 2.2 s at depth 24, while the walk above the split,
-    // repeated by every unit, made depth 32 slower again)
+    // part ways at depth 2 of the tree, at depth 24 where the launch has
+    // fewer roots than waves, and at depth 32 where it has fewer than one
+    // per 8 waves: a pivot tree keeps most of its nodes under the chain of
+    // pivot children, so a shallow split leaves one unit most of a heavy root
+    // (on the 10^6-vertex Chung-Lu graph, all k <= 9: one unit held 5.6M of a
+    // root's nodes and the whole 11 s of its launch at depth 2).  The walk
+    // above the split is repeated by every unit, so the depth grows only as
+    // the roots per wave shrink (there, 708 roots: 2.2 s at depth 24, 3.1 s
+    // at 32; 51 roots: 3.4 s at 24, 2.3 s at 32).
     const int64_t nr = buckets[b].end - buckets[b].begin;
-    sdepth[b] = nr < grid ? 24 : 2;
+    sdepth[b] = nr * 8 < grid ? 32 : (nr < grid ? 24 : 2);
     int nsub = 1;
     if (cfg.sub_units > 0) {
       nsub = std::min(cfg.sub_units, 64);

@@ -129,3 +129,23 @@ def test_per_pair_switches(D, oracle_mod):
             assert got == want, (trial, rep)
     with pytest.raises(D.DistError):
         D.count_batch_tuned(G, ks, [dict(memo=3)] * len(ks))
+
+
+def test_per_bucket_autotune(D, oracle_mod, tmp_path):
+    """The per-bucket autotuner: buckets by (width class, k band), two
+    candidates timed per bucket, winners stored in its database and reused
+    on a second call; the batch run with the per-pair winners equals the
+    oracle."""
+    from paper_2502_00317_amd import autotune
+    graphs, ks = _small_batch(seed=31)
+    G = [D.orient(g.row_ptr, g.col) for g in graphs]
+    want = [oracle_mod.count(g.row_ptr, g.col, k) for g, k in zip(graphs, ks)]
+    cands = [dict(min_width=1, chunk_work=512, memo=1), dict(min_width=2, chunk_work=0, memo=0)]
+    db = autotune.TuningDB(str(tmp_path / "db.json"))
+    per_pair, buckets = autotune.tune_buckets(D, G, ks, db=db, candidates=cands, reps=1)
+    assert sum(e["pairs"] for e in buckets.values()) == len(ks)
+    assert all(e["switches"] in cands for e in buckets.values())
+    got, rc, _ = D.count_batch_tuned(G, ks, per_pair, use_graph=True)
+    assert got == want
+    again, _ = autotune.tune_buckets(D, G, ks, db=autotune.TuningDB(str(tmp_path / "db.json")), candidates=cands)
+    assert again == per_pair

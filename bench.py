@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--serve-shed-frac", type=float, default=0.5,
                     help="report a (graph, k) DNF at once after a bulk cut-off that ran this share of the budget")
     ap.add_argument("--serve-modes", default="served,plain")
+    ap.add_argument("--serve-pivot-k", type=int, default=0,
+                    help="served mode: the bulk lane answers pool queries of k >= this by one pivot-based "
+                         "all-k pass per graph (0 = off)")
     ap.add_argument("--state-dir", default="", metavar="DIR",
                     help="write the autotuner's database and, when the router learns online, its routing "
                          "state here (default: keep them in memory)")
@@ -858,7 +861,7 @@ def run_serving(a, dist, torch, inputs, log):
             table = json.load(f)
     for name, kw, pcts, scfg in modes:
         be = DeviceBackend(slots=kw["slots"], grid_pcts=pcts, slot_cfgs=scfg)
-        extra = dict(router_table=table, learn=table is None) if name == "served" else {}
+        extra = dict(router_table=table, learn=table is None, pivot_k=a.serve_pivot_k) if name == "served" else {}
         srv = Server(be, handles, mem_limit=mem_limit, pool_bytes=pool_bytes, **kw, **extra)
         qs = queries()
         srv.start()
@@ -876,7 +879,9 @@ def run_serving(a, dist, torch, inputs, log):
                          "moved_to_bulk": srv.demoted, "routed_to_bulk": srv.routed_bulk,
                          "heavy_keys": len(srv.heavy), "shed": srv.shed, "shed_frac": srv.shed_frac,
                          "router": ("stored table %s, frozen" % os.path.relpath(a.serve_router, ROOT))
-                         if table is not None else "learned online"})
+                         if table is not None else "learned online",
+                         "pivot_k": srv.pivot_k, "pivot_passes": srv.pivot_passes,
+                         "pivot_slow_graphs": len(srv.pivot_slow)})
             if table is None and a.state_dir:
                 with open(os.path.join(a.state_dir, "router_state.json"), "w") as f:
                     json.dump(srv.router_state(), f, indent=1, sort_keys=True)

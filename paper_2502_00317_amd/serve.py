@@ -135,6 +135,23 @@ class DeviceBackend:
             ms = (time.perf_counter() - t) * 1e3
         return res, [names.get(s, "error") for s in st], ms
 
+    def count_all(self, slot, g, kmax, budget_ms):
+        """Every clique size k <= kmax of one graph in one pivot-based pass
+        (dist_count_all), with the whole device: ([(count, fp)] per k,
+        status)."""
+        import ctypes
+        D = self.dist
+        cfg = D.Config()
+        ctypes.memmove(ctypes.byref(cfg), ctypes.byref(self.cfg_one), ctypes.sizeof(cfg))
+        cfg.deadline_ms = int(budget_ms)
+        try:
+            res, rc = D.count_all(g, int(kmax), cfg=cfg, stream=self.streams[slot])
+        except D.DistError:
+            return None, "error"
+        if rc == D.E_CANCELLED:
+            return None, "dnf"
+        return res, "ok"
+
     def count_one(self, slot, g, k, budget_ms):
         """The per-graph call (dist_count_ex) for one query, with the whole
         device."""
@@ -175,6 +192,12 @@ class Server:
                   baseline without batching);
     stream_results -- complete each query as soon as the device reports it,
                   not when its whole batch ends;
+    pivot_k    -- with pivot_k > 0, the bulk lane answers its pool queries of
+                  k >= pivot_k by pivot-based counting, one pass per graph for
+                  every k it holds (dist_count_all under the longest remaining
+                  budget of those queries); a graph whose pass runs out of
+                  budget goes back to the search for good, and its queries
+                  return to the bulk queue with what is left of their budgets;
     router_table -- routing state to start from (router_state() of an
                   earlier run): the per-k thresholds of both lanes, the
                   (graph, k) known to be heavy or hopeless, and measured
@@ -189,7 +212,7 @@ class Server:
                  mem_limit: int = 1 << 62, pool_bytes: int = 0, max_batch: int = 4096,
                  clock=time.perf_counter, stream_results: bool = True, express_ms: int = 0,
                  plain: bool = False, express_batch_ms: float = 0.0, shed_frac: float = 0.0,
-                 router_table: dict | None = None, learn: bool = True):
+                 router_table: dict | None = None, learn: bool = True, pivot_k: int = 0):
         self.stream_results = stream_results
         self.pool_bytes = pool_bytes
         self.backend = backend
@@ -225,6 +248,9 @@ class Server:
         self._batch_ids = 0
         self._running = {}    # slot -> batch id while a batch runs
         self.learn = learn
+        self.pivot_k = pivot_k if (pivot_k > 0 and not plain) else 0
+        self.pivot_slow = set()   # pool graphs whose pivot pass ran out of budget
+        self.pivot_passes = 0
         if router_table:
             self.load_router(router_table)
 
@@ -470,6 +496,11 @@ class Server:
                     self._complete(q, None, None, "dnf", t_start)
             self.cv.notify_all()
         live = [q for q in batch if not q.done.is_set()]
+        if lane == "bulk" and self.pivot_k and hasattr(self.backend, "count_all"):
+            n_live = len(live)
+            live = self._pivot_pass(slot, live, t_start)
+            if len(live) != n_live or self.pivot_passes:
+                t_start = self.now()  # the rest's budgets run from here
         budgets, cut = [], []
         for q in live:
             rem = int(q.deadline_ms - (t_start - q.t_arrival) * 1e3) if q.deadline_ms else 0
@@ -531,6 +562,49 @@ class Server:
             self.batches.append((slot, len(live), t_start, t_end, ms, t_dev))
             self._running[slot] = None
             self.cv.notify_all()
+
+    def _pivot_pass(self, slot, live, t_start):
+        """The bulk lane's pivot path: pool queries of k >= pivot_k, grouped by
+        graph, each group answered by one all-k pass.  Returns the queries left
+        for the search."""
+        groups = {}
+        rest = []
+        for q in live:
+            if q.adhoc is None and self.pivot_k <= q.k <= 16 and q.graph not in self.pivot_slow:
+                groups.setdefault(q.graph, []).append(q)
+            else:
+                rest.append(q)
+        for gi, qs in groups.items():
+            now = self.now()
+            rem = [q.deadline_ms - (now - q.t_arrival) * 1e3 if q.deadline_ms else 0.0 for q in qs]
+            budget = max(rem) if all(q.deadline_ms for q in qs) else 0.0
+            if all(q.deadline_ms for q in qs) and budget <= 1.0:
+                rest.extend(qs)   # the search path completes them as DNF
+                continue
+            for q in qs:
+                if q.t_start is None:
+                    q.t_start = t_start
+                q.slot = slot
+                q.batch_size = len(qs)
+            try:
+                res, st = self.backend.count_all(slot, self.pool[gi], max(q.k for q in qs), max(1, int(budget)))
+            except Exception as e:  # reported per query; the server keeps running
+                self.errors.append(repr(e))
+                res, st = None, "error"
+            t = self.now()
+            self.pivot_passes += 1
+            with self.cv:
+                if st == "ok":
+                    for q in qs:
+                        c, f = res[q.k]
+                        late = q.deadline_ms and (t - q.t_arrival) * 1e3 > q.deadline_ms
+                        self._complete(q, None if late else c, None if late else f,
+                                       "dnf" if late else ("overflow" if c >> 64 else "ok"), t)
+                else:
+                    self.pivot_slow.add(gi)
+                    rest.extend(qs)
+                self.cv.notify_all()
+        return rest
 
 
 def replay(server: Server, queries, sleep=time.sleep, log=None):

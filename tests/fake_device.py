@@ -19,8 +19,10 @@ class FakeGraph:
 
 class FakeBackend:
     def __init__(self, oracle, cost_fn, seconds_per_cost=1e-3, pool_bytes=0, mem_limit=None,
-                 estimate_fn=None):
+                 estimate_fn=None, pivot_cost_fn=None):
         self.oracle = oracle
+        self.pivot_cost_fn = pivot_cost_fn
+        self.pivot_calls = []
         if estimate_fn is not None:
             self.estimate = estimate_fn
         self.cost_fn = cost_fn
@@ -46,6 +48,17 @@ class FakeBackend:
     def free(self, g):
         with self.lock:
             self.live -= g.nbytes
+
+    def count_all(self, slot, g, kmax, budget_ms):
+        """Every k <= kmax in one simulated pass of pivot_cost_fn(g, kmax)."""
+        c = self.pivot_cost_fn(g, kmax)
+        self.pivot_calls.append((slot, g.n, kmax))
+        if budget_ms and c * self.scale * 1e3 > budget_ms:
+            time.sleep(budget_ms / 1e3)
+            return None, "dnf"
+        res = [(0, 0)] + [self.oracle.count(g.row_ptr, g.col, k, nthreads=1) for k in range(1, kmax + 1)]
+        time.sleep(c * self.scale)
+        return res, "ok"
 
     def count_one(self, slot, g, k, budget_ms):
         res, st, _ = self.count_batch(slot, [g], [k], [budget_ms])

@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--serve-shed-frac", type=float, default=0.5,
                     help="report a (graph, k) DNF at once after a bulk cut-off that ran this share of the budget")
     ap.add_argument("--serve-modes", default="served,plain")
-    ap.add_argument("--serve-pivot-k", type=int, default=0,
+    ap.add_argument("--serve-pivot-k", type=int, default=6,
                     help="served mode: the bulk lane answers pool queries of k >= this by one pivot-based "
                          "all-k pass per graph (0 = off)")
     ap.add_argument("--state-dir", default="", metavar="DIR",

@@ -20,7 +20,11 @@ def D():
     return dist
 
 
-def test_served_equals_alone(D, oracle_mod):
+@pytest.mark.parametrize("pivot_k", [0, 5])
+def test_served_equals_alone(D, oracle_mod, pivot_k):
+    """Every served result equals the same query alone and the oracle: two
+    lanes, and one bulk lane whose pool queries of k >= 5 take the pivot
+    path."""
     from paper_2502_00317_amd.serve import DeviceBackend, Query, Server, oriented_bytes, replay, summarize
     pool = [gg.chung_lu(int(n), 2.4, 12.0, None, [31, i], plants=[10, 12])
             for i, n in enumerate(np.geomspace(2000, 20000, 6))]
@@ -39,7 +43,7 @@ def test_served_equals_alone(D, oracle_mod):
             qs.append(Query(qid=i, k=k, t_arrival=float(t[i]), graph=int(rng.integers(0, len(pool))),
                             deadline_ms=30000))
     srv = Server(be, handles, slots=2, pool_bytes=pool_bytes, mem_limit=pool_bytes + (64 << 20),
-                 express_ms=5)
+                 express_ms=0 if pivot_k else 5, pivot_k=pivot_k)
     srv.start()
     replay(srv, qs)
     srv.stop()
@@ -47,7 +51,9 @@ def test_served_equals_alone(D, oracle_mod):
     print(s, flush=True)
     assert s["completed"] == len(qs), [q.status for q in qs if q.status != "ok"]
     assert len(srv.batches) < len(qs)  # queries were batched
-    print("moved to the bulk lane:", srv.demoted, flush=True)
+    print("moved to the bulk lane:", srv.demoted, "pivot passes:", srv.pivot_passes, flush=True)
+    if pivot_k:
+        assert srv.pivot_passes >= 1  # without an express lane every pool query of k >= 5 takes the path
     P61 = (1 << 61) - 1
     oracle_of = {}
 

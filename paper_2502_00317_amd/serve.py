@@ -497,9 +497,9 @@ class Server:
             self.cv.notify_all()
         live = [q for q in batch if not q.done.is_set()]
         if lane == "bulk" and self.pivot_k and hasattr(self.backend, "count_all"):
-            n_live = len(live)
+            passes = self.pivot_passes
             live = self._pivot_pass(slot, live, t_start)
-            if len(live) != n_live or self.pivot_passes:
+            if self.pivot_passes != passes:
                 t_start = self.now()  # the rest's budgets run from here
         budgets, cut = [], []
         for q in live:
@@ -576,9 +576,10 @@ class Server:
                 rest.append(q)
         for gi, qs in groups.items():
             now = self.now()
-            rem = [q.deadline_ms - (now - q.t_arrival) * 1e3 if q.deadline_ms else 0.0 for q in qs]
-            budget = max(rem) if all(q.deadline_ms for q in qs) else 0.0
-            if all(q.deadline_ms for q in qs) and budget <= 1.0:
+            timed = all(q.deadline_ms for q in qs)
+            # the longest remaining budget of the group; none if a query has none
+            budget = max(q.deadline_ms - (now - q.t_arrival) * 1e3 for q in qs) if timed else 0.0
+            if timed and budget <= 1.0:
                 rest.extend(qs)   # the search path completes them as DNF
                 continue
             for q in qs:
@@ -587,7 +588,8 @@ class Server:
                 q.slot = slot
                 q.batch_size = len(qs)
             try:
-                res, st = self.backend.count_all(slot, self.pool[gi], max(q.k for q in qs), max(1, int(budget)))
+                res, st = self.backend.count_all(slot, self.pool[gi], max(q.k for q in qs),
+                                                 max(1, int(budget)) if timed else 0)
             except Exception as e:  # reported per query; the server keeps running
                 self.errors.append(repr(e))
                 res, st = None, "error"

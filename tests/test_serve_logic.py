@@ -381,3 +381,19 @@ def test_bulk_pivot_pass_too_slow_falls_back(oracle_mod):
     g = graphs[0]
     for q in second:
         assert q.status == "ok" and (q.count, q.fp) == oracle_mod.count(g.row_ptr, g.col, q.k)
+
+
+def test_bulk_pivot_pass_without_deadlines(oracle_mod):
+    """Queries without a latency budget give their pivot pass no deadline
+    (not a 1 ms one): the pass completes and nothing is marked slow."""
+    graphs, handles = _pool(1)
+    be = FakeBackend(oracle_mod, lambda g, k: 1.0, seconds_per_cost=1e-3, pivot_cost_fn=lambda g, kmax: 20.0)
+    srv = Server(be, handles, slots=1, pivot_k=6)
+    qs = [Query(qid=i, k=6 + i, t_arrival=0.0, graph=0) for i in range(3)]
+    srv.start()
+    replay(srv, qs)
+    srv.stop()
+    g = graphs[0]
+    assert srv.pivot_passes >= 1 and not srv.pivot_slow
+    for q in qs:
+        assert q.status == "ok" and (q.count, q.fp) == oracle_mod.count(g.row_ptr, g.col, q.k)

@@ -553,6 +553,7 @@ def main():
         "metric": "k-cliques/sec at k=5..9 (plain vs batched); p50/p99 query latency in serving",
         "value": value,
         "unit": "k-cliques/s",
+        "rate_kind": "counting rate: k-cliques counted (with their fingerprint), not enumerated, per second",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,

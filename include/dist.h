@@ -133,6 +133,19 @@ typedef struct {
                             inserted since the last clear (soft bound), and
                             no node is inserted past 2 tau (hard bound).
                             Results do not depend on it */
+  int32_t edge_units;    /* dist_count / dist_count_ex: EdgeParallel work
+                            units (Section VII-D).  W in DIST_WIDTHS: every
+                            root whose subgraph takes at least W words is
+                            searched as one unit per arc (u, v), over
+                            G[N+(u) & N+(v)] for (k - 2)-cliques, each unit
+                            in the width class of its own set (a pre-pass
+                            builds G_u once to find the sets); 0 = auto
+                            (W = 4 for k = 5..7, W = 5 for k >= 8, off for
+                            k < 5); -1 = off.  Ignored with trie_tau > 0,
+                            k < 4 and by dist_count_noalloc, dist_count_all
+                            and the batched calls.  Results do not depend
+                            on it; work counters count the arcs as roots */
+  int32_t reserved;      /* must be 0 */
 } dist_config;
 
 typedef struct {

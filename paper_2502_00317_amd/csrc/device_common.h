@@ -382,14 +382,16 @@ __device__ int soft_embed_levels(const Lds& s, int d, int K) {
 // from HBM (flattened over the wave so that reads are coalesced) and every
 // entry is located in N+(r) by binary search in LDS.  If oid is set, oid[i]
 // receives the input id of local vertex i.  Returns the arcs read (per lane).
+//
+// build_rows takes the vertex list from s.nb[0, d) (ascending rank, written
+// before a wave barrier); build_subgraph fills it with N+(r) first.
 template <int W>
-__device__ u64 build_subgraph(const Lds& s, const int32_t* dptr, const int32_t* dcol, const u64* gw,
-                              const int32_t* orig, int32_t* oid, int32_t beg, int d) {
+__device__ u64 build_rows(const Lds& s, const int32_t* dptr, const int32_t* dcol, const u64* gw,
+                          const int32_t* orig, int32_t* oid, int d) {
   const int lane = lane_id();
   u64 arcs = 0;
   for (int i = lane; i < d; i += kWave) {
-    int32_t v = dcol[beg + i];
-    s.nb[i] = v;
+    const int32_t v = s.nb[i];
     if (s.gl) s.gl[i] = gw[v];
     if (oid) oid[i] = orig[v];
     int32_t b = dptr[v];
@@ -436,6 +438,14 @@ __device__ u64 build_subgraph(const Lds& s, const int32_t* dptr, const int32_t* 
   }
   __syncthreads();
   return arcs;
+}
+
+template <int W>
+__device__ u64 build_subgraph(const Lds& s, const int32_t* dptr, const int32_t* dcol, const u64* gw,
+                              const int32_t* orig, int32_t* oid, int32_t beg, int d) {
+  // each lane reads back only the entries it wrote
+  for (int i = lane_id(); i < d; i += kWave) s.nb[i] = dcol[beg + i];
+  return build_rows<W>(s, dptr, dcol, gw, orig, oid, d);
 }
 
 }  // namespace

@@ -75,6 +75,17 @@ constexpr u64 kMemoWaveRatio = 16;
 // Batched counting: one entry per (graph, k) pair, and the units of a
 // launch as segments [unit_begin, next unit_begin) of consecutive roots of
 // one pair (one unit per root).
+// An EdgeParallel work unit (Section VII-D): the arc (u, v) of a heavy root
+// u, searched for (k-2)-cliques in G[N+(u) & N+(v)].  That vertex set is
+// row v of G_u, stored as a bitmap over N+(u) (wu words from word `row` of
+// the edge row store).
+struct EdgeRec {
+  int32_t u, v;  // ranks
+  int32_t d;     // |N+(u) & N+(v)|; 0: the arc cannot start a k-clique's second vertex
+  int32_t wu;    // words of the row
+  u64 row;
+};
+
 struct BatchGraph {
   const int32_t* dptr;
   const int32_t* dcol;
@@ -86,6 +97,10 @@ struct BatchGraph {
   u64 budget;         // wall-clock ticks this pair may use; 0 = no limit
   int32_t memo = -1;  // this pair's memo switch; < 0: the launch's
   int32_t pad_ = 0;
+  // EdgeParallel units: roots[i] indexes edges, and k is the clique size
+  // minus one (the units start one level down)
+  const EdgeRec* edges = nullptr;
+  const u64* erows = nullptr;
 };
 
 struct BatchSeg {
@@ -914,9 +929,12 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
   const int32_t* Gorig = nullptr;
   const int32_t* Groots = nullptr;
   const u64* Ggw = nullptr;
+  const EdgeRec* Gedges = nullptr;
+  const u64* Gerows = nullptr;
   int pair = -1;
   int32_t r = 0;
   int d = 0;
+  u64 rw = 0;  // weight of the unit's prefix: g(root), or g(u) g(v) for an edge
   for (;;) {
     // ---- 0. next work unit: (root, range of depth-1 children) -------------------
     uint32_t u = 0;
@@ -964,6 +982,8 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
       Gorig = bgr.orig;
       Groots = bgr.roots;
       Ggw = bgr.gw;
+      Gedges = bgr.edges;
+      Gerows = bgr.erows;
       k = bgr.k;
       pair_budget = bgr.budget;
       own_clock = bgr.own_clock;
@@ -1023,15 +1043,35 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
     if (rel != cur_rel || pair != cur_pair) {
       cur_rel = rel;
       cur_pair = pair;
-      r = Groots[ridx];
-      const int32_t beg = Gdptr[r];
-      d = Gdptr[r + 1] - beg;  // <= 64 * W by the host's bucketing
       __syncthreads();
+      int32_t beg;
+      if (Gedges) {
+        // an EdgeParallel unit: the vertices of G[N+(u) & N+(v)] from the
+        // set bits of its row over N+(u)
+        const EdgeRec er = Gedges[Groots[ridx]];
+        r = er.u;
+        beg = Gdptr[r];
+        d = er.d;  // <= 64 * W by the host's bucketing
+        rw = FP ? mulp(Ggw[er.u], Ggw[er.v]) : 0;
+        const u64* row = Gerows + er.row;
+        int nbase = 0;
+        for (int w = 0; w < er.wu; ++w) {
+          const u64 bw = row[w];
+          if ((bw >> lane) & 1ull) s.nb[nbase + __popcll(bw & lanemask_lt())] = Gdcol[beg + w * 64 + lane];
+          nbase += __popcll(bw);
+        }
+      } else {
+        r = Groots[ridx];
+        beg = Gdptr[r];
+        d = Gdptr[r + 1] - beg;  // <= 64 * W by the host's bucketing
+        rw = FP ? Ggw[r] : 0;
+        for (int i = lane; i < d; i += kWave) s.nb[i] = Gdcol[beg + i];
+      }
       if (lane == 0) s.ctl[3] = (u64)(uint32_t)beg;
       __syncthreads();
       ++n_builds;
-      // ---- 1. G_u in LDS ------------------------------------------------------
-      arcs += build_subgraph<W>(s, Gdptr, Gdcol, Ggw, Gorig, nullptr, beg, d);
+      // ---- 1. G_u (or G_uv) in LDS ---------------------------------------------
+      arcs += build_rows<W>(s, Gdptr, Gdcol, Ggw, Gorig, nullptr, d);
       if (s.wtab) build_weight_table<W>(s, d);
 
       // ---- 2. soft-embedding bound (Algorithm 5) ---------------------------------
@@ -1063,6 +1103,11 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
     // with nsub > 1, frame 1 holds only part of its subtree: it neither reads
     // nor writes memo entries, and its closed forms count in sub-unit 0 only
     const int jsplit = nsub > 1 ? 1 : -1;
+    // an edge unit's frame 0 (a depth-1 set of its root) takes the closed
+    // forms too; all units of the edge reach the same decision, and the
+    // first of them counts it
+    const bool cf0 = Gedges != nullptr;
+    const bool own0 = ci == 0 && sub == 0;
 
     // ---- 3. depth-first search over candidate bitmaps -----------------------------
     // frame j needs l = k-1-j more vertices from its candidate set stP[j].
@@ -1156,7 +1201,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             mode = FINISH;
             continue;
           }
-          if (l == 3 && j > 0) {
+          if (l == 3 && (j > 0 || cf0)) {
             // edges of G[P] first: a complete P needs no leaf search
             u64 m = 0;
             for (int i = lane; i < np; i += kWave) {
@@ -1178,7 +1223,8 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
                   res_lo = clo;
                   res_hi = chi;
                   res_fp = cfp;
-                  if (memo_j && memo_live) {
+                  if (j == 0 && !own0) res_lo = res_hi = res_fp = 0;
+                  if (memo_j && memo_live && j > 0) {
                     memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr, room());
                     ++n_ins;
                   }
@@ -1192,7 +1238,8 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
               res_lo = clo;
               res_hi = chi;
               res_fp = FP ? esym_members<W>(s.mem, np, s.gl, 3) : 0;
-                if (memo_j && memo_live) {
+              if (j == 0 && !own0) res_lo = res_hi = res_fp = 0;
+              if (memo_j && memo_live && j > 0) {
                 memo_put<W>(p, table, tag, s.stP + j * W, -1, res_lo, res_hi, res_fp, p.tau ? Gdcol + (int32_t)s.ctl[3] : nullptr, room());
                 ++n_ins;
               }
@@ -1253,12 +1300,12 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
           if (c >= l - 1 && s.rcap[x] >= l) atomicOr(&Q[x >> 6], 1ull << (x & 63));
         }
         m_edges = wave_sum(m_edges);
-        if (j > 0 && m_edges == (u64)np * (u64)(np - 1) / 2) {
+        if ((j > 0 || cf0) && m_edges == (u64)np * (u64)(np - 1) / 2) {
           u64 clo, chi;
           if (binom128(np, l, clo, chi)) {
             // at a shared split frame the closed form is sub-unit 0's: the
             // others skip it (and its fingerprint) entirely
-            const bool mine = !(j == jsplit && sub != 0);
+            const bool mine = !(j == jsplit && sub != 0) && (j > 0 || own0);
             res_lo = mine ? clo : 0;
             res_hi = mine ? chi : 0;
             res_fp = (FP && mine) ? esym_members<W>(s.mem, np, s.gl, l) : 0;
@@ -1278,14 +1325,14 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             mode = FINISH;
             continue;
           }
-          if (j > 0 && m_edges < full && full - m_edges <= (u64)kNearMissing) {
+          if ((j > 0 || cf0) && m_edges < full && full - m_edges <= (u64)kNearMissing) {
             const int e = missing_edges<W>(s, Pr, np, s.pos);
             u64 clo, chi, cfp;
             if (e == (int)(full - m_edges) && near_complete<W, FP>(s.pos, e, np, l, s.mem, s.gl, clo, chi, cfp)) {
               res_lo = clo;
               res_hi = chi;
               res_fp = cfp;
-              if (j == jsplit && sub != 0) res_lo = res_hi = res_fp = 0;
+              if ((j == jsplit && sub != 0) || (j == 0 && !own0)) res_lo = res_hi = res_fp = 0;
               __syncthreads();
               mode = FINISH;
               continue;
@@ -1545,8 +1592,8 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
       finish_units(p, pair, 1u + skip_rest(p, sg.pair_end));
       continue;
     }
-    // root result: cnt, fp * g(root)
-    u64 rfp = FP ? mulp(Ggw[r], res_fp) : 0;
+    // unit result: cnt, fp times the prefix weight
+    u64 rfp = FP ? mulp(rw, res_fp) : 0;
     if (p.pair_out && lane == 0) {
       // plain atomic adds only: many waves finish units of one pair at once
       u64* o = p.pair_out + 4 * (u64)pair;
@@ -1594,6 +1641,78 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
   }
 }
 
+// ---- EdgeParallel set-up (Section VII-D) ----------------------------------------
+
+struct EdgePrep {
+  const int32_t* dptr;
+  const int32_t* dcol;
+  const int32_t* roots;     // heavy roots are roots[0, nh)
+  const u64* base;          // per heavy root: first record, first row word
+  int32_t first, last;      // this launch's heavy roots
+  int k;
+  int prune;
+  int32_t drows;
+  EdgeRec* recs;
+  u64* rows;
+  unsigned* hist;           // records of each size d (DIST_MAX_OUTDEG + 1 bins)
+};
+
+// One wave per heavy root u: G_u is built and pruned exactly as for its own
+// search, and each depth-1 child v that passes the search's child test at
+// frame 0 (|N+(u) & N+(v)| >= k - 2, soft-embedding bound >= k - 1) gets a
+// record whose row is G_u's row of v; the other children and a pruned root
+// get d = 0.
+template <int W>
+__global__ __launch_bounds__(64) void k_edge_rows(EdgePrep p) {
+  extern __shared__ __align__(16) char smem[];
+  const int lane = lane_id();
+  const Lds s = carve<W>(smem, p.k, 0, p.drows);
+  for (int32_t i = p.first + (int32_t)blockIdx.x; i < p.last; i += (int32_t)gridDim.x) {
+    const int32_t r = p.roots[i];
+    const int32_t beg = p.dptr[r];
+    const int d = p.dptr[r + 1] - beg;
+    __syncthreads();
+    build_subgraph<W>(s, p.dptr, p.dcol, nullptr, nullptr, nullptr, beg, d);
+    bool dead = false;
+    if (p.prune) {
+      dead = soft_embed_levels<W>(s, d, p.k) < p.k;
+    } else {
+      for (int x = lane; x < d; x += kWave) s.rcap[x] = 63;
+    }
+    __syncthreads();
+    const u64 rec0 = p.base[2 * (u64)i], row0 = p.base[2 * (u64)i + 1];
+    for (int a = lane; a < d; a += kWave) {
+      int c = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) c += __popcll(s.A[a * W + w]);
+      const bool ok = !dead && c >= p.k - 2 && s.rcap[a] >= p.k - 1;
+      EdgeRec e;
+      e.u = r;
+      e.v = p.dcol[beg + a];
+      e.d = ok ? c : 0;
+      e.wu = W;
+      e.row = row0 + (u64)a * W;
+      p.recs[rec0 + a] = e;
+      if (ok) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) p.rows[e.row + w] = s.A[a * W + w];
+        atomicAdd(p.hist + c, 1u);
+      }
+    }
+  }
+}
+
+// Records in descending order of size: cur[d] starts at the first slot of
+// size d (a counting sort; the order among equal sizes is arbitrary).
+__global__ void k_edge_order(const EdgeRec* recs, u64 nrec, unsigned* cur, int32_t* list) {
+  u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (; i < nrec; i += stride) {
+    const int d = recs[i].d;
+    if (d > 0) list[atomicAdd(cur + d, 1u)] = (int32_t)i;
+  }
+}
+
 __global__ void k_zero_u32(unsigned* p, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -1637,6 +1756,8 @@ struct Workspace {
   char* d_plan = nullptr;   // graph descriptor + segments of a single-graph launch
   char* h_plan = nullptr;   // pinned staging for the same
   size_t plan_cap = 0;
+  char* edge = nullptr;     // EdgeParallel records, rows, order and histogram
+  size_t edge_cap = 0;
 };
 
 Workspace g_ws;  // one device per process in this library
@@ -1753,7 +1874,24 @@ int ws_plan(size_t bytes) {
 // mean over its children, and a launch of W waves ideally takes
 // sum(cost) / W; where the heaviest unit exceeds that, each child of a
 // single-child unit is shared by up to kMaxSub units.
-void split_children(const dist_graph* g, int32_t nroots, int k, int cw, int forced, int (&sub_of)[kClasses]) {
+using DegHist = std::vector<std::pair<int32_t, int64_t>>;
+
+// Calls f(d, a, b) for each run [a, b) of roots of equal out-degree d that
+// falls in [first, end) (runs in descending out-degree order, as the roots).
+template <class F>
+void for_runs(const DegHist& h, int32_t first, int32_t end, F&& f) {
+  int64_t a = 0;
+  for (const auto& run : h) {
+    if (a >= end) break;
+    const int64_t b = std::min<int64_t>(a + run.second, end);
+    const int64_t lo = std::max<int64_t>(a, first);
+    if (b > lo) f((int)run.first, (int32_t)lo, (int32_t)b);
+    a += run.second;
+  }
+}
+
+void split_children(const DegHist& h, int32_t first, int32_t nroots, int k, int cw, int forced,
+                    int (&sub_of)[kClasses]) {
   for (int& x : sub_of) x = 1;
   if (k < 6) return;
   if (forced > 0) {
@@ -1761,17 +1899,12 @@ void split_children(const dist_graph* g, int32_t nroots, int k, int cw, int forc
     return;
   }
   double total[kClasses] = {}, heavy[kClasses] = {};
-  int32_t a = 0;
-  for (const auto& run : g->deg_hist) {
-    if (a >= nroots) break;
-    const int d = run.first;
-    const int32_t cnt = (int32_t)std::min<int64_t>(run.second, (int64_t)nroots - a);
-    a += cnt;
+  for_runs(h, first, nroots, [&](int d, int32_t a, int32_t b) {
     const int sl = wslot_of_width(width_of(d));
     const double child = std::pow((double)d / 64.0, (double)(k - 3));
-    total[sl] += (double)cnt * (double)d * child;
+    total[sl] += (double)(b - a) * (double)d * child;
     if (children_per_unit(d, k, cw) == 1 && child > heavy[sl]) heavy[sl] = child;
-  }
+  });
   const double waves = 8.0 * (g_ws.cus > 0 ? g_ws.cus : 256);
   for (int sl = 0; sl < kClasses; ++sl) {
     if (heavy[sl] <= 0 || total[sl] <= 0) continue;
@@ -1783,18 +1916,51 @@ void split_children(const dist_graph* g, int32_t nroots, int k, int cw, int forc
   }
 }
 
-// Appends the work segments of pair `pair` (roots [0, nroots) of g, clique
-// size k) to the width classes: consecutive roots with the same width and the
-// same split into units form one segment.
+void split_children(const dist_graph* g, int32_t nroots, int k, int cw, int forced, int (&sub_of)[kClasses]) {
+  split_children(g->deg_hist, 0, nroots, k, cw, forced, sub_of);
+}
+
+// The same for EdgeParallel units (clique size k counted from the arc's set,
+// i.e. one less than the query's), each one range of children, per set size
+// d: a unit costs about d (d/64)^(k-3), its heaviest depth-1 subtree
+// 2^(k-4) times the mean, and units are shared out where that would hold
+// their launch past the mean load of a wave.  sub_d[d] for d <= DIST_MAX_OUTDEG.
+void split_edges(const DegHist& h, int32_t n, int k, int forced, std::vector<int>& sub_d) {
+  sub_d.assign(DIST_MAX_OUTDEG + 1, 1);
+  if (k < 6) return;
+  if (forced > 0) {
+    for (int& x : sub_d) x = forced < kMaxSub ? forced : kMaxSub;
+    return;
+  }
+  auto unit = [&](int d) { return (double)d * std::pow((double)d / 64.0, (double)(k - 3)); };
+  double total[kClasses] = {};
+  for_runs(h, 0, n, [&](int d, int32_t a, int32_t b) { total[wslot_of_width(width_of(d))] += (double)(b - a) * unit(d); });
+  const double waves = 8.0 * (g_ws.cus > 0 ? g_ws.cus : 256);
+  for_runs(h, 0, n, [&](int d, int32_t, int32_t) {
+    const double t = total[wslot_of_width(width_of(d))];
+    const double r = t > 0 ? unit(d) * std::ldexp(1.0, k - 4) * waves / t : 0.0;
+    int sub = 1;
+    while (sub < kMaxSub && sub < r) sub <<= 1;
+    sub_d[d] = sub;
+  });
+}
+
+// Appends the work segments of pair `pair` (roots [first, nroots) of a pair
+// whose out-degree runs are h, clique size k) to the width classes:
+// consecutive roots with the same width and the same split into units form
+// one segment.  dmax[c] grows to the widest root put in class c.
+// one_range: a root's depth-1 children form one range (units only share
+// depth-2 children); sub_d, if set, gives the units sharing a range by
+// out-degree instead of by class.
 template <class SegList>
-void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, bool whole_roots, int min_w,
-                  const int (&sub_of)[kClasses], SegList (&segs)[kClasses],
-                  uint64_t (&units)[kClasses], int (&kmax)[kClasses]) {
+void add_segments(const DegHist& h, int pair, int32_t first, int32_t nroots, int k, int cw, bool whole_roots,
+                  int min_w, const int (&sub_of)[kClasses], SegList (&segs)[kClasses],
+                  uint64_t (&units)[kClasses], int (&kmax)[kClasses], int* dmax = nullptr,
+                  bool one_range = false, const int* sub_d = nullptr) {
   // walks the runs of equal out-degree (roots are in descending out-degree
   // order), so planning costs O(distinct degrees), not O(roots)
-  int32_t a = 0;
   int cur_sl = -1, cur_upr = 0, cur_sub = 1;
-  int32_t seg_a = 0;
+  int32_t seg_a = 0, last = first;
   size_t first_seg[kClasses];
   for (int b = 0; b < kClasses; ++b) first_seg[b] = segs[b].size();
   auto flush = [&](int32_t end) {
@@ -1803,15 +1969,13 @@ void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, 
     units[cur_sl] += (uint64_t)(end - seg_a) * (uint64_t)cur_upr;
     if (k > kmax[cur_sl]) kmax[cur_sl] = k;
   };
-  for (const auto& run : g->deg_hist) {
-    if (a >= nroots) break;
-    const int d = run.first;
-    const int32_t b = (int32_t)std::min<int64_t>((int64_t)a + run.second, (int64_t)nroots);
+  for_runs(h, first, nroots, [&](int d, int32_t a, int32_t b) {
     int W = width_of(d);
     if (W < min_w) W = width_of(64 * min_w);  // the narrowest class of at least min_w words
     const int sl = wslot_of_width(W);
-    const int sub = (whole_roots || k < 6) ? 1 : sub_of[sl];
-    const int upr = whole_roots ? 1 : units_per_root(d, k, cw) * sub;
+    if (dmax && d > dmax[sl]) dmax[sl] = d;
+    const int sub = (whole_roots || k < 6) ? 1 : sub_d ? sub_d[d] : sub_of[sl];
+    const int upr = (whole_roots || one_range) ? sub : units_per_root(d, k, cw) * sub;
     if (sl != cur_sl || upr != cur_upr || sub != cur_sub) {
       flush(a);
       cur_sl = sl;
@@ -1819,11 +1983,18 @@ void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, 
       cur_sub = sub;
       seg_a = a;
     }
-    a = b;
-  }
-  flush(a);
+    last = b;
+  });
+  flush(last);
   for (int b = 0; b < kClasses; ++b)
     for (size_t i = first_seg[b]; i < segs[b].size(); ++i) segs[b][i].pair_end = (uint32_t)units[b];
+}
+
+template <class SegList>
+void add_segments(const dist_graph* g, int pair, int32_t nroots, int k, int cw, bool whole_roots, int min_w,
+                  const int (&sub_of)[kClasses], SegList (&segs)[kClasses],
+                  uint64_t (&units)[kClasses], int (&kmax)[kClasses]) {
+  add_segments(g->deg_hist, pair, 0, nroots, k, cw, whole_roots, min_w, sub_of, segs, units, kmax);
 }
 
 // The fingerprint switch is a template parameter: a count without
@@ -1876,6 +2047,98 @@ std::vector<Bucket> make_buckets(const dist_graph* g, int32_t nroots) {
   return out;
 }
 
+
+// ---- EdgeParallel units (Section VII-D) --------------------------------------------
+// The heavy roots' arcs (u, v) become units of their own, each searched over
+// G[N+(u) & N+(v)] in the width class of that set: the deep subtrees of a
+// wide root then run on rows of a few words instead of the root's.
+
+template <int W>
+int launch_edge_rows(const EdgePrep& ep, int32_t count, hipStream_t s) {
+  const size_t lds = lds_bytes(W, ep.k, 0, ep.drows);
+  DIST_CHECK(hipFuncSetAttribute((const void*)k_edge_rows<W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_edge_rows<W>, 64, lds) != hipSuccess || occ < 1) occ = 1;
+  int64_t grid = (int64_t)occ * (g_ws.cus > 0 ? g_ws.cus : 256);
+  if (grid > count) grid = count;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_edge_rows<W>, dim3((unsigned)grid), dim3(64), lds, s, ep);
+  DIST_CHECK(hipGetLastError());
+  return DIST_OK;
+}
+
+struct EdgeSet {
+  const EdgeRec* recs = nullptr;
+  const u64* rows = nullptr;
+  const int32_t* list = nullptr;  // record indices, descending size
+  DegHist hist;                   // runs (size, records) of the list
+  int32_t n = 0;                  // records in the list
+};
+
+// Builds the edge units of heavy roots [0, nh) for clique size k (with the
+// search's own pruning switch).  Synchronises the stream once (the size
+// histogram sets the plan).
+int edge_prepare(const dist_graph* g, int32_t nh, int k, int prune, hipStream_t s, EdgeSet* es) {
+  constexpr int kBins = DIST_MAX_OUTDEG + 1;
+  std::vector<u64> base(2 * (size_t)nh);
+  u64 nrec = 0, nwords = 0;
+  for (int32_t i = 0; i < nh; ++i) {
+    const int d = g->root_deg[i];
+    base[2 * (size_t)i] = nrec;
+    base[2 * (size_t)i + 1] = nwords;
+    nrec += (u64)d;
+    nwords += (u64)d * (u64)width_of(d);
+  }
+  if (nrec >= 0x7fffffffull) return DIST_E_UNSUPPORTED;  // list entries are int32
+  const size_t o_rows = align8(nrec * sizeof(EdgeRec));
+  const size_t o_base = o_rows + nwords * sizeof(u64);
+  const size_t o_list = o_base + base.size() * sizeof(u64);
+  const size_t o_hist = align8(o_list + nrec * sizeof(int32_t));
+  const size_t o_cur = o_hist + kBins * sizeof(unsigned);
+  const size_t bytes = o_cur + kBins * sizeof(unsigned);
+  if (bytes > g_ws.edge_cap) {
+    if (g_ws.edge) dev_free(g_ws.edge);
+    g_ws.edge = nullptr;
+    g_ws.edge_cap = 0;
+    if (dev_alloc((void**)&g_ws.edge, bytes)) return DIST_E_NOMEM;
+    g_ws.edge_cap = bytes;
+  }
+  char* b = g_ws.edge;
+  EdgeRec* recs = (EdgeRec*)b;
+  u64* rows = (u64*)(b + o_rows);
+  u64* d_base = (u64*)(b + o_base);
+  int32_t* list = (int32_t*)(b + o_list);
+  unsigned* hist = (unsigned*)(b + o_hist);
+  unsigned* cur = (unsigned*)(b + o_cur);
+  DIST_CHECK(hipMemcpyAsync(d_base, base.data(), base.size() * sizeof(u64), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_zero_u32, dim3((kBins + 63) / 64), dim3(64), 0, s, hist, kBins);
+  for (const Bucket& bk : make_buckets(g, nh)) {
+    EdgePrep ep{g->dptr, g->dcol, g->roots, d_base, bk.begin, bk.end, k, prune, bk.D, recs, rows, hist};
+    const int rc = with_width(bk.W, [&](auto w) { return launch_edge_rows<decltype(w)::value>(ep, bk.end - bk.begin, s); });
+    if (rc) return rc;
+  }
+  std::vector<unsigned> h(kBins), c(kBins, 0u);
+  DIST_CHECK(hipMemcpyAsync(h.data(), hist, kBins * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  DIST_CHECK(hipStreamSynchronize(s));
+  es->hist.clear();
+  unsigned off = 0;
+  for (int d = kBins - 1; d >= 1; --d) {
+    c[d] = off;
+    off += h[d];
+    if (h[d]) es->hist.push_back({d, (int64_t)h[d]});
+  }
+  es->n = (int32_t)off;
+  es->recs = recs;
+  es->rows = rows;
+  es->list = list;
+  if (off == 0) return DIST_OK;
+  DIST_CHECK(hipMemcpyAsync(cur, c.data(), kBins * sizeof(unsigned), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_edge_order, dim3(512), dim3(256), 0, s, recs, nrec, cur, list);
+  DIST_CHECK(hipGetLastError());
+  // the host vectors are read by the copies above before they go out of scope
+  DIST_CHECK(hipStreamSynchronize(s));
+  return DIST_OK;
+}
 
 // Segments of one graph's count: consecutive roots of equal out-degree fall
 // into one segment, so a class holds at most as many segments as there are
@@ -1959,8 +2222,27 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   uint64_t units64[kClasses] = {};
   int kmax[kClasses] = {};
   int sub_of[kClasses];
-  split_children(g, nroots, base.k, cw, cfg.sub_units, sub_of);
-  add_segments(g, 0, nroots, base.k, cw, base.soft_only != 0, 1, sub_of, segs, units64, kmax);
+  int dmax[kClasses] = {};
+  // EdgeParallel units for the heavy roots, a prefix of the roots (they are
+  // in descending out-degree order); their segments come first in each class
+  int32_t nh = 0;
+  EdgeSet es;
+  // automatic: roots of 4 or more words for k = 5..7, of 5 or more for larger
+  // k (their arcs' sets then still fill several words)
+  const int ew = cfg.edge_units != 0 ? cfg.edge_units : base.k >= 8 ? 5 : base.k >= 5 ? 4 : -1;
+  if (ew > 0 && !fixed && !base.soft_only && base.tau == 0 && base.k >= 4) {
+    while (nh < nroots && width_of(g->root_deg[nh]) >= ew) ++nh;
+    if (nh > 0) {
+      if (int re = edge_prepare(g, nh, base.k, base.prune, s, &es)) return re;
+      std::vector<int> sub_d;
+      split_edges(es.hist, es.n, base.k - 1, cfg.sub_units, sub_d);
+      add_segments(es.hist, 1, 0, es.n, base.k - 1, cw, false, 1, sub_of, segs, units64, kmax, dmax, true,
+                   sub_d.data());
+    }
+  }
+  split_children(g->deg_hist, nh, nroots, base.k, cw, cfg.sub_units, sub_of);
+  add_segments(g->deg_hist, 0, nh, nroots, base.k, cw, base.soft_only != 0, 1, sub_of, segs, units64, kmax, dmax);
+  const int nbg = nh > 0 ? 2 : 1;
   Bucket buckets[kClasses];
   uint32_t units[kClasses];
   size_t seg_off[kClasses];
@@ -1971,7 +2253,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     if (units64[sl] == 0) continue;
     if (units64[sl] >= 0xffffffffull) return DIST_E_UNSUPPORTED;
     // roots are in descending out-degree order: a class's first root is its widest
-    buckets[nbk] = Bucket{kSlotWidth[sl], 0, 0, lds_rows(kSlotWidth[sl], g->root_deg[segs[sl][0].a])};
+    buckets[nbk] = Bucket{kSlotWidth[sl], 0, 0, lds_rows(kSlotWidth[sl], dmax[sl])};
     units[nbk] = (uint32_t)units64[sl];
     seg_off[nbk] = nseg_total;
     ++nbk;
@@ -2027,7 +2309,7 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   u64* host_out;
   char* d_plan;
   char* h_plan;
-  const size_t plan_bytes = sizeof(BatchGraph) + sizeof(BatchSeg) * (nseg_total + 1);
+  const size_t plan_bytes = nbg * sizeof(BatchGraph) + sizeof(BatchSeg) * (nseg_total + 1);
   int rc = DIST_OK;
   if (fixed) {
     cursor = (unsigned*)fixed;
@@ -2048,18 +2330,22 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
     d_plan = g_ws.d_plan;
     h_plan = g_ws.h_plan;
   }
-  // device plan: the graph descriptor, then the segments of every class
+  // device plan: the graph descriptors (the roots; the edge units), then the
+  // segments of every class
   {
-    BatchGraph bgh{g->dptr, g->dcol, g->orig, g->roots, g->gw, base.k, 0};
-    memcpy(h_plan, &bgh, sizeof(bgh));
-    BatchSeg* hs = (BatchSeg*)(h_plan + sizeof(BatchGraph));
+    BatchGraph bgh[2] = {{g->dptr, g->dcol, g->orig, g->roots, g->gw, base.k, 0},
+                         {g->dptr, g->dcol, g->orig, es.list, g->gw, base.k - 1, 0}};
+    bgh[1].edges = es.recs;
+    bgh[1].erows = es.rows;
+    memcpy(h_plan, bgh, nbg * sizeof(BatchGraph));
+    BatchSeg* hs = (BatchSeg*)(h_plan + nbg * sizeof(BatchGraph));
     size_t o = 0;
     for (int sl = 0; sl < kClasses; ++sl)
       for (size_t i = 0; i < segs[sl].size(); ++i) hs[o++] = segs[sl][i];
     DIST_CHECK(hipMemcpyAsync(d_plan, h_plan, plan_bytes, hipMemcpyHostToDevice, s));
   }
   const BatchGraph* d_bg = (const BatchGraph*)d_plan;
-  const BatchSeg* d_segs = (const BatchSeg*)(d_plan + sizeof(BatchGraph));
+  const BatchSeg* d_segs = (const BatchSeg*)(d_plan + nbg * sizeof(BatchGraph));
 
   hipEvent_t e0 = nullptr, e1 = nullptr, kb0 = nullptr, kb1 = nullptr;
   if (!fixed) {

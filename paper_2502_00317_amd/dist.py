@@ -39,7 +39,8 @@ class Config(ctypes.Structure):
                 ("chunk_work", ctypes.c_int32), ("grid_pct", ctypes.c_int32),
                 ("budget_from_pair_start", ctypes.c_int32), ("min_width", ctypes.c_int32),
                 ("sub_units", ctypes.c_int32), ("trie_nodes", ctypes.c_int32),
-                ("list_bytes", ctypes.c_int64), ("trie_tau", ctypes.c_int64)]
+                ("list_bytes", ctypes.c_int64), ("trie_tau", ctypes.c_int64),
+                ("edge_units", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

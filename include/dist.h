@@ -140,8 +140,7 @@ typedef struct {
                             G[N+(u) & N+(v)] for (k - 2)-cliques, each unit
                             in the width class of its own set (a pre-pass
                             builds G_u once to find the sets); 0 = auto
-                            (W = 4 for k = 5..7, W = 5 for k >= 8, off for
-                            k < 5); -1 = off.  Ignored with trie_tau > 0,
+                            (W = 4 for k >= 5, off for k < 5); -1 = off.  Ignored with trie_tau > 0,
                             k < 4 and by dist_count_noalloc, dist_count_all
                             and the batched calls.  Results do not depend
                             on it; work counters count the arcs as roots */

@@ -1922,9 +1922,11 @@ void split_children(const dist_graph* g, int32_t nroots, int k, int cw, int forc
 
 // The same for EdgeParallel units (clique size k counted from the arc's set,
 // i.e. one less than the query's), each one range of children, per set size
-// d: a unit costs about d (d/64)^(k-3), its heaviest depth-1 subtree
-// 2^(k-4) times the mean, and units are shared out where that would hold
-// their launch past the mean load of a wave.  sub_d[d] for d <= DIST_MAX_OUTDEG.
+// d: a unit costs about d (d/64)^(k-3) on average, but the arcs of equal
+// set size differ widely (a dense core's arcs carry most of the work), so a
+// run is shared out where 2^(k-2) times that mean (a factor measured on
+// power-law graphs with planted cliques, k = 6..8) exceeds the mean load of
+// a wave.  sub_d[d] for d <= DIST_MAX_OUTDEG.
 void split_edges(const DegHist& h, int32_t n, int k, int forced, std::vector<int>& sub_d) {
   sub_d.assign(DIST_MAX_OUTDEG + 1, 1);
   if (k < 6) return;
@@ -1938,7 +1940,7 @@ void split_edges(const DegHist& h, int32_t n, int k, int forced, std::vector<int
   const double waves = 8.0 * (g_ws.cus > 0 ? g_ws.cus : 256);
   for_runs(h, 0, n, [&](int d, int32_t, int32_t) {
     const double t = total[wslot_of_width(width_of(d))];
-    const double r = t > 0 ? unit(d) * std::ldexp(1.0, k - 4) * waves / t : 0.0;
+    const double r = t > 0 ? unit(d) * std::ldexp(1.0, k - 2) * waves / t : 0.0;
     int sub = 1;
     while (sub < kMaxSub && sub < r) sub <<= 1;
     sub_d[d] = sub;
@@ -2227,9 +2229,9 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   // in descending out-degree order); their segments come first in each class
   int32_t nh = 0;
   EdgeSet es;
-  // automatic: roots of 4 or more words for k = 5..7, of 5 or more for larger
-  // k (their arcs' sets then still fill several words)
-  const int ew = cfg.edge_units != 0 ? cfg.edge_units : base.k >= 8 ? 5 : base.k >= 5 ? 4 : -1;
+  // automatic: roots of 4 or more words for k >= 5 (their arcs' sets then
+  // still fill one word or more)
+  const int ew = cfg.edge_units != 0 ? cfg.edge_units : base.k >= 5 ? 4 : -1;
   if (ew > 0 && !fixed && !base.soft_only && base.tau == 0 && base.k >= 4) {
     while (nh < nroots && width_of(g->root_deg[nh]) >= ew) ++nh;
     if (nh > 0) {

@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--no-pivot", action="store_true", help="skip the pivot-based all-k section")
     ap.add_argument("--no-cfg3", action="store_true", help="skip the dense-core R-MAT attempt")
     ap.add_argument("--cfg3-deadline-ms", type=int, default=5000)
+    ap.add_argument("--cfg3-k6-deadline-ms", type=int, default=200000,
+                    help="deadline of the dense-core k=6 count (degree order); 0 skips it")
     ap.add_argument("--out", default="")
     return ap.parse_args()
 
@@ -658,8 +660,9 @@ def run_listing(a, dist, torch, log):
 def run_cfg3(a, dist, torch, log):
     """The dense-core stress graph (R-MAT scale 22, edge factor 16, 10 planted
     60-cliques): orientation, then k = 6 and 8 by the search and every k <= 12
-    by pivoting, each under a deadline; a count that does not finish is
-    reported as DNF."""
+    by pivoting, each under a short deadline, and k = 6 again in degree order
+    under a long one (the heavy roots' arcs as EdgeParallel units); a count
+    that does not finish is reported as DNF."""
     from paper_2502_00317_amd import graphgen as gg
     t = time.time()
     g = gg.dense_core_rmat()
@@ -691,6 +694,23 @@ def run_cfg3(a, dist, torch, log):
         out["pivot"]["counts"] = {str(k): [str(res[k][0]), str(res[k][1])] for k in range(13)}
     log("dense-core R-MAT pivot k<=12: %s" % out["pivot"]["status"])
     G.free()
+    if a.cfg3_k6_deadline_ms > 0:
+        H = dist.orient(g.row_ptr, g.col, order=dist.ORDER_DEGREE)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        try:
+            c, f, rc = dist.count(H, 6, cfg=dist.config(deadline_ms=a.cfg3_k6_deadline_ms))
+            torch.cuda.synchronize()
+            s = time.perf_counter() - t
+            st = H.stats()
+            out["k6_degree_order"] = {"status": "finished", "count": str(c), "fp": str(f), "s": s,
+                                      "cliques_per_s": c / s, "kernel_ms": st.kernel_ms, "units": st.roots,
+                                      "deadline_ms": a.cfg3_k6_deadline_ms}
+        except dist.DistError as e:
+            out["k6_degree_order"] = {"status": "DNF" if e.status == dist.E_CANCELLED else "error %d" % e.status,
+                                      "deadline_ms": a.cfg3_k6_deadline_ms}
+        log("dense-core R-MAT k=6 (degree order): %s" % out["k6_degree_order"]["status"])
+        H.free()
     return out
 
 

@@ -153,7 +153,12 @@ def test_batched_workload_every_pair(D, oracle_mod):
         Gi.free()
 
 
-def test_dense_core_rmat_orientation_and_budget(D):
+@pytest.fixture(scope="module")
+def rmat():
+    return gg.dense_core_rmat()
+
+
+def test_dense_core_rmat_orientation_and_budget(D, rmat):
     """The dense-core stress graph (R-MAT scale 22, 64M edges): degeneracy
     order bounds every out-degree by the degeneracy the oracle computes
     (stored by tests/golden/make_rmat_degeneracy.py); both orders keep every
@@ -163,7 +168,7 @@ def test_dense_core_rmat_orientation_and_budget(D):
     import json
     import os
     fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rmat_s22_degeneracy.json")))
-    g = gg.dense_core_rmat()
+    g = rmat
     assert (g.n, g.m) == (fx["n"], fx["m"])
     G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGENERACY)
     info = G.info()
@@ -176,3 +181,44 @@ def test_dense_core_rmat_orientation_and_budget(D):
         with pytest.raises(D.DistError) as e:
             D.count(X, 6, cfg=D.config(fingerprint=0, deadline_ms=3000))
         assert e.value.status == D.E_CANCELLED
+
+
+def test_dense_core_rmat_k6_counted(D, oracle_mod, rmat):
+    """k = 6 on the dense-core graph in degree order, which the heavy roots'
+    arcs as EdgeParallel units bring within about two minutes: the total and
+    fingerprint equal the sum of the per-root results; roots the enumerating
+    oracle finishes quickly and mid-size roots (64 <= d+ < 512, through the
+    oracle's pivot-based counter) equal the oracle's one by one.  The ~9,000
+    roots of d+ >= 512 (the dense core) are beyond the CPU oracle: parity
+    unpinned there."""
+    g = rmat
+    k = 6
+    G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+    per = np.zeros(3 * g.n, np.uint64)
+    print("dense core k=6 with per-root output", flush=True)
+    total, tfp, rc = D.count(G, k, cfg=D.config(deadline_ms=300000), per_root=per)
+    assert rc == D.OK
+    lo = per[0::3].astype(object)
+    hi = per[1::3].astype(object)
+    assert int(sum(lo)) + (int(sum(hi)) << 64) == total
+    P61 = (1 << 61) - 1
+    assert sum(int(x) for x in per[2::3]) % P61 == tfp
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    ks = deg[src] * (g.n + 1) + src
+    kd = deg[g.col] * (g.n + 1) + g.col
+    outd = np.bincount(src[ks < kd], minlength=g.n)
+
+    def check(roots, want):
+        for v, (wc, wf) in zip(roots, want):
+            assert int(per[3 * v]) | (int(per[3 * v + 1]) << 64) == wc, (int(v), int(outd[v]))
+            assert int(per[3 * v + 2]) == wf, int(v)
+
+    roots = _sample_roots(outd, k, 2e6, 2000, 0, 300 + k)
+    print("  %d enumerable roots" % len(roots), flush=True)
+    check(roots, oracle_mod.count_roots(g.row_ptr, g.col, k, roots))
+    rng = np.random.default_rng(400 + k)
+    mid = np.concatenate([rng.choice(np.flatnonzero((outd >= a) & (outd < b)), 12, replace=False)
+                          for a, b in ((64, 128), (128, 256), (256, 512))]).astype(np.int32)
+    print("  %d mid-size roots by pivoting" % len(mid), flush=True)
+    check(mid, oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, mid))

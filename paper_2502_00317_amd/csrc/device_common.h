@@ -27,10 +27,19 @@ __device__ __forceinline__ u64 subp(u64 a, u64 b) {
   return a >= b ? a - b : a + (DIST_P61 - b);
 }
 
+// a, b < p.  With a = a1 2^32 + a0 and b = b1 2^32 + b0 (a1, b1 < 2^29),
+// a b = a1 b1 2^64 + (a0 b1 + a1 b0) 2^32 + a0 b0, and since 2^61 = 1 mod p:
+// 2^64 = 8, a middle term m = mh 2^29 + ml gives m 2^32 = mh + ml 2^32, and
+// a0 b0 = (its bits from 61 up) + (its low 61 bits).  Four 32 x 32 -> 64
+// multiply-adds in place of the six multiplies of a full 64 x 64 -> 128
+// product; the sum of the five terms stays below 2^63.
 __device__ __forceinline__ u64 mulp(u64 a, u64 b) {
-  u64 lo = a * b;
-  u64 hi = __umul64hi(a, b);
-  u64 r = (lo & DIST_P61) + ((hi << 3) | (lo >> 61));
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const u64 p00 = (u64)a0 * b0;
+  const u64 mid = (u64)a0 * b1 + (u64)a1 * b0;
+  const u64 p11 = (u64)a1 * b1;
+  u64 r = (p11 << 3) + (mid >> 29) + ((mid & ((1ull << 29) - 1)) << 32) + (p00 >> 61) + (p00 & DIST_P61);
   r = (r & DIST_P61) + (r >> 61);
   return r >= DIST_P61 ? r - DIST_P61 : r;
 }

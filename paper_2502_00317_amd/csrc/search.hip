@@ -882,6 +882,94 @@ __device__ __forceinline__ void leaf3_count(const Lds& s, const u64 (&Pr)[W], in
   fp = FP ? wave_sum_p(f_acc) : 0;
 }
 
+// Children x of a frame with l = 4 (the bits of Q) whose sets P & A[x] are
+// complete, or hold fewer than 3 vertices, one child per lane: a complete
+// set of n vertices holds C(n, 3) triangles, and their fingerprint sum is
+// e_3 of its weights, taken member by member (e_3 += e_2 g, e_2 += e_1 g,
+// e_1 += g).  Such children leave Q, and their totals come back summed over
+// the wave (fp with each child's own weight); the others stay in Q for the
+// wave-wide leaf count.  A lane's completeness test stops at the first
+// member short of its forward neighbours.  s.pos is scratch.
+struct LeafSum {
+  u64 lo, fp, wops;
+};
+
+template <int W, bool FP>
+__device__ __noinline__ LeafSum leaf_complete_children(const Lds& s, u64* Q, const u64* P_) {
+  const auto* A = as_lds(s.A);
+  const auto* gl = as_lds(s.gl);
+  const auto* P = as_lds(P_);
+  const auto* Qr = as_lds(Q);
+  const int lane = lane_id();
+  u64 Pr[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) Pr[w] = P[w];
+  int nq = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const u64 bw = Qr[w];
+    if ((bw >> lane) & 1ull) s.pos[nq + __popcll(bw & lanemask_lt())] = (uint16_t)(w * 64 + lane);
+    nq += __popcll(bw);
+  }
+  __syncthreads();
+  u64 lo = 0, fp = 0, wops = 0;
+  for (int i0 = 0; i0 < nq; i0 += kWave) {
+    const int i = i0 + lane;
+    if (i >= nq) continue;
+    const int x = s.pos[i];
+    u64 c[W];
+    int n = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      c[w] = Pr[w] & A[x * W + w];
+      n += __popcll(c[w]);
+    }
+    wops += W;
+    bool take = n < 3;
+    if (!take) {
+      bool comp = true;
+      int above = n;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        u64 b = c[w];
+        while (b && comp) {
+          const int y = w * 64 + __ffsll((unsigned long long)b) - 1;
+          b &= b - 1;
+          --above;
+          int cy = 0;
+#pragma unroll
+          for (int v = 0; v < W; ++v) cy += __popcll(c[v] & A[y * W + v]);
+          wops += W;
+          comp = cy == above;
+        }
+      }
+      if (comp) {
+        take = true;
+        lo += (u64)n * (u64)(n - 1) * (u64)(n - 2) / 6;
+        if (FP) {
+          u64 e1 = 0, e2 = 0, e3 = 0;
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            u64 b = c[w];
+            while (b) {
+              const int y = w * 64 + __ffsll((unsigned long long)b) - 1;
+              b &= b - 1;
+              const u64 g = gl[y];
+              e3 = addp(e3, mulp(e2, g));
+              e2 = addp(e2, mulp(e1, g));
+              e1 = addp(e1, g);
+            }
+          }
+          fp = addp(fp, mulp(gl[x], e3));
+        }
+      }
+    }
+    if (take) atomicAnd((unsigned long long*)&Q[x >> 6], ~(1ull << (x & 63)));
+  }
+  __syncthreads();
+  return LeafSum{wave_sum(lo), FP ? wave_sum_p(fp) : 0ull, wops};
+}
+
 // ---- the kernel ----------------------------------------------------------------
 
 // Counting kernels of up to 6 words are held to 256 VGPRs, i.e. two waves per
@@ -1427,6 +1515,16 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             const bool memo_c = memo_mode == 2 || (memo_mode == 1 && memo_j);
             const u64 ctag = (mtag << 8) | 3ull;
             __syncthreads();
+            if (!(memo_j && memo_live && j > 0 && j != jsplit)) {
+              // complete (and tiny) child sets first, one child per lane;
+              // a frame that stores its prefixes in the memo keeps the order
+              const LeafSum ls = leaf_complete_children<W, FP>(s, Q, s.stP + j * W);
+              const u64 nlo = acc_lo + ls.lo;
+              acc_hi += nlo < acc_lo ? 1ull : 0ull;
+              acc_lo = nlo;
+              if (FP) acc_fp = addp(acc_fp, ls.fp);
+              wops += ls.wops;
+            }
             while (true) {
               int x = -1;
               for (int w = W - 1; w >= 0; --w) {

@@ -970,6 +970,104 @@ __device__ __noinline__ LeafSum leaf_complete_children(const Lds& s, u64* Q, con
   return LeafSum{wave_sum(lo), FP ? wave_sum_p(fp) : 0ull, wops};
 }
 
+// The same for the children of deeper frames, whose child frames need L
+// vertices (4 <= L <= kLaneEsymMaxL): a complete set of n vertices holds
+// C(n, L) L-cliques, and their fingerprint sum is e_L of its weights
+// (member by member, e_t += e_{t-1} g for t = L .. 1).  Such children leave
+// Q; with count = false (the children of a unit's root frame that are shared
+// split frames, outside sub-unit 0) they add nothing, as their own frames
+// would.  A set whose binomial does not fit 128 bits stays in Q.
+constexpr int kLaneEsymMaxL = 8;
+
+struct ChildSum {
+  u64 lo, hi, fp, wops;
+};
+
+template <int W, bool FP>
+__device__ __noinline__ ChildSum complete_children(const Lds& s, u64* Q, const u64* P_, int L, bool count) {
+  const auto* A = as_lds(s.A);
+  const auto* gl = as_lds(s.gl);
+  const auto* P = as_lds(P_);
+  const auto* Qr = as_lds(Q);
+  const int lane = lane_id();
+  u64 Pr[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) Pr[w] = P[w];
+  int nq = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const u64 bw = Qr[w];
+    if ((bw >> lane) & 1ull) s.pos[nq + __popcll(bw & lanemask_lt())] = (uint16_t)(w * 64 + lane);
+    nq += __popcll(bw);
+  }
+  __syncthreads();
+  u64 lo = 0, hi = 0, fp = 0, wops = 0;
+  for (int i0 = 0; i0 < nq; i0 += kWave) {
+    const int i = i0 + lane;
+    if (i >= nq) continue;
+    const int x = s.pos[i];
+    u64 c[W];
+    int n = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      c[w] = Pr[w] & A[x * W + w];
+      n += __popcll(c[w]);
+    }
+    wops += W;
+    bool comp = true;
+    int above = n;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      u64 b = c[w];
+      while (b && comp) {
+        const int y = w * 64 + __ffsll((unsigned long long)b) - 1;
+        b &= b - 1;
+        --above;
+        int cy = 0;
+#pragma unroll
+        for (int v = 0; v < W; ++v) cy += __popcll(c[v] & A[y * W + v]);
+        wops += W;
+        comp = cy == above;
+      }
+    }
+    if (!comp) continue;
+    if (count) {
+      u64 blo, bhi;
+      if (!binom128(n, L, blo, bhi)) continue;
+      const u64 nlo = lo + blo;
+      hi += bhi + (nlo < lo ? 1ull : 0ull);
+      lo = nlo;
+      if (FP) {
+        u64 e[kLaneEsymMaxL + 1];
+        e[0] = 1;
+#pragma unroll
+        for (int t = 1; t <= kLaneEsymMaxL; ++t) e[t] = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          u64 b = c[w];
+          while (b) {
+            const int y = w * 64 + __ffsll((unsigned long long)b) - 1;
+            b &= b - 1;
+            const u64 g = gl[y];
+#pragma unroll
+            for (int t = kLaneEsymMaxL; t >= 1; --t)
+              if (t <= L) e[t] = addp(e[t], mulp(e[t - 1], g));
+          }
+        }
+        u64 eL = 0;
+#pragma unroll
+        for (int t = 1; t <= kLaneEsymMaxL; ++t)
+          if (t == L) eL = e[t];
+        fp = addp(fp, mulp(gl[x], eL));
+      }
+    }
+    atomicAnd((unsigned long long*)&Q[x >> 6], ~(1ull << (x & 63)));
+  }
+  __syncthreads();
+  wave_sum128(lo, hi);
+  return ChildSum{lo, hi, FP ? wave_sum_p(fp) : 0ull, wops};
+}
+
 // ---- the kernel ----------------------------------------------------------------
 
 // Counting kernels of up to 6 words are held to 256 VGPRs, i.e. two waves per
@@ -1608,6 +1706,15 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             mode = FINISH;
             continue;
           }
+        }
+        if (l - 1 <= kLaneEsymMaxL && !(memo_j && memo_live && j > 0 && j != jsplit)) {
+          // complete child sets first, one child per lane (as for l = 4)
+          const ChildSum cs = complete_children<W, FP>(s, Q, s.stP + j * W, l - 1, !(j + 1 == jsplit && sub != 0));
+          const u64 nlo = acc_lo + cs.lo;
+          acc_hi += cs.hi + (nlo < acc_lo ? 1ull : 0ull);
+          acc_lo = nlo;
+          if (FP) acc_fp = addp(acc_fp, cs.fp);
+          wops += cs.wops;
         }
         if (lane == 0) {
           s.stCnt[2 * j] = acc_lo;

@@ -65,11 +65,15 @@ constexpr int kMemoProbe = 1;
 // forms already cover the dense branches, hits mostly save single leaf
 // frames and do not repay the lookups and inserts; one hit in four lookups
 // is about where they break even, and inserts (a trie node after each child)
-// outnumber lookups, so they are bounded on their own.
-constexpr int kMemoMinLook = 1024;
+// outnumber lookups, so they are bounded on their own.  A wave stops for
+// all its later units once kMemoWaveIns inserts drew fewer than one hit in
+// kMemoWaveRatio.  The samples are short: a launch holds thousands of waves,
+// and since complete child sets are counted without frames, a hit saves
+// little, so an unproductive table costs more than a late decision gains.
+constexpr int kMemoMinLook = 256;
 constexpr int kMemoMinRatio = 4;
 constexpr int kMemoMinInsRatio = 8;
-constexpr u64 kMemoWaveIns = 4096;
+constexpr u64 kMemoWaveIns = 256;
 constexpr u64 kMemoWaveRatio = 16;
 
 // Batched counting: one entry per (graph, k) pair, and the units of a

@@ -886,106 +886,54 @@ __device__ __forceinline__ void leaf3_count(const Lds& s, const u64 (&Pr)[W], in
   fp = FP ? wave_sum_p(f_acc) : 0;
 }
 
-// Children x of a frame with l = 4 (the bits of Q) whose sets P & A[x] are
-// complete, or hold fewer than 3 vertices, one child per lane: a complete
-// set of n vertices holds C(n, 3) triangles, and their fingerprint sum is
-// e_3 of its weights, taken member by member (e_3 += e_2 g, e_2 += e_1 g,
-// e_1 += g).  Such children leave Q, and their totals come back summed over
-// the wave (fp with each child's own weight); the others stay in Q for the
-// wave-wide leaf count.  A lane's completeness test stops at the first
-// member short of its forward neighbours.  s.pos is scratch.
-struct LeafSum {
-  u64 lo, fp, wops;
-};
-
-template <int W, bool FP>
-__device__ __noinline__ LeafSum leaf_complete_children(const Lds& s, u64* Q, const u64* P_) {
-  const auto* A = as_lds(s.A);
-  const auto* gl = as_lds(s.gl);
-  const auto* P = as_lds(P_);
-  const auto* Qr = as_lds(Q);
-  const int lane = lane_id();
-  u64 Pr[W];
-#pragma unroll
-  for (int w = 0; w < W; ++w) Pr[w] = P[w];
-  int nq = 0;
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    const u64 bw = Qr[w];
-    if ((bw >> lane) & 1ull) s.pos[nq + __popcll(bw & lanemask_lt())] = (uint16_t)(w * 64 + lane);
-    nq += __popcll(bw);
-  }
-  __syncthreads();
-  u64 lo = 0, fp = 0, wops = 0;
-  for (int i0 = 0; i0 < nq; i0 += kWave) {
-    const int i = i0 + lane;
-    if (i >= nq) continue;
-    const int x = s.pos[i];
-    u64 c[W];
-    int n = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      c[w] = Pr[w] & A[x * W + w];
-      n += __popcll(c[w]);
-    }
-    wops += W;
-    bool take = n < 3;
-    if (!take) {
-      bool comp = true;
-      int above = n;
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        u64 b = c[w];
-        while (b && comp) {
-          const int y = w * 64 + __ffsll((unsigned long long)b) - 1;
-          b &= b - 1;
-          --above;
-          int cy = 0;
-#pragma unroll
-          for (int v = 0; v < W; ++v) cy += __popcll(c[v] & A[y * W + v]);
-          wops += W;
-          comp = cy == above;
-        }
-      }
-      if (comp) {
-        take = true;
-        lo += (u64)n * (u64)(n - 1) * (u64)(n - 2) / 6;
-        if (FP) {
-          u64 e1 = 0, e2 = 0, e3 = 0;
-#pragma unroll
-          for (int w = 0; w < W; ++w) {
-            u64 b = c[w];
-            while (b) {
-              const int y = w * 64 + __ffsll((unsigned long long)b) - 1;
-              b &= b - 1;
-              const u64 g = gl[y];
-              e3 = addp(e3, mulp(e2, g));
-              e2 = addp(e2, mulp(e1, g));
-              e1 = addp(e1, g);
-            }
-          }
-          fp = addp(fp, mulp(gl[x], e3));
-        }
-      }
-    }
-    if (take) atomicAnd((unsigned long long*)&Q[x >> 6], ~(1ull << (x & 63)));
-  }
-  __syncthreads();
-  return LeafSum{wave_sum(lo), FP ? wave_sum_p(fp) : 0ull, wops};
-}
-
-// The same for the children of deeper frames, whose child frames need L
-// vertices (4 <= L <= kLaneEsymMaxL): a complete set of n vertices holds
-// C(n, L) L-cliques, and their fingerprint sum is e_L of its weights
-// (member by member, e_t += e_{t-1} g for t = L .. 1).  Such children leave
-// Q; with count = false (the children of a unit's root frame that are shared
-// split frames, outside sub-unit 0) they add nothing, as their own frames
-// would.  A set whose binomial does not fit 128 bits stays in Q.
+// Children x of a frame (the bits of Q) whose child frames need L vertices
+// (3 <= L <= kLaneEsymMaxL) and whose sets c = P & A[x] are complete or miss
+// at most two edges, one child per lane instead of a frame each.  A lane
+// lists the missing edges of G[c] (its test stops at a third).  By
+// inclusion-exclusion over the subsets S of the missing edges, with V(S)
+// their endpoints, c holds
+//   sum_S (-1)^|S| C(n - |V(S)|, L - |V(S)|)
+// L-cliques, with fingerprint sum
+//   sum_S (-1)^|S| prod_{v in V(S)} g(v) e_{L-|V(S)|}(c \ V(S)),
+// where the polynomial prod_{v in c} (1 + g(v) t) is built member by member
+// (e_t += e_{t-1} g) and divided by (1 + g(v) t) for each v in V(S).  Such
+// children leave Q; with count = false (the children of a unit's root frame
+// that are shared split frames, outside sub-unit 0) they add nothing, as
+// their own frames would.  A set whose binomials do not fit 128 bits stays
+// in Q.  s.pos is scratch.
 constexpr int kLaneEsymMaxL = 8;
 
 struct ChildSum {
   u64 lo, hi, fp, wops;
 };
+
+// C(n, r) as 128 bits (0 outside 0 <= r <= n); false if it does not fit.
+__device__ __forceinline__ bool binom_or_zero(int n, int r, u64& lo, u64& hi) {
+  if (r < 0 || r > n) {
+    lo = hi = 0;
+    return true;
+  }
+  return binom128(n, r, lo, hi);
+}
+
+// e_r of (prod over c of (1 + g t)) / prod over the removed vertices of
+// (1 + g(v) t), the quotient taken in place on a copy of the coefficients.
+__device__ __forceinline__ u64 quotient_coef(const u64 (&e)[kLaneEsymMaxL + 1], const u64* gv, int nv, int L,
+                                             int r) {
+  u64 q[kLaneEsymMaxL + 1];
+#pragma unroll
+  for (int t = 0; t <= kLaneEsymMaxL; ++t) q[t] = e[t];
+  for (int i = 0; i < nv; ++i) {
+#pragma unroll
+    for (int t = 1; t <= kLaneEsymMaxL; ++t)
+      if (t <= L) q[t] = subp(q[t], mulp(gv[i], q[t - 1]));
+  }
+  u64 out = 0;
+#pragma unroll
+  for (int t = 0; t <= kLaneEsymMaxL; ++t)
+    if (t == r) out = q[t];
+  return out;
+}
 
 template <int W, bool FP>
 __device__ __noinline__ ChildSum complete_children(const Lds& s, u64* Q, const u64* P_, int L, bool count) {
@@ -1018,12 +966,13 @@ __device__ __noinline__ ChildSum complete_children(const Lds& s, u64* Q, const u
       n += __popcll(c[w]);
     }
     wops += W;
-    bool comp = true;
+    // the missing edges (y, z), y < z, of G[c]: at most two are kept
+    int miss = 0, a0 = 0, b0 = 0, a1 = 0, b1 = 0;
     int above = n;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
       u64 b = c[w];
-      while (b && comp) {
+      while (b && miss <= 2) {
         const int y = w * 64 + __ffsll((unsigned long long)b) - 1;
         b &= b - 1;
         --above;
@@ -1031,15 +980,47 @@ __device__ __noinline__ ChildSum complete_children(const Lds& s, u64* Q, const u
 #pragma unroll
         for (int v = 0; v < W; ++v) cy += __popcll(c[v] & A[y * W + v]);
         wops += W;
-        comp = cy == above;
+        if (cy == above) continue;
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+          u64 mz = c[v] & cut_mask(y + 1, v) & ~A[y * W + v];
+          while (mz && miss <= 2) {
+            const int z = v * 64 + __ffsll((unsigned long long)mz) - 1;
+            mz &= mz - 1;
+            if (miss == 0) {
+              a0 = y;
+              b0 = z;
+            } else if (miss == 1) {
+              a1 = y;
+              b1 = z;
+            }
+            ++miss;
+          }
+        }
       }
     }
-    if (!comp) continue;
+    if (miss > 2) continue;
+    // endpoints of both edges (3 if they share one, else 4)
+    const int nv2 = 4 - (a1 == a0 || a1 == b0) - (b1 == a0 || b1 == b0);
+    u64 c0l, c0h, c1l = 0, c1h = 0, c2l = 0, c2h = 0;
+    // the same test in every unit that shares the frame
+    if (!binom_or_zero(n, L, c0l, c0h)) continue;
+    if (miss >= 1 && !binom_or_zero(n - 2, L - 2, c1l, c1h)) continue;
+    if (miss == 2 && !binom_or_zero(n - nv2, L - nv2, c2l, c2h)) continue;
     if (count) {
-      u64 blo, bhi;
-      if (!binom128(n, L, blo, bhi)) continue;
-      const u64 nlo = lo + blo;
-      hi += bhi + (nlo < lo ? 1ull : 0ull);
+      // c0 - miss * c1 + [miss == 2] c2 (never negative)
+      u64 tl = c0l, th = c0h;
+      for (int m = 0; m < miss; ++m) {
+        th -= c1h + (tl < c1l ? 1ull : 0ull);
+        tl -= c1l;
+      }
+      if (miss == 2) {
+        const u64 nl = tl + c2l;
+        th += c2h + (nl < tl ? 1ull : 0ull);
+        tl = nl;
+      }
+      const u64 nlo = lo + tl;
+      hi += th + (nlo < lo ? 1ull : 0ull);
       lo = nlo;
       if (FP) {
         u64 e[kLaneEsymMaxL + 1];
@@ -1054,15 +1035,34 @@ __device__ __noinline__ ChildSum complete_children(const Lds& s, u64* Q, const u
             b &= b - 1;
             const u64 g = gl[y];
 #pragma unroll
-            for (int t = kLaneEsymMaxL; t >= 1; --t)
+            for (int t = kLaneEsymMaxL; t >= 2; --t)
               if (t <= L) e[t] = addp(e[t], mulp(e[t - 1], g));
+            e[1] = addp(e[1], g);
           }
         }
-        u64 eL = 0;
+        u64 f = 0;
 #pragma unroll
         for (int t = 1; t <= kLaneEsymMaxL; ++t)
-          if (t == L) eL = e[t];
-        fp = addp(fp, mulp(gl[x], eL));
+          if (t == L) f = e[t];
+        if (miss >= 1) {
+          const u64 g2[2] = {gl[a0], gl[b0]};
+          f = subp(f, mulp(mulp(g2[0], g2[1]), quotient_coef(e, g2, 2, L, L - 2)));
+        }
+        if (miss == 2) {
+          const u64 g2[2] = {gl[a1], gl[b1]};
+          f = subp(f, mulp(mulp(g2[0], g2[1]), quotient_coef(e, g2, 2, L, L - 2)));
+          // both edges: their distinct endpoints
+          u64 gv[4];
+          int nv = 0;
+          gv[nv++] = gl[a0];
+          gv[nv++] = gl[b0];
+          if (a1 != a0 && a1 != b0) gv[nv++] = gl[a1];
+          if (b1 != a0 && b1 != b0) gv[nv++] = gl[b1];
+          u64 pv = 1;
+          for (int q = 0; q < nv; ++q) pv = mulp(pv, gv[q]);
+          f = addp(f, mulp(pv, L - nv >= 0 ? quotient_coef(e, gv, nv, L, L - nv) : 0ull));
+        }
+        fp = addp(fp, mulp(gl[x], f));
       }
     }
     atomicAnd((unsigned long long*)&Q[x >> 6], ~(1ull << (x & 63)));
@@ -1618,14 +1618,15 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
             const u64 ctag = (mtag << 8) | 3ull;
             __syncthreads();
             if (!(memo_j && memo_live && j > 0 && j != jsplit)) {
-              // complete (and tiny) child sets first, one child per lane;
-              // a frame that stores its prefixes in the memo keeps the order
-              const LeafSum ls = leaf_complete_children<W, FP>(s, Q, s.stP + j * W);
-              const u64 nlo = acc_lo + ls.lo;
-              acc_hi += nlo < acc_lo ? 1ull : 0ull;
+              // complete and nearly complete child sets first, one child per
+              // lane; a frame that stores its prefixes in the memo keeps the
+              // order
+              const ChildSum cs = complete_children<W, FP>(s, Q, s.stP + j * W, 3, true);
+              const u64 nlo = acc_lo + cs.lo;
+              acc_hi += cs.hi + (nlo < acc_lo ? 1ull : 0ull);
               acc_lo = nlo;
-              if (FP) acc_fp = addp(acc_fp, ls.fp);
-              wops += ls.wops;
+              if (FP) acc_fp = addp(acc_fp, cs.fp);
+              wops += cs.wops;
             }
             while (true) {
               int x = -1;
@@ -1712,7 +1713,7 @@ __global__ __launch_bounds__(64, (W <= 6 ? 2 : 1)) void k_search(Params p) {
           }
         }
         if (l - 1 <= kLaneEsymMaxL && !(memo_j && memo_live && j > 0 && j != jsplit)) {
-          // complete child sets first, one child per lane (as for l = 4)
+          // complete and nearly complete child sets first, one per lane
           const ChildSum cs = complete_children<W, FP>(s, Q, s.stP + j * W, l - 1, !(j + 1 == jsplit && sub != 0));
           const u64 nlo = acc_lo + cs.lo;
           acc_hi += cs.hi + (nlo < acc_lo ? 1ull : 0ull);

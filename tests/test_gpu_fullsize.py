@@ -183,7 +183,7 @@ def test_dense_core_rmat_orientation_and_budget(D, rmat):
         assert e.value.status == D.E_CANCELLED
 
 
-def test_dense_core_rmat_k6_counted(D, oracle_mod, rmat):
+def test_dense_core_rmat_k6_counted(D, oracle_mod, rmat, capsys):
     """k = 6 on the dense-core graph in degree order, which the heavy roots'
     arcs as EdgeParallel units bring within about two minutes: the total and
     fingerprint equal the sum of the per-root results; roots the enumerating
@@ -191,13 +191,19 @@ def test_dense_core_rmat_k6_counted(D, oracle_mod, rmat):
     oracle's pivot-based counter) equal the oracle's one by one.  The ~9,000
     roots of d+ >= 512 (the dense core) are beyond the CPU oracle: parity
     unpinned there."""
+    def step(msg):
+        # each finished step is reported as it ends (the test runs minutes)
+        with capsys.disabled():
+            print("  [dense core k=6] " + msg, flush=True)
+
     g = rmat
     k = 6
     G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
     per = np.zeros(3 * g.n, np.uint64)
-    print("dense core k=6 with per-root output", flush=True)
+    step("oriented; counting with per-root output (about two minutes)")
     total, tfp, rc = D.count(G, k, cfg=D.config(deadline_ms=300000), per_root=per)
     assert rc == D.OK
+    step("counted: %d" % total)
     lo = per[0::3].astype(object)
     hi = per[1::3].astype(object)
     assert int(sum(lo)) + (int(sum(hi)) << 64) == total
@@ -215,10 +221,10 @@ def test_dense_core_rmat_k6_counted(D, oracle_mod, rmat):
             assert int(per[3 * v + 2]) == wf, int(v)
 
     roots = _sample_roots(outd, k, 2e6, 2000, 0, 300 + k)
-    print("  %d enumerable roots" % len(roots), flush=True)
     check(roots, oracle_mod.count_roots(g.row_ptr, g.col, k, roots))
+    step("%d enumerable roots equal the oracle's" % len(roots))
     rng = np.random.default_rng(400 + k)
     mid = np.concatenate([rng.choice(np.flatnonzero((outd >= a) & (outd < b)), 12, replace=False)
                           for a, b in ((64, 128), (128, 256), (256, 512))]).astype(np.int32)
-    print("  %d mid-size roots by pivoting" % len(mid), flush=True)
     check(mid, oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, mid))
+    step("%d mid-size roots equal the oracle's pivot-based counts" % len(mid))

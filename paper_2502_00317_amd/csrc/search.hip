@@ -916,17 +916,22 @@ __device__ __forceinline__ bool binom_or_zero(int n, int r, u64& lo, u64& hi) {
   return binom128(n, r, lo, hi);
 }
 
-// e_r of (prod over c of (1 + g t)) / prod over the removed vertices of
-// (1 + g(v) t), the quotient taken in place on a copy of the coefficients.
-__device__ __forceinline__ u64 quotient_coef(const u64 (&e)[kLaneEsymMaxL + 1], const u64* gv, int nv, int L,
-                                             int r) {
+// e_r of (prod over c of (1 + g t)) / prod over the nv removed vertices
+// (weights v0..v3) of (1 + g(v) t), the quotient taken on a copy of the
+// coefficients.  Values, not arrays, so that everything stays in registers.
+__device__ __forceinline__ u64 quotient_coef(const u64 (&e)[kLaneEsymMaxL + 1], u64 v0, u64 v1, u64 v2, u64 v3,
+                                             int nv, int L, int r) {
   u64 q[kLaneEsymMaxL + 1];
 #pragma unroll
   for (int t = 0; t <= kLaneEsymMaxL; ++t) q[t] = e[t];
-  for (int i = 0; i < nv; ++i) {
 #pragma unroll
-    for (int t = 1; t <= kLaneEsymMaxL; ++t)
-      if (t <= L) q[t] = subp(q[t], mulp(gv[i], q[t - 1]));
+  for (int i = 0; i < 4; ++i) {
+    if (i < nv) {
+      const u64 g = i == 0 ? v0 : i == 1 ? v1 : i == 2 ? v2 : v3;
+#pragma unroll
+      for (int t = 1; t <= kLaneEsymMaxL; ++t)
+        if (t <= L) q[t] = subp(q[t], mulp(g, q[t - 1]));
+    }
   }
   u64 out = 0;
 #pragma unroll
@@ -1044,23 +1049,16 @@ __device__ __noinline__ ChildSum complete_children(const Lds& s, u64* Q, const u
 #pragma unroll
         for (int t = 1; t <= kLaneEsymMaxL; ++t)
           if (t == L) f = e[t];
-        if (miss >= 1) {
-          const u64 g2[2] = {gl[a0], gl[b0]};
-          f = subp(f, mulp(mulp(g2[0], g2[1]), quotient_coef(e, g2, 2, L, L - 2)));
-        }
+        const u64 ga0 = gl[a0], gb0 = gl[b0];
+        if (miss >= 1) f = subp(f, mulp(mulp(ga0, gb0), quotient_coef(e, ga0, gb0, 0, 0, 2, L, L - 2)));
         if (miss == 2) {
-          const u64 g2[2] = {gl[a1], gl[b1]};
-          f = subp(f, mulp(mulp(g2[0], g2[1]), quotient_coef(e, g2, 2, L, L - 2)));
-          // both edges: their distinct endpoints
-          u64 gv[4];
-          int nv = 0;
-          gv[nv++] = gl[a0];
-          gv[nv++] = gl[b0];
-          if (a1 != a0 && a1 != b0) gv[nv++] = gl[a1];
-          if (b1 != a0 && b1 != b0) gv[nv++] = gl[b1];
-          u64 pv = 1;
-          for (int q = 0; q < nv; ++q) pv = mulp(pv, gv[q]);
-          f = addp(f, mulp(pv, L - nv >= 0 ? quotient_coef(e, gv, nv, L, L - nv) : 0ull));
+          const u64 ga1 = gl[a1], gb1 = gl[b1];
+          f = subp(f, mulp(mulp(ga1, gb1), quotient_coef(e, ga1, gb1, 0, 0, 2, L, L - 2)));
+          // both edges: their distinct endpoints (a shared one once)
+          const bool na = a1 != a0 && a1 != b0, nb = b1 != a0 && b1 != b0;
+          const u64 w2 = na ? ga1 : gb1, w3 = gb1;  // the new endpoints, in order
+          const u64 pv = mulp(mulp(ga0, gb0), mulp(na ? ga1 : 1ull, nb ? gb1 : 1ull));
+          f = addp(f, mulp(pv, L - nv2 >= 0 ? quotient_coef(e, ga0, gb0, w2, w3, nv2, L, L - nv2) : 0ull));
         }
         fp = addp(fp, mulp(gl[x], f));
       }

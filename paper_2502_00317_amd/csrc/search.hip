@@ -3641,9 +3641,10 @@ int plan_batch(BatchWs* P, const dist_graph* const* gs, const int* ks, const int
     prm.memo = cfg.memo;
     prm.fingerprint = cfg.fingerprint;
     prm.tau = cfg.trie_tau > 0 ? (u64)cfg.trie_tau : 0;
-    // a batch's units are light and many: a wave takes runs of them, which
-    // spares the cursor (4,096 graphs: 118 -> 107 ms)
-    prm.chunk = kShChunk;
+    // runs of units only for the shared trie: runs of 8 took the 4,096-graph
+    // batch from 118 to 107 ms, but they hold small serving batches back
+    // (p50 18 -> 63 ms), where a few waves would take all the units
+    prm.chunk = prm.tau ? kShChunk : 1;
     prm.cursor = P->d_cursor + (t * kClasses + b);
     prm.units = (uint32_t)units64[t][b];
     prm.chunk_work = cw;

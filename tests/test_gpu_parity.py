@@ -334,3 +334,41 @@ def test_shared_trie_crosses_roots(D, oracle_mod):
     srcs = [g, g2, g, g2, g2]
     res, rc, _ = D.count_batch(graphs, ks, cfg=D.config(memo=2, trie_tau=1 << 20))
     assert res == [oracle_mod.count(x.row_ptr, x.col, k) for x, k in zip(srcs, ks)]
+
+
+@pytest.mark.parametrize("missing", [
+    [(0, 1)],                      # one edge
+    [(0, 1), (2, 3)],              # two disjoint edges (4 endpoints)
+    [(0, 1), (0, 2)],              # two edges sharing a vertex (3 endpoints)
+    [(3, 7), (7, 11)],             # the same, sharing the middle vertex
+    [(0, 1), (1, 2), (2, 3)],      # a path of three: past the per-lane limit
+    [(4, 5), (5, 6), (4, 6)],      # a triangle of three
+])
+def test_children_missing_few_edges(D, oracle_mod, missing):
+    """K_n minus a few edges in set patterns: child sets missing one or two
+    edges are counted one per lane by inclusion-exclusion (two edges may
+    share an endpoint), three go through frames; per-root results equal the
+    oracle's under sub-units (a root frame's shared children count in
+    sub-unit 0 only), EdgeParallel units, and memo modes that keep the
+    frame order."""
+    n = 34
+    iu, ju = np.triu_indices(n, 1)
+    drop = {tuple(sorted(e)) for e in missing}
+    keep = np.array([(int(a), int(b)) not in drop for a, b in zip(iu, ju)])
+    g = gg.csr_from_edges(n, iu[keep], ju[keep], name="K%d-%s" % (n, missing))
+    G = D.orient(g.row_ptr, g.col, order=D.ORDER_DEGREE)
+    P61 = (1 << 61) - 1
+    for k in (3, 4, 5, 6, 7, 9):
+        want = oracle_mod.pivot_count_roots(g.row_ptr, g.col, k, np.arange(n, dtype=np.int32))
+        for cfg in (dict(memo=1), dict(memo=0, sub_units=3), dict(memo=2, sub_units=7),
+                    dict(memo=0, edge_units=1), dict(memo=1, edge_units=1, sub_units=2)):
+            for fp in (1, 0):
+                per = np.zeros(3 * n, np.uint64)
+                c, f, rc = D.count(G, k, cfg=D.config(fingerprint=fp, **cfg), per_root=per)
+                assert rc == D.OK
+                got = [int(per[3 * v]) | (int(per[3 * v + 1]) << 64) for v in range(n)]
+                assert got == [w for w, _ in want], (missing, k, cfg, fp)
+                assert c == sum(w for w, _ in want)
+                if fp:
+                    assert [int(per[3 * v + 2]) for v in range(n)] == [x for _, x in want], (missing, k, cfg)
+                    assert f == sum(x for _, x in want) % P61

@@ -2577,6 +2577,11 @@ int run_buckets(const dist_graph* g, Params base, int32_t nroots, const dist_con
   if (!fixed) DIST_CHECK(hipEventRecord(e0, s));
   for (size_t b = 0; b < nbk; ++b) {
     Params prm = base;
+    // light units (k <= 5) in a launch with many of them: a wave takes runs
+    // of 8, which spares the cursor (the n = 1e6 graph at k = 5: 58 -> 43 ms);
+    // deeper counts keep one unit at a time, since runs of heavy units
+    // lengthen the tail (k = 9: 0.74 -> 0.99 s), and so do small launches
+    if (!base.tau && base.k <= 5 && (uint64_t)units[b] >= 64ull * (uint64_t)grids[b]) prm.chunk = kShChunk;
     prm.root_deg = g->d_root_deg;
     prm.chunk_work = cw;
     prm.units = units[b];

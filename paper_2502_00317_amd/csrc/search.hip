@@ -2775,7 +2775,7 @@ int search_root_soft_embed(const dist_graph* g, int cap, int32_t* d_out, hipStre
   return run_buckets(g, prm, g->n, cfg, s, tot, &ms);
 }
 
-// ---- listing driver ------------------------------------------------------------
+// ---- listing: host side -----------------------------------------------------------
 namespace {
 
 u64 addp_host(u64 a, u64 b) {

@@ -261,6 +261,7 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
         }
         __syncthreads();
         int best = -1, bestc = -1;
+        u64 csum = 0;  // neighbours in P, summed over the members
         for (int base = 0; base < np; base += kWave) {
           const int i = base + lane;
           int c = -1, idx = -1;
@@ -269,6 +270,7 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
             c = 0;
 #pragma unroll
             for (int w = 0; w < W; ++w) c += __popcll(P[w] & s.A[idx * W + w]);
+            csum += (u64)c;
           }
           for (int off = 32; off > 0; off >>= 1) {
             const int oc = __shfl_xor(c, off), oi = __shfl_xor(idx, off);
@@ -283,6 +285,48 @@ __global__ __launch_bounds__(64, 1) void k_pivot(PivParams p) {
           }
         }
         __syncthreads();
+        if (wave_sum(csum) == (u64)np * (u64)(np - 1)) {
+          // a complete P: its tree is the chain of pivot children down to an
+          // empty set, i.e. one leaf whose pivots gain every member of P
+          // (the polynomial times (1 + g(v) t) for each)
+          if (shared && sub != 0) {
+            mode = FINISH;
+            continue;
+          }
+          ++n_leaves;
+          u64 e = (lane <= K) ? sld(f.E + lane) : 0ull;
+          if (fp) {
+            for (int i = 0; i < np; ++i) {
+              const u64 g = s.gl[s.mem[i]];
+              const u64 prev = __shfl_up(e, 1);
+              if (lane >= 1 && lane <= K) e = addp(e, mulp(prev, g));
+            }
+          }
+          const int qq = q + np;
+          const int need = lane - h;
+          const u64 e_need = __shfl(e, (need >= 0 && need <= K) ? need : 0);
+          if (lane >= h && lane <= K && need <= qq) {
+            u64 clo, chi;
+            binom_at(p.binom, qq, need, clo, chi);
+            const u64 nlo = acc_lo + clo;
+            acc_hi += chi + (nlo < acc_lo ? 1ull : 0ull);
+            acc_lo = nlo;
+            u64 f2 = 0;
+            if (fp) {
+              f2 = mulp(prod, e_need);
+              acc_fp = addp(acc_fp, f2);
+            }
+            if (lane == p.per_root_k) {
+              const u64 t = r_lo + clo;
+              r_hi += chi + (t < r_lo ? 1ull : 0ull);
+              r_lo = t;
+              r_fp = addp(r_fp, f2);
+            }
+          }
+          __syncthreads();
+          mode = FINISH;
+          continue;
+        }
         // R: members of P that are neither the pivot nor its neighbours
         if (lane < W) {
           u64 rw = P[lane] & ~s.A[best * W + lane];
